@@ -1,0 +1,336 @@
+"""CPU oracle for the EMST hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports it and shares no code with it.
+
+Contents
+--------
+* ``prim``          dense O(n^2) Prim under the key K (C, ``emst_oracle.c``)
+* ``kdboruvka``     Boruvka over a kd-tree, serial or OpenMP (C)
+* ``sqdist``        the float32 squared distance D for one pair (C)
+* ``kruskal_bruteforce``  all n(n-1)/2 keys sorted, then union-find (numpy)
+* ``nearest_other_bruteforce``  per-point nearest neighbour in another
+                    component under (D, j) (numpy), the per-point step of
+                    Section 3 ("Finding the shortest outgoing edge")
+* ``radix_tree`` / ``reduce_labels``  the binary radix tree over sorted keys
+                    and the bottom-up label propagation of Section 3,
+                    Optimization 1 (pure Python; small inputs)
+* invariant checkers: spanning tree, cycle property, round structure.
+
+The key K(u, v) = (bits(D(u, v)), min(u, v), max(u, v)) is the paper's
+tie-break (Section 2, Boruvka's algorithm) applied to the float32 squared
+distance; the tree minimising it is unique.  Pins for every function live in
+``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "emst_oracle.c")
+
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+          "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (contraction off, IEEE semantics)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        f32p = ctypes.POINTER(ctypes.c_float)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_sqdist.argtypes = [f32p, f32p, ctypes.c_int]
+        L.oracle_sqdist.restype = ctypes.c_float
+        L.oracle_prim.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i32p, f32p]
+        L.oracle_prim.restype = ctypes.c_int
+        L.oracle_kdboruvka.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i32p, f32p,
+                                       ctypes.c_int, i64p, i64p]
+        L.oracle_kdboruvka.restype = ctypes.c_int
+        L.oracle_canonicalize.argtypes = [ctypes.c_int64, i32p, f32p, f32p]
+        L.oracle_canonicalize.restype = ctypes.c_int
+        L.oracle_total_weight.argtypes = [ctypes.c_int64, f32p]
+        L.oracle_total_weight.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _points(points) -> np.ndarray:
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32))
+    if pts.ndim != 2:
+        raise ValueError("points must be [n, dim]")
+    return pts
+
+
+def sqdist(a, b) -> np.float32:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float32))
+    return np.float32(lib().oracle_sqdist(_p(a, ctypes.c_float), _p(b, ctypes.c_float), a.shape[0]))
+
+
+class MST:
+    """Canonical EMST: edges [m, 2] int32 (u < v), d2 [m] float32, w [m]
+    float32 = sqrtf(d2), sorted by K."""
+
+    def __init__(self, edges, d2, w, rounds=None, comps=None):
+        self.edges, self.d2, self.w = edges, d2, w
+        self.rounds, self.comps = rounds, comps
+
+    @property
+    def total_weight(self) -> float:
+        """FP64 left-to-right sum of w in canonical order."""
+        return float(lib().oracle_total_weight(self.w.shape[0], _p(self.w, ctypes.c_float)))
+
+
+def canonicalize(edges, d2) -> MST:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2)).copy()
+    d = np.ascontiguousarray(np.asarray(d2, dtype=np.float32).reshape(-1)).copy()
+    w = np.empty_like(d)
+    rc = lib().oracle_canonicalize(d.shape[0], _p(e, ctypes.c_int32), _p(d, ctypes.c_float),
+                                   _p(w, ctypes.c_float))
+    if rc != 0:
+        raise RuntimeError(f"oracle_canonicalize failed: {rc}")
+    return MST(e, d, w)
+
+
+def prim(points) -> MST:
+    pts = _points(points)
+    n, dim = pts.shape
+    m = max(n - 1, 0)
+    e = np.zeros((m, 2), np.int32)
+    d = np.zeros(m, np.float32)
+    rc = lib().oracle_prim(_p(pts, ctypes.c_float), n, dim, _p(e, ctypes.c_int32), _p(d, ctypes.c_float))
+    if rc != 0:
+        raise RuntimeError(f"oracle_prim failed: {rc}")
+    return canonicalize(e, d)
+
+
+def kdboruvka(points, threads: int = 1) -> MST:
+    pts = _points(points)
+    n, dim = pts.shape
+    m = max(n - 1, 0)
+    e = np.zeros((m, 2), np.int32)
+    d = np.zeros(m, np.float32)
+    rounds = np.zeros(1, np.int64)
+    comps = np.zeros(64, np.int64)
+    rc = lib().oracle_kdboruvka(_p(pts, ctypes.c_float), n, dim, _p(e, ctypes.c_int32),
+                                _p(d, ctypes.c_float), int(threads), _p(rounds, ctypes.c_int64),
+                                _p(comps, ctypes.c_int64))
+    if rc != 0:
+        raise RuntimeError(f"oracle_kdboruvka failed: {rc}")
+    out = canonicalize(e, d)
+    out.rounds = int(rounds[0])
+    out.comps = comps[:out.rounds].copy()
+    return out
+
+
+def emst(points, threads: int = 1) -> MST:
+    """The oracle's answer for any size: Prim for small n, kd-Boruvka above."""
+    pts = _points(points)
+    if pts.shape[0] <= 4000:
+        return prim(pts)
+    return kdboruvka(pts, threads=threads)
+
+
+# ----------------------------------------------------------------------------
+# numpy brute force (small n)
+
+
+def pair_d2_matrix(points) -> np.ndarray:
+    """All-pairs D as float32, evaluated coordinate by coordinate in the
+    fixed order with numpy float32 elementwise arithmetic (no fusion)."""
+    pts = _points(points)
+    a = pts[:, None, :]
+    b = pts[None, :, :]
+    dk = a[..., 0] - b[..., 0]
+    s = dk * dk
+    for k in range(1, pts.shape[1]):
+        dk = a[..., k] - b[..., k]
+        s = s + dk * dk
+    return s.astype(np.float32)
+
+
+def kruskal_bruteforce(points) -> MST:
+    """Kruskal (Section 2): sort all pairs by K, add every pair that joins
+    two different components (union-find)."""
+    pts = _points(points)
+    n = pts.shape[0]
+    if n < 2:
+        return canonicalize(np.zeros((0, 2), np.int32), np.zeros(0, np.float32))
+    D = pair_d2_matrix(pts)
+    iu, ju = np.triu_indices(n, k=1)
+    w = D[iu, ju].view(np.uint32)
+    order = np.lexsort((ju, iu, w))  # primary w, then min (=iu), then max (=ju)
+    par = list(range(n))
+
+    def find(x):
+        while par[x] != x:
+            par[x] = par[par[x]]
+            x = par[x]
+        return x
+
+    out_e, out_d = [], []
+    for k in order:
+        a, b = int(iu[k]), int(ju[k])
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            par[max(ra, rb)] = min(ra, rb)
+            out_e.append((a, b))
+            out_d.append(D[a, b])
+            if len(out_e) == n - 1:
+                break
+    return canonicalize(np.array(out_e, np.int32).reshape(-1, 2), np.array(out_d, np.float32))
+
+
+def nearest_other_bruteforce(points, labels):
+    """Per point i: the j with labels[j] != labels[i] minimising (D, j);
+    returns (d2 float32 [n] with +inf for none, j int64 [n] with -1)."""
+    pts = _points(points)
+    lab = np.asarray(labels).reshape(-1)
+    D = pair_d2_matrix(pts).view(np.uint32).astype(np.int64)
+    n = pts.shape[0]
+    same = lab[:, None] == lab[None, :]
+    D[same] = np.int64(1) << 40
+    key = D * (n + 1) + np.arange(n)[None, :]
+    j = key.argmin(axis=1)
+    kmin = key[np.arange(n), j]
+    none = (kmin >> 0) >= (np.int64(1) << 40) * (n + 1)
+    d2 = pair_d2_matrix(pts)[np.arange(n), j]
+    d2 = np.where(none, np.float32(np.inf), d2).astype(np.float32)
+    j = np.where(none, -1, j)
+    return d2, j
+
+
+# ----------------------------------------------------------------------------
+# invariants
+
+
+def check_spanning_tree(n: int, edges) -> None:
+    e = np.asarray(edges).reshape(-1, 2)
+    assert e.shape[0] == max(n - 1, 0), f"expected {max(n - 1, 0)} edges, got {e.shape[0]}"
+    if n < 2:
+        return
+    assert (e[:, 0] < e[:, 1]).all(), "edges must satisfy u < v"
+    assert (e[:, 0] >= 0).all() and (e[:, 1] < n).all(), "index out of range"
+    par = np.arange(n)
+
+    def find(x):
+        while par[x] != x:
+            par[x] = par[par[x]]
+            x = par[x]
+        return x
+
+    for a, b in e.tolist():
+        ra, rb = find(a), find(b)
+        assert ra != rb, f"edge ({a},{b}) closes a cycle"
+        par[max(ra, rb)] = min(ra, rb)
+
+
+def check_cycle_property(points, mst: MST) -> None:
+    """Every non-tree pair's key exceeds the largest key on its tree path
+    (the cycle property that characterises the unique MST under K)."""
+    pts = _points(points)
+    n = pts.shape[0]
+    if n < 3:
+        return
+    D = pair_d2_matrix(pts).view(np.uint32).astype(np.int64)
+    adj = [[] for _ in range(n)]
+    for (u, v), d in zip(mst.edges.tolist(), mst.d2.view(np.uint32).tolist()):
+        adj[u].append((v, d))
+        adj[v].append((u, d))
+    B = np.int64(n + 1)
+    for s in range(n):
+        # max key on the path from s to every vertex (BFS over the tree)
+        mx = np.full(n, -1, np.int64)
+        mx[s] = -2
+        stack = [s]
+        while stack:
+            x = stack.pop()
+            for y, d in adj[x]:
+                if mx[y] == -1:
+                    k = (int(d) * B + min(x, y)) * B + max(x, y)
+                    mx[y] = max(int(mx[x]), k)
+                    stack.append(y)
+        ys = np.arange(s + 1, n)
+        keys = (D[s, ys] * B + s) * B + ys
+        assert (keys >= mx[ys]).all(), f"cycle property violated from vertex {s}"
+
+
+# ----------------------------------------------------------------------------
+# binary radix tree and label propagation (small inputs, pure Python)
+
+INVALID = -1
+
+
+def radix_tree(codes, code_bits: int = 64):
+    """Binary radix tree over sorted codes with equal codes separated by
+    their sorted index.  Every internal node is a leaf range [lo, hi] split
+    where the first bit (from the most significant one) of the augmented key
+    (code, index) changes.  Returns {(lo, hi): ((llo, lhi), (rlo, rhi))}."""
+    codes = [int(c) for c in codes]
+    n = len(codes)
+    assert all(codes[i] <= codes[i + 1] for i in range(n - 1)), "codes must be sorted"
+    ibits = max(1, (n - 1).bit_length())
+    keys = [(c << ibits) | i for i, c in enumerate(codes)]
+    tree = {}
+
+    def build(lo, hi):
+        if lo == hi:
+            return
+        x = keys[lo] ^ keys[hi]
+        top = x.bit_length() - 1
+        split = lo
+        while split < hi and not ((keys[split + 1] >> top) & 1):
+            split += 1
+        tree[(lo, hi)] = ((lo, split), (split + 1, hi))
+        build(lo, split)
+        build(split + 1, hi)
+
+    if n >= 2:
+        build(0, n - 1)
+    return tree
+
+
+def reduce_labels(tree, leaf_labels):
+    """Internal label = the children's common label, else INVALID
+    (Section 3, Optimization 1).  Returns {(lo, hi): label}."""
+    out = {}
+
+    def lab(node):
+        lo, hi = node
+        if lo == hi:
+            return int(leaf_labels[lo])
+        if node in out:
+            return out[node]
+        l, r = tree[node]
+        a, b = lab(l), lab(r)
+        out[node] = a if (a == b and a != INVALID) else INVALID
+        return out[node]
+
+    for node in tree:
+        lab(node)
+    return out
