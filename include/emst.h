@@ -1,0 +1,141 @@
+/*
+ * emst.h -- single-tree Boruvka Euclidean minimum spanning tree on one
+ * MI355X (gfx950), C ABI.
+ *
+ * The problem (Section 2, "EMST computation"): given n points in d
+ * dimensions, return the minimum spanning tree of their complete distance
+ * graph.  Equal weights are ordered by the vertex indices (Section 2, the
+ * tie-breaking rule in "Boruvka's algorithm"), applied here to the float32
+ * squared distance:
+ *
+ *     K(u, v) = ( bits(D(u, v)), min(u, v), max(u, v) )
+ *
+ * where D(a, b) = ((a0-b0)^2 + (a1-b1)^2) [+ (a2-b2)^2], each step rounded
+ * to float32 (round to nearest even), evaluated left to right with no fused
+ * multiply-add and with denormals kept.  K is a strict total order, so the
+ * tree is unique, and it is the tree every entry point below returns.
+ *
+ * Method (Section 3, Figure 3): a linear BVH over the points (Morton codes,
+ * radix sort, binary radix hierarchy, bottom-up bounding boxes), then
+ * Boruvka rounds, each of which (1) propagates component labels to the
+ * internal nodes (Optimization 1), (2) bounds every component's shortest
+ * outgoing edge from Morton-adjacent pairs (Optimization 2), (3) runs one
+ * nearest-other-component traversal per point (Algorithm 2) and keeps each
+ * component's minimum edge, and (4) merges the components along the chains
+ * of chosen edges ("Merging components together").
+ *
+ * Conventions for every entry point:
+ *  - Every pointer named d_* is DEVICE memory on the context's HIP device;
+ *    every pointer named h_* is HOST memory.  The caller owns all of them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All device work is ordered on it.
+ *  - The library allocates no device memory in these calls: scratch space is
+ *    the caller's workspace of at least emst_workspace_bytes(n, dim) bytes,
+ *    256-byte aligned.
+ *  - Functions return EMST_OK (0) or a negative EMST_E* code; the context
+ *    keeps a message for the last error (emst_last_error).  No C++ exception
+ *    crosses this interface.
+ *  - A context is not thread-safe: one host thread at a time.
+ */
+#ifndef EMST_H
+#define EMST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMST_OK 0
+#define EMST_EINVAL (-1)      /* bad argument: null pointer, n < 0, dim not 2 or 3, n > 2^31-1 */
+#define EMST_ENONFINITE (-2)  /* a coordinate is NaN or +-inf */
+#define EMST_ERANGE (-3)      /* the squared extent of the cloud overflows float32 */
+#define EMST_ENOMEM (-4)      /* workspace smaller than emst_workspace_bytes() */
+#define EMST_EHIP (-5)        /* a HIP runtime call failed; see emst_last_error */
+#define EMST_EBUSY (-6)       /* reserved */
+#define EMST_EINTERNAL (-7)   /* an internal consistency check failed */
+
+typedef struct emst_ctx emst_ctx;
+
+/* Create a context bound to HIP device `hip_device` (it becomes current on
+ * the calling thread).  *out receives the handle. */
+int emst_create(emst_ctx **out, int hip_device);
+
+/* Destroy a context (NULL is allowed).  Waits for nothing: the caller
+ * synchronises its streams first. */
+void emst_destroy(emst_ctx *ctx);
+
+/* Message of the last failing call on this context ("" if none). */
+const char *emst_last_error(const emst_ctx *ctx);
+
+/* Exact number of workspace bytes emst_build needs for n points of
+ * dimension dim (0 for invalid arguments).  Grows linearly in n, about
+ * 150 bytes per point in 3D. */
+size_t emst_workspace_bytes(int64_t n, int dim);
+
+/*
+ * emst_build -- EMST of one point cloud.
+ *
+ *  d_points   [n][dim] float32, row-major (point i at d_points[i*dim]).
+ *  n, dim     0 <= n <= 2^31-1, dim in {2, 3}.
+ *  d_edges    [n-1][2] int32 out: edge e joins d_edges[2e] < d_edges[2e+1],
+ *             original point indices; edges sorted by K ascending.
+ *  d_weights  [n-1] float32 out: sqrtf(D) of each edge, correctly rounded.
+ *  d_d2       [n-1] float32 out, or NULL: D of each edge.
+ *  d_workspace, ws_bytes   caller scratch, >= emst_workspace_bytes(n, dim).
+ *
+ * n = 0 or 1 writes nothing and returns EMST_OK.  Errors: EMST_EINVAL,
+ * EMST_ENONFINITE, EMST_ERANGE (then nothing is written to the outputs),
+ * EMST_ENOMEM, EMST_EHIP, EMST_EINTERNAL.  The call returns when the
+ * result is complete on `stream` (the round loop reads the component
+ * count back once per round, as in Figure 3).
+ */
+int emst_build(emst_ctx *ctx, const float *d_points, int64_t n, int dim,
+               int32_t *d_edges, float *d_weights, float *d_d2,
+               void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Per-call statistics of the last successful emst_build on this context.
+ * Timings are measured with HIP events on the call's stream when profiling
+ * is on (emst_set_profiling), else they are 0. */
+typedef struct emst_stats {
+    int64_t n;
+    int32_t dim;
+    int32_t rounds;                 /* Boruvka rounds */
+    int64_t components[64];         /* components at the start of each round */
+    int32_t tree_height;            /* edges on the longest root-leaf path */
+    int32_t traversal_launches;     /* = rounds */
+    double traversal_ms;            /* sum over rounds, traversal kernel only */
+    double traversal_ms_round[64];  /* per round */
+    double tree_ms;                 /* Morton codes .. bounding boxes */
+    double rounds_ms;               /* all rounds, every kernel */
+    double finalize_ms;             /* canonical edge sort and weights */
+    double total_ms;                /* whole call on the stream */
+    /* filled only when counting is on (emst_set_counting): child-box tests
+     * of internal nodes and of leaves (distance evaluations), summed over
+     * all points of all rounds, and per round */
+    int64_t child_tests;
+    int64_t leaf_tests;
+    int64_t child_tests_round[64];
+    int64_t leaf_tests_round[64];
+} emst_stats;
+
+/* Time every phase with HIP events (adds synchronisation; off by default). */
+int emst_set_profiling(emst_ctx *ctx, int on);
+
+/* Use the instrumented traversal that counts child-box tests and leaf
+ * distance evaluations (same result, slower; off by default). */
+int emst_set_counting(emst_ctx *ctx, int on);
+
+/* Traversal variant: 0 = one lane per query with a per-lane stack,
+ * 1 = wavefront-cooperative (the 64 Morton-ordered queries of a wave walk
+ * the tree together).  Results are identical; the default is the faster one. */
+int emst_set_traversal(emst_ctx *ctx, int variant);
+
+int emst_get_stats(const emst_ctx *ctx, emst_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMST_H */

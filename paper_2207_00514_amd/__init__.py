@@ -1,1 +1,236 @@
-"""MI355X-native single-tree Boruvka EMST (placeholder, filled in below)."""
+"""Single-tree Boruvka EMST on MI355X (gfx950).
+
+A thin ctypes binding over ``libemst.so`` (C ABI in ``include/emst.h``):
+argument marshalling only, every step of the EMST runs in the HIP kernels.
+PyTorch provides device memory and streams.
+
+    import torch, paper_2207_00514_amd as emst
+    pts = torch.rand(10_000, 3, device="cuda")
+    edges, weights, d2 = emst.build(pts)
+
+The library is required: if ``libemst.so`` is missing or fails to load,
+every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import workloads  # noqa: F401  (seeded input generators)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libemst.so")
+
+EMST_OK = 0
+ERRORS = {
+    -1: "EMST_EINVAL", -2: "EMST_ENONFINITE", -3: "EMST_ERANGE", -4: "EMST_ENOMEM",
+    -5: "EMST_EHIP", -6: "EMST_EBUSY", -7: "EMST_EINTERNAL",
+}
+
+EXPORTS = [
+    "emst_create", "emst_destroy", "emst_last_error", "emst_workspace_bytes", "emst_build",
+    "emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_get_stats",
+    "emst_test_tree_from_codes", "emst_test_radix_sort",
+]
+
+
+class EmstError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("rounds", ctypes.c_int32),
+        ("components", ctypes.c_int64 * 64), ("tree_height", ctypes.c_int32),
+        ("traversal_launches", ctypes.c_int32), ("traversal_ms", ctypes.c_double),
+        ("traversal_ms_round", ctypes.c_double * 64), ("tree_ms", ctypes.c_double),
+        ("rounds_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double), ("child_tests", ctypes.c_int64),
+        ("leaf_tests", ctypes.c_int64), ("child_tests_round", ctypes.c_int64 * 64),
+        ("leaf_tests_round", ctypes.c_int64 * 64),
+    ]
+
+    def as_dict(self) -> dict:
+        r = self.rounds
+        return dict(
+            n=self.n, dim=self.dim, rounds=r, components=list(self.components[:r]),
+            tree_height=self.tree_height, traversal_ms=self.traversal_ms,
+            traversal_ms_round=list(self.traversal_ms_round[:r]), tree_ms=self.tree_ms,
+            rounds_ms=self.rounds_ms, finalize_ms=self.finalize_ms, total_ms=self.total_ms,
+            child_tests=self.child_tests, leaf_tests=self.leaf_tests,
+        )
+
+
+_lib = None
+
+
+def lib():
+    """Load libemst.so (raises if it is missing: no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python -m paper_2207_00514_amd._build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+        L.emst_create.argtypes = [ctypes.POINTER(vp), i32]
+        L.emst_create.restype = i32
+        L.emst_destroy.argtypes = [vp]
+        L.emst_destroy.restype = None
+        L.emst_last_error.argtypes = [vp]
+        L.emst_last_error.restype = ctypes.c_char_p
+        L.emst_workspace_bytes.argtypes = [i64, i32]
+        L.emst_workspace_bytes.restype = sz
+        L.emst_build.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]
+        L.emst_build.restype = i32
+        for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal"):
+            getattr(L, f).argtypes = [vp, i32]
+            getattr(L, f).restype = i32
+        L.emst_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.emst_get_stats.restype = i32
+        L.emst_test_tree_from_codes.argtypes = [vp, vp, i64, vp, vp, vp, vp,
+                                                ctypes.POINTER(ctypes.c_int32), vp, sz, vp]
+        L.emst_test_tree_from_codes.restype = i32
+        L.emst_test_radix_sort.argtypes = [vp, vp, vp, i64, vp, sz, vp]
+        L.emst_test_radix_sort.restype = i32
+        _lib = L
+    return _lib
+
+
+def workspace_bytes(n: int, dim: int) -> int:
+    return int(lib().emst_workspace_bytes(int(n), int(dim)))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One emst_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = int(device)
+        torch.cuda.init()
+        h = ctypes.c_void_p()
+        rc = lib().emst_create(ctypes.byref(h), self.device)
+        if rc != EMST_OK:
+            raise EmstError(rc, "emst_create failed")
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().emst_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != EMST_OK:
+            raise EmstError(rc, lib().emst_last_error(self._h).decode())
+
+    def set_profiling(self, on: bool = True):
+        self._check(lib().emst_set_profiling(self._h, int(bool(on))))
+
+    def set_counting(self, on: bool = True):
+        self._check(lib().emst_set_counting(self._h, int(bool(on))))
+
+    def set_traversal(self, variant: int):
+        self._check(lib().emst_set_traversal(self._h, int(variant)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(lib().emst_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def workspace(self, n: int, dim: int):
+        """A cached device workspace of at least emst_workspace_bytes(n, dim)."""
+        import torch
+        need = workspace_bytes(n, dim) + 256
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def _ws_ptr(self, n: int, dim: int):
+        ws = self.workspace(n, dim)
+        return ctypes.c_void_p((ws.data_ptr() + 255) & ~255), ctypes.c_size_t(workspace_bytes(n, dim))
+
+    def test_tree_from_codes(self, codes, leaf_labels, stream=None):
+        """Hierarchy + one label propagation on sorted uint64 codes (int64
+        tensor, bit pattern) and int32 leaf labels; returns (left, right,
+        label, root) -- see include/emst_test.h."""
+        import torch
+        n = codes.shape[0]
+        left = torch.empty(n - 1, dtype=torch.int32, device=codes.device)
+        right = torch.empty_like(left)
+        label = torch.empty_like(left)
+        root = ctypes.c_int32()
+        ws, wsb = self._ws_ptr(n, 3)
+        self._check(lib().emst_test_tree_from_codes(
+            self._h, ctypes.c_void_p(codes.data_ptr()), int(n), ctypes.c_void_p(leaf_labels.data_ptr()),
+            ctypes.c_void_p(left.data_ptr()), ctypes.c_void_p(right.data_ptr()),
+            ctypes.c_void_p(label.data_ptr()), ctypes.byref(root), ws, wsb, _stream_handle(stream)))
+        return left, right, label, root.value
+
+    def test_radix_sort(self, keys, vals, stream=None):
+        """Sort (keys int64 bit patterns as uint64, vals int32) in place."""
+        n = keys.shape[0]
+        ws, wsb = self._ws_ptr(max(n, 2), 3)
+        self._check(lib().emst_test_radix_sort(
+            self._h, ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), int(n),
+            ws, wsb, _stream_handle(stream)))
+
+    def build(self, points, out=None, want_d2: bool = True, stream=None):
+        """EMST of points [n, dim] (float32, on this context's device).
+        Returns (edges int32 [n-1, 2], weights float32 [n-1], d2 float32 [n-1]
+        or None), sorted by (D, min index, max index)."""
+        import torch
+        if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
+            raise TypeError("points must be a CUDA (HIP) torch tensor")
+        if points.dtype != torch.float32 or points.dim() != 2:
+            raise TypeError("points must be float32 [n, dim]")
+        points = points.contiguous()
+        n, dim = points.shape
+        m = max(n - 1, 0)
+        if out is None:
+            edges = torch.empty((m, 2), dtype=torch.int32, device=points.device)
+            weights = torch.empty(m, dtype=torch.float32, device=points.device)
+            d2 = torch.empty(m, dtype=torch.float32, device=points.device) if want_d2 else None
+        else:
+            edges, weights, d2 = out
+        ws_bytes = workspace_bytes(n, dim) if dim in (2, 3) else 0
+        ws = self.workspace(n, dim if dim in (2, 3) else 3)
+        base = ws.data_ptr()
+        aligned = (base + 255) & ~255
+        rc = lib().emst_build(self._h, ctypes.c_void_p(points.data_ptr()), int(n), int(dim),
+                              ctypes.c_void_p(edges.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
+                              ctypes.c_void_p(d2.data_ptr() if d2 is not None else 0),
+                              ctypes.c_void_p(aligned), ctypes.c_size_t(ws_bytes),
+                              _stream_handle(stream))
+        self._check(rc)
+        return edges, weights, d2
+
+
+_default = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def build(points, **kw):
+    """EMST of a device tensor with the default context of its device."""
+    return context(points.device.index or 0).build(points, **kw)

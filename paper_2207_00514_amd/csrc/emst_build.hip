@@ -1,0 +1,865 @@
+// Single-tree Boruvka EMST on one gfx950 GPU: kernels and the C ABI.
+//
+// Pipeline of emst_build (Section 3, Figure 3):
+//   tree      bbox + validation -> Morton codes -> radix sort ->
+//             gather into Morton order -> bottom-up hierarchy + boxes
+//   round     label propagation -> component bounds -> traversal (+ stage-A
+//             component minimum) -> stage-B resolve -> merge (successor,
+//             roots + edge emission, pointer jumping, relabel)
+//   finalize  canonical edge order by (D bits, u, v), weights = sqrtf(D)
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/emst.h"
+#include "../../include/emst_test.h"
+#include "emst_kernels.h"
+#include "radix_sort.h"
+#include "traverse.h"
+
+namespace emst {
+
+// ===========================================================================
+// tree construction
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts, int64_t n, Ctrl* ctrl) {
+    float lo[DIM], hi[DIM];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const float x = pts[i * DIM + k];
+            bad |= !isfinite(x);
+            lo[k] = fminf(lo[k], x);
+            hi[k] = fmaxf(hi[k], x);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+        }
+    const bool any_bad = __ballot(bad) != 0ull;
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            if (lo[k] <= hi[k]) {
+                atomicMin(&ctrl->bb_min[k], ord_enc(lo[k]));
+                atomicMax(&ctrl->bb_max[k], ord_enc(hi[k]));
+            }
+        }
+        if (any_bad) atomicOr(&ctrl->nonfinite, 1u);
+    }
+}
+
+__global__ void k_init_ctrl(Ctrl* ctrl) {
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) { ctrl->bb_min[k] = 0xFFFFFFFFu; ctrl->bb_max[k] = 0u; }
+        ctrl->nonfinite = 0; ctrl->root = kNone; ctrl->height = 0;
+        ctrl->ncomp_next = 0; ctrl->edge_count = 0; ctrl->error = 0;
+        ctrl->key_or = 0ull; ctrl->key_and = ~0ull;
+        ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0;
+    }
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+    x &= 0x1FFFFFull;
+    x = (x | x << 32) & 0x1F00000000FFFFull;
+    x = (x | x << 16) & 0x1F0000FF0000FFull;
+    x = (x | x << 8) & 0x100F00F00F00F00Full;
+    x = (x | x << 4) & 0x10C30C30C30C30C3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+__device__ __forceinline__ uint64_t spread2(uint64_t x) {
+    x &= 0xFFFFFFFFull;
+    x = (x | x << 16) & 0x0000FFFF0000FFFFull;
+    x = (x | x << 8) & 0x00FF00FF00FF00FFull;
+    x = (x | x << 4) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | x << 2) & 0x3333333333333333ull;
+    x = (x | x << 1) & 0x5555555555555555ull;
+    return x;
+}
+
+struct MortonParams {
+    double lo[3];
+    double scale[3];
+    double qmax;
+};
+
+// Z-curve code of every point: 21 bits per coordinate in 3D (63-bit code),
+// 32 bits per coordinate in 2D (64-bit code).  The quantisation only shapes
+// the tree; the EMST does not depend on it.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, int64_t n, MortonParams mp,
+                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                Ctrl* ctrl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t code = 0, kor = 0, kand = ~0ull;
+    if (i < n) {
+        uint64_t q[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double t = ((double)pts[i * DIM + k] - mp.lo[k]) * mp.scale[k];
+            t = fmin(fmax(t, 0.0), mp.qmax);
+            q[k] = (uint64_t)t;
+        }
+        if (DIM == 3) code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2 % DIM]);
+        else code = (spread2(q[0]) << 1) | spread2(q[1 % DIM]);
+        keys[i] = code;
+        vals[i] = (uint32_t)i;
+        kor = kand = code;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        kor |= __shfl_xor(kor, off);
+        kand &= __shfl_xor(kand, off);
+    }
+    if (lane_id() == 0) {
+        atomicOr((unsigned long long*)&ctrl->key_or, (unsigned long long)kor);
+        atomicAnd((unsigned long long*)&ctrl->key_and, (unsigned long long)kand);
+    }
+}
+
+// Gather the coordinates into Morton order and initialise the per-point and
+// per-component state: labels = own sorted position (Figure 3: every vertex
+// starts as its own component), bounds = +inf, component keys = max.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, const uint32_t* __restrict__ perm,
+                                                int64_t n, float* __restrict__ spts, uint32_t* __restrict__ orig,
+                                                uint32_t* __restrict__ pos, uint32_t* __restrict__ labels,
+                                                uint32_t* __restrict__ ub, uint64_t* __restrict__ compkey,
+                                                uint32_t* __restrict__ compmax, uint64_t* __restrict__ exch,
+                                                uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t o = perm[i];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) spts[i * DIM + k] = pts[(int64_t)o * DIM + k];
+    orig[i] = o;
+    pos[o] = (uint32_t)i;
+    labels[i] = (uint32_t)i;
+    ub[i] = kInfBits;
+    compkey[i] = kKeyMax;
+    compmax[i] = kNone;
+    if (i + 1 < n) {
+        exch[i] = ~0ull;
+        flags[i] = 0u;
+    }
+}
+
+// Highest differing bit between sorted augmented keys (code, index) k and
+// k+1: codes that differ rank above any index difference.
+__device__ __forceinline__ int split_bit(const uint64_t* __restrict__ codes, int64_t k) {
+    const uint64_t x = codes[k] ^ codes[k + 1];
+    if (x) return 32 + 63 - __clzll(x);
+    return 31 - __clz((uint32_t)k ^ (uint32_t)(k + 1));
+}
+
+// Bottom-up construction of the binary radix tree over the sorted codes
+// together with the bounding boxes (the agglomerative scheme of Apetrei 2014,
+// one of the two constructions the paper's BVH follows).  Internal node k
+// is the node that splits between leaves k and k+1.  A node spanning leaves
+// [l, r] becomes the left child of node r if its right neighbour pair
+// (r, r+1) shares a longer prefix than its left neighbour pair (l-1, l),
+// else the right child of node l-1.  The first of the two children to reach
+// a parent parks its range end and height there and stops; the second
+// combines both boxes and continues upwards.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ codes,
+                                               const uint32_t* __restrict__ orig, const float* __restrict__ spts,
+                                               int64_t n, Rec<DIM>* recs, uint32_t* __restrict__ leaf_parent,
+                                               uint32_t* __restrict__ node_parent, uint64_t* exch, Ctrl* ctrl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float lo[DIM], hi[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) lo[k] = hi[k] = spts[i * DIM + k];
+    int64_t l = i, r = i;
+    uint32_t h = 0;
+    uint32_t self = (uint32_t)i, self_ref = orig[i] | kLeafFlag;
+    bool leaf = true;
+    // every step climbs one level; a radix tree over 95-bit augmented keys
+    // has height <= 96
+    for (int step = 0;; ++step) {
+        if (step > 128) {
+            atomicOr(&ctrl->error, kErrStack);
+            return;
+        }
+        bool left_child;
+        if (l == 0) left_child = true;
+        else if (r == n - 1) left_child = false;
+        else left_child = split_bit(codes, r) < split_bit(codes, l - 1);
+        const uint32_t parent = (uint32_t)(left_child ? r : l - 1);
+        const int side = left_child ? 0 : 1;
+        store_child_box<DIM>(&recs[parent], side, lo, hi, self_ref);
+        const uint32_t link = (parent << 1) | (uint32_t)side;
+        if (leaf) leaf_parent[i] = link;
+        else node_parent[self] = link;
+        const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
+        const uint64_t other = atomic_xchg_acqrel(&exch[parent], mine);
+        if (other == ~0ull) return;
+        float slo[DIM], shi[DIM];
+        load_child_box<DIM>(&recs[parent], 1 - side, slo, shi);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) { lo[k] = fminf(lo[k], slo[k]); hi[k] = fmaxf(hi[k], shi[k]); }
+        const int64_t oend = (int64_t)(other >> 32);
+        if (left_child) r = oend;
+        else l = oend;
+        h = max(h, (uint32_t)(other & 0xFFFFFFFFu)) + 1u;
+        self = parent;
+        self_ref = parent;
+        leaf = false;
+        if (l == 0 && r == n - 1) {
+            ctrl->root = parent;
+            ctrl->height = h;
+            node_parent[parent] = kNone;
+            return;
+        }
+    }
+}
+
+// ===========================================================================
+// one Boruvka round
+
+// Optimization 1 (Section 3): every internal node gets its leaves' common
+// component label, or kInvalid.  One thread per leaf climbs the tree; the
+// first arrival at a node stops, the second combines the two child labels
+// and goes on.  Labels live in the parent's record next to each child's box.
+// The per-node arrival counter grows by 2 every round, so its parity tells
+// first from second arrival without a reset.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_reduce_labels(const uint32_t* __restrict__ labels,
+                                                       const uint32_t* __restrict__ leaf_parent,
+                                                       const uint32_t* __restrict__ node_parent, Rec<DIM>* recs,
+                                                       uint32_t* flags, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t lab = labels[i];
+    uint32_t link = leaf_parent[i];
+    for (int step = 0; step <= 128; ++step) {
+        const uint32_t node = link >> 1;
+        const int side = (int)(link & 1u);
+        *label_slot<DIM>(&recs[node], side) = lab;
+        const uint32_t old = atomic_add_acqrel(&flags[node], 1u);
+        if ((old & 1u) == 0u) return;
+        const uint32_t other = *label_slot<DIM>(&recs[node], 1 - side);
+        lab = (other == lab) ? lab : kInvalid;
+        link = node_parent[node];
+        if (link == kNone) return;
+    }
+}
+
+// Optimization 2 (Section 3): a Morton-adjacent pair with different labels
+// bounds the shortest outgoing edge of both components by its D.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, const uint32_t* __restrict__ labels,
+                                                int64_t n, uint32_t* ub, Ctrl* ctrl) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) ctrl->ncomp_next = 0u;
+    if (k + 1 >= n) return;
+    const uint32_t a = labels[k], b = labels[k + 1];
+    if (a == b) return;
+    float p[DIM], q[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { p[c] = spts[k * DIM + c]; q[c] = spts[(k + 1) * DIM + c]; }
+    const uint32_t d = fbits(sqdist<DIM>(p, q));
+    atomicMin(&ub[a], d);
+    atomicMin(&ub[b], d);
+}
+
+// Stage B of the component minimum: among the points whose candidate matches
+// the component's (D bits, min index) key, the smallest max index wins, so
+// the component edge is the minimum under (D, min, max).
+__global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ cand_d,
+                                                 const uint32_t* __restrict__ cand_j,
+                                                 const uint32_t* __restrict__ labels,
+                                                 const uint32_t* __restrict__ orig,
+                                                 const uint64_t* __restrict__ compkey, uint32_t* compmax,
+                                                 int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t cd = cand_d[i];
+    if (cd == kNone) return;
+    const uint32_t j = cand_j[i], oi = orig[i], c = labels[i];
+    const uint64_t key = ((uint64_t)cd << 32) | (uint64_t)min(oi, j);
+    if (key == compkey[c]) atomicMin(&compmax[c], max(oi, j));
+}
+
+// Merge, step 1: successor component of every component (the component at
+// the other end of its shortest outgoing edge).
+__global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__ labels,
+                                                    const uint32_t* __restrict__ pos,
+                                                    const uint64_t* __restrict__ compkey,
+                                                    const uint32_t* __restrict__ compmax, uint32_t* succ,
+                                                    Ctrl* ctrl, int64_t n) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || labels[c] != (uint32_t)c) return;
+    const uint64_t key = compkey[c];
+    const uint32_t v = compmax[c];
+    if (key == kKeyMax || v == kNone) {
+        atomicOr(&ctrl->error, kErrNoEdge);
+        succ[c] = (uint32_t)c;
+        return;
+    }
+    const uint32_t u = (uint32_t)(key & 0xFFFFFFFFu);
+    const uint32_t lu = labels[pos[u]], lv = labels[pos[v]];
+    if (lu != (uint32_t)c && lv != (uint32_t)c) atomicOr(&ctrl->error, kErrNoEdge);
+    succ[c] = (lu == (uint32_t)c) ? lv : lu;
+}
+
+// Merge, step 2: the chains of successors end in a mutual pair (Section 2);
+// the smaller label of that pair becomes the root of the merged component
+// ("Merging components together").  Every other component emits its edge,
+// so a mutual pair contributes its shared edge once.  Roots reset their
+// per-component state for the next round.
+__global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict__ labels,
+                                                      const uint32_t* __restrict__ succ, uint32_t* par,
+                                                      uint64_t* compkey, uint32_t* compmax, uint32_t* ub,
+                                                      uint32_t* __restrict__ eu, uint32_t* __restrict__ ev,
+                                                      uint32_t* __restrict__ ed, Ctrl* ctrl, int64_t n) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || labels[c] != (uint32_t)c) return;
+    const uint32_t s = succ[c];
+    const bool root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
+    par[c] = root ? (uint32_t)c : s;
+    if (root) {
+        atomicAdd(&ctrl->ncomp_next, 1u);
+        ub[c] = kInfBits;
+        compkey[c] = kKeyMax;
+        compmax[c] = kNone;
+    } else {
+        const uint32_t slot = atomicAdd(&ctrl->edge_count, 1u);
+        if (slot >= (uint32_t)(n - 1)) {
+            atomicOr(&ctrl->error, kErrNoEdge);
+            return;
+        }
+        const uint64_t key = compkey[c];
+        eu[slot] = (uint32_t)(key & 0xFFFFFFFFu);
+        ev[slot] = compmax[c];
+        ed[slot] = (uint32_t)(key >> 32);
+    }
+}
+
+// Merge, step 3: pointer jumping towards the roots.  Concurrent updates only
+// ever replace a pointer by one of its ancestors, so any interleaving is
+// safe; the loop is capped and the relabel step finishes any remaining hops.
+__global__ __launch_bounds__(256) void k_merge_jump(const uint32_t* __restrict__ labels, uint32_t* par,
+                                                    int64_t n, int steps) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || labels[c] != (uint32_t)c) return;
+    uint32_t p = load_relaxed(&par[c]);
+    for (int it = 0; it < steps; ++it) {
+        const uint32_t pp = load_relaxed(&par[p]);
+        if (pp == p) return;
+        __hip_atomic_store(&par[c], pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        p = pp;
+    }
+}
+
+// Merge, step 4: every point takes its component's root as its new label
+// (following any hops the jumping step left, up to a cap).
+__global__ __launch_bounds__(256) void k_relabel(uint32_t* labels, const uint32_t* __restrict__ par, int64_t n,
+                                                 int steps, Ctrl* ctrl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t r = par[labels[i]];
+    int it = 0;
+    for (; it < steps; ++it) {
+        const uint32_t rr = par[r];
+        if (rr == r) break;
+        r = rr;
+    }
+    if (it == steps) atomicOr(&ctrl->error, kErrJump);
+    labels[i] = r;
+}
+
+// ===========================================================================
+// finalize
+
+__global__ __launch_bounds__(256) void k_edge_keys(const uint32_t* __restrict__ eu, const uint32_t* __restrict__ ev,
+                                                   int64_t m, uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    keys[e] = ((uint64_t)eu[e] << 32) | (uint64_t)ev[e];
+    vals[e] = (uint32_t)e;
+}
+
+__global__ __launch_bounds__(256) void k_edge_dkeys(const uint32_t* __restrict__ ed,
+                                                    const uint32_t* __restrict__ perm, int64_t m,
+                                                    uint64_t* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    keys[i] = (uint64_t)ed[perm[i]];
+}
+
+__global__ __launch_bounds__(256) void k_edge_write(const uint32_t* __restrict__ eu,
+                                                    const uint32_t* __restrict__ ev,
+                                                    const uint32_t* __restrict__ ed,
+                                                    const uint32_t* __restrict__ perm, int64_t m,
+                                                    int32_t* __restrict__ edges, float* __restrict__ w,
+                                                    float* __restrict__ d2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t e = perm[i];
+    const float d = bitsf(ed[e]);
+    edges[2 * i] = (int32_t)eu[e];
+    edges[2 * i + 1] = (int32_t)ev[e];
+    w[i] = sqrtf(d);
+    if (d2) d2[i] = d;
+}
+
+// ===========================================================================
+// workspace layout
+
+struct Layout {
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, leaf_parent, node_parent, exch, flags, labels, ub,
+        compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Layout make_layout(int64_t n, int dim) {
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += align_up(bytes);
+        return r;
+    };
+    const size_t N = (size_t)(n > 0 ? n : 1), M = (size_t)(n > 1 ? n - 1 : 1);
+    L.ctrl = take(sizeof(Ctrl));
+    L.k0 = take(8 * N);
+    L.k1 = take(8 * N);
+    L.v0 = take(4 * N);
+    L.v1 = take(4 * N);
+    L.hist = take(4 * radix_hist_elems());
+    L.spts = take(4 * N * dim);
+    L.orig = take(4 * N);
+    L.pos = take(4 * N);
+    L.recs = take(M * (dim == 3 ? sizeof(Rec<3>) : sizeof(Rec<2>)));
+    L.leaf_parent = take(4 * N);
+    L.node_parent = take(4 * M);
+    L.exch = take(8 * M);
+    L.flags = take(4 * M);
+    L.labels = take(4 * N);
+    L.ub = take(4 * N);
+    L.compkey = take(8 * N);
+    L.compmax = take(4 * N);
+    L.succ = take(4 * N);
+    L.par = take(4 * N);
+    L.cand_d = take(4 * N);
+    L.cand_j = take(4 * N);
+    L.eu = take(4 * N);
+    L.ev = take(4 * N);
+    L.ed = take(4 * N);
+    L.total = o;
+    return L;
+}
+
+}  // namespace emst
+
+// ===========================================================================
+// C ABI
+
+using namespace emst;
+
+struct emst_ctx {
+    int device = 0;
+    std::string err;
+    bool profiling = false;
+    bool counting = false;
+    int traversal = 0;
+    emst_stats stats;
+    Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
+    hipEvent_t ev[2 * 64 + 8];
+    bool ev_ok = false;
+};
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess) {                                                          \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(_e);                \
+            return EMST_EHIP;                                                            \
+        }                                                                                \
+    } while (0)
+
+static int fail(emst_ctx* ctx, int code, const char* msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+static inline unsigned grid_for(int64_t n, int threads = 256) {
+    int64_t g = (n + threads - 1) / threads;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+extern "C" int emst_create(emst_ctx** out, int hip_device) {
+    if (!out) return EMST_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return EMST_EINVAL;
+    emst_ctx* ctx = new (std::nothrow) emst_ctx();
+    if (!ctx) return EMST_ENOMEM;
+    ctx->device = hip_device;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (hipSetDevice(hip_device) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl) + 256, hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return EMST_EHIP;
+    }
+    ctx->ev_ok = true;
+    for (auto& e : ctx->ev)
+        if (hipEventCreate(&e) != hipSuccess) ctx->ev_ok = false;
+    *out = ctx;
+    return EMST_OK;
+}
+
+extern "C" void emst_destroy(emst_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
+    delete ctx;
+}
+
+extern "C" const char* emst_last_error(const emst_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" size_t emst_workspace_bytes(int64_t n, int dim) {
+    if (n < 0 || n > 0x7FFFFFFFll || (dim != 2 && dim != 3)) return 0;
+    return make_layout(n, dim).total;
+}
+
+extern "C" int emst_set_profiling(emst_ctx* ctx, int on) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->profiling = on != 0;
+    return EMST_OK;
+}
+extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->counting = on != 0;
+    return EMST_OK;
+}
+extern "C" int emst_set_traversal(emst_ctx* ctx, int variant) {
+    if (!ctx || variant < 0 || variant > 1) return EMST_EINVAL;
+    ctx->traversal = variant;
+    return EMST_OK;
+}
+extern "C" int emst_get_stats(const emst_ctx* ctx, emst_stats* out) {
+    if (!ctx || !out) return EMST_EINVAL;
+    *out = ctx->stats;
+    return EMST_OK;
+}
+
+namespace {
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+template <int DIM>
+int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float* weights, float* d2, char* ws,
+               hipStream_t st) {
+    const Layout L = make_layout(n, DIM);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+    uint64_t* k0 = reinterpret_cast<uint64_t*>(ws + L.k0);
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(ws + L.k1);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(ws + L.v0);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(ws + L.v1);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+    float* spts = reinterpret_cast<float*>(ws + L.spts);
+    uint32_t* orig = reinterpret_cast<uint32_t*>(ws + L.orig);
+    uint32_t* pos = reinterpret_cast<uint32_t*>(ws + L.pos);
+    Rec<DIM>* recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
+    uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
+    uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
+    uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
+    uint32_t* flags = reinterpret_cast<uint32_t*>(ws + L.flags);
+    uint32_t* labels = reinterpret_cast<uint32_t*>(ws + L.labels);
+    uint32_t* ub = reinterpret_cast<uint32_t*>(ws + L.ub);
+    uint64_t* compkey = reinterpret_cast<uint64_t*>(ws + L.compkey);
+    uint32_t* compmax = reinterpret_cast<uint32_t*>(ws + L.compmax);
+    uint32_t* succ = reinterpret_cast<uint32_t*>(ws + L.succ);
+    uint32_t* par = reinterpret_cast<uint32_t*>(ws + L.par);
+    uint32_t* cand_d = reinterpret_cast<uint32_t*>(ws + L.cand_d);
+    uint32_t* cand_j = reinterpret_cast<uint32_t*>(ws + L.cand_j);
+    uint32_t* eu = reinterpret_cast<uint32_t*>(ws + L.eu);
+    uint32_t* ev = reinterpret_cast<uint32_t*>(ws + L.ev);
+    uint32_t* ed = reinterpret_cast<uint32_t*>(ws + L.ed);
+
+    emst_stats S;
+    memset(&S, 0, sizeof(S));
+    S.n = n;
+    S.dim = DIM;
+    const bool prof = ctx->profiling && ctx->ev_ok;
+    hipEvent_t* E = ctx->ev;  // E[0..7] phases, E[8 + 2r], E[9 + 2r] traversal of round r
+
+    if (prof) HIP_TRY(hipEventRecord(E[0], st));
+    // ---- validation + scene box
+    k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
+    k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 4096), 256, 0, st>>>(pts, n, ctrl);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->h_ctrl->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int k = 0; k < DIM; ++k) {
+        lo[k] = ord_dec(ctx->h_ctrl->bb_min[k]);
+        hi[k] = ord_dec(ctx->h_ctrl->bb_max[k]);
+    }
+    {
+        // every D is at most the squared extent, evaluated in the same order
+        volatile float s = 0.f;
+        for (int k = 0; k < DIM; ++k) {
+            volatile float g = hi[k] - lo[k];
+            volatile float g2 = g * g;
+            s = (k == 0) ? (float)g2 : (float)(s + g2);
+        }
+        if (!isfinite((float)s)) return fail(ctx, EMST_ERANGE, "squared extent of the cloud overflows float32");
+    }
+    // ---- Morton codes + sort
+    MortonParams mp;
+    const int bits = DIM == 3 ? 21 : 32;
+    mp.qmax = (double)((1ull << bits) - 1ull);
+    for (int k = 0; k < 3; ++k) {
+        mp.lo[k] = k < DIM ? (double)lo[k] : 0.0;
+        const double ext = k < DIM ? (double)hi[k] - (double)lo[k] : 0.0;
+        mp.scale[k] = ext > 0.0 ? mp.qmax / ext : 0.0;
+    }
+    k_morton<DIM><<<grid_for(n), 256, 0, st>>>(pts, n, mp, k0, v0, ctrl);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int shifts[8], ns = 0;
+    {
+        const uint64_t vary = ctx->h_ctrl->key_or ^ ctx->h_ctrl->key_and;
+        for (int s = 0; s < 64; s += 8)
+            if ((vary >> s) & 0xFFull) shifts[ns++] = s;
+    }
+    int in1 = 0;
+    HIP_TRY(radix_sort_pairs(st, k0, v0, k1, v1, hist, n, shifts, ns, &in1));
+    const uint64_t* codes = in1 ? k1 : k0;
+    const uint32_t* perm = in1 ? v1 : v0;
+    // ---- hierarchy + boxes
+    k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, spts, orig, pos, labels, ub, compkey, compmax, exch,
+                                               flags);
+    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, leaf_parent, node_parent, exch, ctrl);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const uint32_t root = ctx->h_ctrl->root;
+    S.tree_height = (int32_t)ctx->h_ctrl->height;
+    if (root == kNone || root >= (uint32_t)(n - 1) || ctx->h_ctrl->error)
+        return fail(ctx, EMST_EINTERNAL, "tree construction failed");
+    if (prof) HIP_TRY(hipEventRecord(E[1], st));
+
+    // ---- Boruvka rounds
+    TraverseArgs<DIM> ta;
+    ta.spts = spts; ta.labels = labels; ta.orig = orig; ta.ub = ub; ta.recs = recs; ta.root = root; ta.n = n;
+    ta.cand_d = cand_d; ta.cand_j = cand_j; ta.compkey = compkey; ta.ctrl = ctrl;
+    int64_t ncomp = n;
+    int round = 0;
+    while (ncomp > 1) {
+        if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
+        S.components[round] = ncomp;
+        k_reduce_labels<DIM><<<grid_for(n), 256, 0, st>>>(labels, leaf_parent, node_parent, recs, flags, n);
+        k_bounds<DIM><<<grid_for(n), 256, 0, st>>>(spts, labels, n, ub, ctrl);
+        if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
+        HIP_TRY(launch_traverse<DIM>(ta, S.tree_height, ctx->traversal, ctx->counting, st));
+        if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
+        k_resolve<<<grid_for(n), 256, 0, st>>>(cand_d, cand_j, labels, orig, compkey, compmax, n);
+        k_merge_succ<<<grid_for(n), 256, 0, st>>>(labels, pos, compkey, compmax, succ, ctrl, n);
+        k_merge_parent<<<grid_for(n), 256, 0, st>>>(labels, succ, par, compkey, compmax, ub, eu, ev, ed, ctrl, n);
+        HIP_TRY(hipGetLastError());
+        k_merge_jump<<<grid_for(n), 256, 0, st>>>(labels, par, n, 1024);
+        k_relabel<<<grid_for(n), 256, 0, st>>>(labels, par, n, 4096, ctrl);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (ctx->h_ctrl->error & kErrStack) return fail(ctx, EMST_EINTERNAL, "traversal stack overflow");
+        if (ctx->h_ctrl->error & kErrJump) return fail(ctx, EMST_EINTERNAL, "component merge did not converge");
+        if (ctx->h_ctrl->error) return fail(ctx, EMST_EINTERNAL, "a component found no outgoing edge");
+        const int64_t next = ctx->h_ctrl->ncomp_next;
+        if (next >= ncomp || next < 1) return fail(ctx, EMST_EINTERNAL, "round made no progress");
+        ncomp = next;
+        ++round;
+    }
+    S.rounds = round;
+    S.traversal_launches = round;
+    if (ctx->h_ctrl->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
+    if (ctx->counting) {
+        S.child_tests = (int64_t)ctx->h_ctrl->internal_tests;
+        S.leaf_tests = (int64_t)ctx->h_ctrl->leaf_tests;
+    }
+    if (prof) HIP_TRY(hipEventRecord(E[2], st));
+
+    // ---- canonical order: by (u, v) first, then stably by D bits
+    const int64_t m = n - 1;
+    k_edge_keys<<<grid_for(m), 256, 0, st>>>(eu, ev, m, k0, v0);
+    int sh[16], q = 0;
+    const int ib = 32 - __builtin_clz((unsigned)(n - 1));  // bits of the largest index
+    for (int s = 0; s < ib; s += 8) sh[q++] = s;
+    for (int s = 0; s < ib; s += 8) sh[q++] = 32 + s;
+    HIP_TRY(radix_sort_pairs(st, k0, v0, k1, v1, hist, m, sh, q, &in1));
+    uint32_t* p1 = in1 ? v1 : v0;
+    uint64_t* kd = in1 ? k1 : k0;
+    uint64_t* kd_alt = in1 ? k0 : k1;
+    uint32_t* p1_alt = in1 ? v0 : v1;
+    k_edge_dkeys<<<grid_for(m), 256, 0, st>>>(ed, p1, m, kd);
+    const int dsh[4] = {0, 8, 16, 24};
+    HIP_TRY(radix_sort_pairs(st, kd, p1, kd_alt, p1_alt, hist, m, dsh, 4, &in1));
+    const uint32_t* pfin = in1 ? p1_alt : p1;
+    k_edge_write<<<grid_for(m), 256, 0, st>>>(eu, ev, ed, pfin, m, edges, weights, d2);
+    HIP_TRY(hipGetLastError());
+    if (prof) HIP_TRY(hipEventRecord(E[3], st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (prof) {
+        S.tree_ms = elapsed(E[0], E[1]);
+        S.rounds_ms = elapsed(E[1], E[2]);
+        S.finalize_ms = elapsed(E[2], E[3]);
+        S.total_ms = elapsed(E[0], E[3]);
+        for (int r = 0; r < round; ++r) {
+            S.traversal_ms_round[r] = elapsed(E[8 + 2 * r], E[9 + 2 * r]);
+            S.traversal_ms += S.traversal_ms_round[r];
+        }
+    }
+    ctx->stats = S;
+    return EMST_OK;
+}
+
+}  // namespace
+
+extern "C" int emst_build(emst_ctx* ctx, const float* d_points, int64_t n, int dim, int32_t* d_edges,
+                          float* d_weights, float* d_d2, void* d_workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > 0x7FFFFFFFll) return fail(ctx, EMST_EINVAL, "n out of range");
+    if (dim != 2 && dim != 3) return fail(ctx, EMST_EINVAL, "dim must be 2 or 3");
+    if (n < 2) {
+        memset(&ctx->stats, 0, sizeof(ctx->stats));
+        ctx->stats.n = n;
+        ctx->stats.dim = dim;
+        return EMST_OK;
+    }
+    if (!d_points || !d_edges || !d_weights || !d_workspace) return fail(ctx, EMST_EINVAL, "null pointer");
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(ctx, EMST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < emst_workspace_bytes(n, dim)) return fail(ctx, EMST_ENOMEM, "workspace too small");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (dim == 3) return build_impl<3>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st);
+    return build_impl<2>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st);
+}
+
+// ===========================================================================
+// test entry points (include/emst_test.h)
+
+namespace emst {
+
+__global__ __launch_bounds__(256) void k_test_prep(const uint32_t* __restrict__ leaf_labels, int64_t n,
+                                                   float* __restrict__ spts, uint32_t* __restrict__ orig,
+                                                   uint32_t* __restrict__ labels, uint64_t* __restrict__ exch,
+                                                   uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    spts[3 * i] = spts[3 * i + 1] = spts[3 * i + 2] = 0.f;
+    orig[i] = (uint32_t)i;
+    labels[i] = leaf_labels[i];
+    if (i + 1 < n) {
+        exch[i] = ~0ull;
+        flags[i] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_test_extract(const Rec<3>* __restrict__ recs,
+                                                      const uint32_t* __restrict__ node_parent, int64_t m,
+                                                      int32_t* __restrict__ left, int32_t* __restrict__ right,
+                                                      uint32_t* __restrict__ label) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    Child<3> c0, c1;
+    unpack<3>(recs[k], c0, c1);
+    left[k] = (c0.ref & kLeafFlag) ? -(int32_t)(c0.ref & ~kLeafFlag) - 1 : (int32_t)c0.ref;
+    right[k] = (c1.ref & kLeafFlag) ? -(int32_t)(c1.ref & ~kLeafFlag) - 1 : (int32_t)c1.ref;
+    const uint32_t link = node_parent[k];
+    if (link == kNone) {
+        label[k] = (c0.lab == c1.lab) ? c0.lab : kInvalid;
+    } else {
+        Rec<3> pr = recs[link >> 1];
+        label[k] = *label_slot<3>(&pr, (int)(link & 1u));
+    }
+}
+
+}  // namespace emst
+
+extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes, int64_t n,
+                                         const uint32_t* d_leaf_labels, int32_t* d_left, int32_t* d_right,
+                                         uint32_t* d_label, int32_t* root_out, void* d_workspace, size_t ws_bytes,
+                                         void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 2 || n > 0x7FFFFFFFll || !d_codes || !d_leaf_labels || !d_left || !d_right || !d_label || !root_out ||
+        !d_workspace)
+        return fail(ctx, EMST_EINVAL, "bad argument");
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(ctx, EMST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < emst_workspace_bytes(n, 3)) return fail(ctx, EMST_ENOMEM, "workspace too small");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* ws = (char*)d_workspace;
+    const Layout L = make_layout(n, 3);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+    float* spts = reinterpret_cast<float*>(ws + L.spts);
+    uint32_t* orig = reinterpret_cast<uint32_t*>(ws + L.orig);
+    uint32_t* labels = reinterpret_cast<uint32_t*>(ws + L.labels);
+    uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
+    uint32_t* flags = reinterpret_cast<uint32_t*>(ws + L.flags);
+    Rec<3>* recs = reinterpret_cast<Rec<3>*>(ws + L.recs);
+    uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
+    uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
+    k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
+    k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch, flags);
+    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, leaf_parent, node_parent, exch, ctrl);
+    k_reduce_labels<3><<<grid_for(n), 256, 0, st>>>(labels, leaf_parent, node_parent, recs, flags, n);
+    k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, node_parent, n - 1, d_left, d_right, d_label);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->h_ctrl->error || ctx->h_ctrl->root == kNone) return fail(ctx, EMST_EINTERNAL, "tree construction failed");
+    *root_out = (int32_t)ctx->h_ctrl->root;
+    return EMST_OK;
+}
+
+extern "C" int emst_test_radix_sort(emst_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, int64_t n, void* d_workspace,
+                                    size_t ws_bytes, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > 0x7FFFFFFFll || (n > 0 && (!d_keys || !d_vals || !d_workspace)))
+        return fail(ctx, EMST_EINVAL, "bad argument");
+    if (n < 2) return EMST_OK;
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(ctx, EMST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < emst_workspace_bytes(n, 3)) return fail(ctx, EMST_ENOMEM, "workspace too small");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* ws = (char*)d_workspace;
+    const Layout L = make_layout(n, 3);
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(ws + L.k1);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(ws + L.v1);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+    int shifts[8];
+    for (int q = 0; q < 8; ++q) shifts[q] = 8 * q;
+    int in1 = 0;
+    HIP_TRY(radix_sort_pairs(st, d_keys, d_vals, k1, v1, hist, n, shifts, 8, &in1));
+    if (in1) {
+        HIP_TRY(hipMemcpyAsync(d_keys, k1, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_vals, v1, 4 * (size_t)n, hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return EMST_OK;
+}

@@ -1,0 +1,171 @@
+// Device-side building blocks shared by the EMST kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emst {
+
+constexpr uint32_t kLeafFlag = 0x80000000u;   // child ref: leaf (low 31 bits = original index)
+constexpr uint32_t kInvalid = 0xFFFFFFFFu;    // label of a subtree that spans several components
+constexpr uint32_t kNone = 0xFFFFFFFFu;       // "no candidate" / "no parent"
+constexpr uint32_t kInfBits = 0x7F800000u;    // +inf as float32 bits
+constexpr uint64_t kKeyMax = ~0ull;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Node record of the binary LBVH.  One record per internal node holds
+// everything a traversal needs about BOTH children, so testing the two
+// children of a node is one contiguous read: per child its bounding box, its
+// reference (internal node index, or kLeafFlag | original point index) and
+// its component label (kInvalid if its leaves span several components).
+// With one point per leaf a leaf child's box is the point itself.
+//
+//   3D, 64 B:  child c at [32c, 32c+32): float4(lo.x, lo.y, lo.z, label)
+//                                        float4(hi.x, hi.y, hi.z, ref)
+//   2D, 48 B:  float4(lo0.x, lo0.y, hi0.x, hi0.y)
+//              float4(lo1.x, lo1.y, hi1.x, hi1.y)
+//              uint4 (label0, ref0, label1, ref1)
+template <int DIM> struct Rec;
+
+template <> struct alignas(64) Rec<3> {
+    float4 a0, b0, a1, b1;
+};
+template <> struct alignas(16) Rec<2> {
+    float4 box0, box1;
+    uint4 meta;
+};
+
+static_assert(sizeof(Rec<3>) == 64, "3D record is 64 bytes");
+static_assert(sizeof(Rec<2>) == 48, "2D record is 48 bytes");
+
+template <int DIM> struct Child {
+    float lo[DIM], hi[DIM];
+    uint32_t lab, ref;
+};
+
+__device__ __forceinline__ uint32_t fbits(float f) { return __float_as_uint(f); }
+__device__ __forceinline__ float bitsf(uint32_t u) { return __uint_as_float(u); }
+
+template <int DIM>
+__device__ __forceinline__ void unpack(const Rec<DIM>& r, Child<DIM>& c0, Child<DIM>& c1);
+
+template <>
+__device__ __forceinline__ void unpack<3>(const Rec<3>& r, Child<3>& c0, Child<3>& c1) {
+    c0.lo[0] = r.a0.x; c0.lo[1] = r.a0.y; c0.lo[2] = r.a0.z; c0.lab = fbits(r.a0.w);
+    c0.hi[0] = r.b0.x; c0.hi[1] = r.b0.y; c0.hi[2] = r.b0.z; c0.ref = fbits(r.b0.w);
+    c1.lo[0] = r.a1.x; c1.lo[1] = r.a1.y; c1.lo[2] = r.a1.z; c1.lab = fbits(r.a1.w);
+    c1.hi[0] = r.b1.x; c1.hi[1] = r.b1.y; c1.hi[2] = r.b1.z; c1.ref = fbits(r.b1.w);
+}
+
+template <>
+__device__ __forceinline__ void unpack<2>(const Rec<2>& r, Child<2>& c0, Child<2>& c1) {
+    c0.lo[0] = r.box0.x; c0.lo[1] = r.box0.y; c0.hi[0] = r.box0.z; c0.hi[1] = r.box0.w;
+    c1.lo[0] = r.box1.x; c1.lo[1] = r.box1.y; c1.hi[0] = r.box1.z; c1.hi[1] = r.box1.w;
+    c0.lab = r.meta.x; c0.ref = r.meta.y; c1.lab = r.meta.z; c1.ref = r.meta.w;
+}
+
+// Write the box and reference of child `side` of record r (labels are
+// written separately, every round).
+template <int DIM>
+__device__ __forceinline__ void store_child_box(Rec<DIM>* r, int side, const float* lo, const float* hi,
+                                                uint32_t ref);
+
+template <>
+__device__ __forceinline__ void store_child_box<3>(Rec<3>* r, int side, const float* lo, const float* hi,
+                                                   uint32_t ref) {
+    float* f = reinterpret_cast<float*>(r) + 8 * side;
+    f[0] = lo[0]; f[1] = lo[1]; f[2] = lo[2];
+    f[4] = hi[0]; f[5] = hi[1]; f[6] = hi[2];
+    f[7] = bitsf(ref);
+}
+
+template <>
+__device__ __forceinline__ void store_child_box<2>(Rec<2>* r, int side, const float* lo, const float* hi,
+                                                   uint32_t ref) {
+    float* f = reinterpret_cast<float*>(r) + 4 * side;
+    f[0] = lo[0]; f[1] = lo[1]; f[2] = hi[0]; f[3] = hi[1];
+    reinterpret_cast<uint32_t*>(r)[8 + 2 * side + 1] = ref;
+}
+
+template <int DIM>
+__device__ __forceinline__ uint32_t* label_slot(Rec<DIM>* r, int side);
+
+template <>
+__device__ __forceinline__ uint32_t* label_slot<3>(Rec<3>* r, int side) {
+    return reinterpret_cast<uint32_t*>(r) + 8 * side + 3;
+}
+template <>
+__device__ __forceinline__ uint32_t* label_slot<2>(Rec<2>* r, int side) {
+    return reinterpret_cast<uint32_t*>(r) + 8 + 2 * side;
+}
+
+template <int DIM>
+__device__ __forceinline__ void load_child_box(const Rec<DIM>* r, int side, float* lo, float* hi);
+
+template <>
+__device__ __forceinline__ void load_child_box<3>(const Rec<3>* r, int side, float* lo, float* hi) {
+    const float* f = reinterpret_cast<const float*>(r) + 8 * side;
+    lo[0] = f[0]; lo[1] = f[1]; lo[2] = f[2];
+    hi[0] = f[4]; hi[1] = f[5]; hi[2] = f[6];
+}
+template <>
+__device__ __forceinline__ void load_child_box<2>(const Rec<2>* r, int side, float* lo, float* hi) {
+    const float* f = reinterpret_cast<const float*>(r) + 4 * side;
+    lo[0] = f[0]; lo[1] = f[1]; hi[0] = f[2]; hi[1] = f[3];
+}
+
+// ---------------------------------------------------------------------------
+// Distances.  The float32 squared distance D is evaluated in one fixed
+// order -- d = a0 - b0; s = d*d; then s = s + (ak - bk)^2 for k = 1.. --
+// with every step rounded separately (no contraction into FMA).  The box
+// distance uses the same order on the per-coordinate gap
+// g = max(lo - p, 0, p - hi); rounding is monotone, so it never exceeds D(p, q)
+// for a q inside the box, and for a degenerate box (a leaf, lo = hi = q) it
+// equals D(p, q) bit for bit because |fl(q - p)| = |fl(p - q)|.
+
+#pragma clang fp contract(off)
+
+template <int DIM>
+__device__ __forceinline__ float sqdist(const float* a, const float* b) {
+    float d = a[0] - b[0];
+    float s = d * d;
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) {
+        d = a[k] - b[k];
+        s = s + d * d;
+    }
+    return s;
+}
+
+template <int DIM>
+__device__ __forceinline__ float boxdist(const float* p, const float* lo, const float* hi) {
+    float g = fmaxf(fmaxf(lo[0] - p[0], p[0] - hi[0]), 0.0f);
+    float s = g * g;
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) {
+        g = fmaxf(fmaxf(lo[k] - p[k], p[k] - hi[k]), 0.0f);
+        s = s + g * g;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// atomics with explicit scope / ordering
+
+__device__ __forceinline__ uint64_t atomic_xchg_acqrel(uint64_t* p, uint64_t v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_add_acqrel(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace emst

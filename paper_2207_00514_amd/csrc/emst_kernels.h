@@ -1,0 +1,43 @@
+// Kernels of the single-tree Boruvka EMST (gfx950).  Every kernel is a
+// template over the dimension so coordinate loops unroll.
+#pragma once
+
+#include "emst_common.h"
+
+namespace emst {
+
+// Device control block: reductions, counters and flags of one build.
+struct Ctrl {
+    uint32_t bb_min[3];      // order-preserving encoding of float (see ord_enc)
+    uint32_t bb_max[3];
+    uint32_t nonfinite;
+    uint32_t root;
+    uint32_t height;
+    uint32_t ncomp_next;
+    uint32_t edge_count;
+    uint32_t error;          // kErr* bits
+    uint64_t key_or;
+    uint64_t key_and;
+    unsigned long long internal_tests;
+    unsigned long long leaf_tests;
+    unsigned long long dist_evals;
+    uint32_t pad[8];
+};
+
+constexpr uint32_t kErrStack = 1u;
+constexpr uint32_t kErrNoEdge = 2u;
+constexpr uint32_t kErrJump = 4u;
+
+// float <-> uint32 whose unsigned order equals the float order (finite values)
+__device__ __forceinline__ uint32_t ord_enc(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float ord_dec(uint32_t u) {
+    uint32_t b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    float f;
+    __builtin_memcpy(&f, &b, 4);
+    return f;
+}
+
+}  // namespace emst

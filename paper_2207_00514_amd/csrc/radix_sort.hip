@@ -1,0 +1,165 @@
+// Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits,
+// written for gfx950 wave64.
+//
+// One pass = three launches:
+//   upsweep    every block counts the digits of its contiguous chunk of
+//              tiles into an LDS histogram (one sub-histogram per wave);
+//   scan       one block turns the digit-major [256][blocks] count table
+//              into exclusive global offsets;
+//   downsweep  every block walks its chunk tile by tile; inside a tile the
+//              stable rank of each item among equal digits comes from 8
+//              wave ballots (lanes with the same digit), per-(slot, wave)
+//              digit counts are staged in LDS and prefix-summed per digit,
+//              and the items are scattered to their global positions.
+// Items are loaded striped (item s of thread t is tile element s*256 + t),
+// so the (slot, wave, lane) order equals the input order and the sort is
+// stable.
+#include "radix_sort.h"
+
+namespace emst {
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int kRsWaves = kRsThreads / 64;
+
+__global__ __launch_bounds__(kRsThreads) void rs_upsweep(const uint64_t* __restrict__ keys, int64_t n,
+                                                         int shift, int64_t tiles_per_block,
+                                                         uint32_t* __restrict__ hist, int nb) {
+    __shared__ uint32_t h[kRsWaves][256];
+    const int t = threadIdx.x, w = t / 64;
+    for (int k = t; k < kRsWaves * 256; k += kRsThreads) (&h[0][0])[k] = 0;
+    __syncthreads();
+    const int64_t begin = (int64_t)blockIdx.x * tiles_per_block * kRsTile;
+    const int64_t end = min(n, begin + tiles_per_block * kRsTile);
+    for (int64_t i = begin + t; i < end; i += kRsThreads) {
+        uint32_t d = (uint32_t)(keys[i] >> shift) & 255u;
+        atomicAdd(&h[w][d], 1u);
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kRsWaves; ++k) s += h[k][t];
+    hist[(int64_t)t * nb + blockIdx.x] = s;
+}
+
+// Exclusive scan of `total` counts in place, one block of 1024 threads.
+__global__ __launch_bounds__(1024) void rs_scan(uint32_t* __restrict__ hist, int total) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (total + 1023) / 1024;
+    const int b = min(total, t * per), e = min(total, b + per);
+    uint32_t s = 0;
+    for (int k = b; k < e; ++k) s += hist[k];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int k = b; k < e; ++k) {
+        uint32_t c = hist[k];
+        hist[k] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin,
+                                                           uint64_t* __restrict__ kout,
+                                                           uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                           int64_t tiles_per_block,
+                                                           const uint32_t* __restrict__ hist, int nb) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t cnt[kRsItems][kRsWaves][256];
+    const int t = threadIdx.x, w = t / 64, lane = t & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    base[t] = hist[(int64_t)t * nb + blockIdx.x];
+    const int64_t first_tile = (int64_t)blockIdx.x * tiles_per_block;
+    const int64_t num_tiles = (n + kRsTile - 1) / kRsTile;
+    const int64_t last_tile = min(num_tiles, first_tile + tiles_per_block);
+    for (int64_t tile = first_tile; tile < last_tile; ++tile) {
+        for (int k = t; k < kRsItems * kRsWaves * 256; k += kRsThreads) (&cnt[0][0][0])[k] = 0;
+        __syncthreads();
+        const int64_t tb = tile * kRsTile;
+        uint64_t key[kRsItems];
+        uint32_t val[kRsItems], dig[kRsItems], rank[kRsItems];
+        bool ok[kRsItems];
+#pragma unroll
+        for (int s = 0; s < kRsItems; ++s) {
+            const int64_t idx = tb + (int64_t)s * kRsThreads + t;
+            ok[s] = idx < n;
+            key[s] = ok[s] ? kin[idx] : 0ull;
+            val[s] = ok[s] ? vin[idx] : 0u;
+            dig[s] = (uint32_t)(key[s] >> shift) & 255u;
+        }
+#pragma unroll
+        for (int s = 0; s < kRsItems; ++s) {
+            uint64_t peers = __ballot(ok[s]);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (dig[s] >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            rank[s] = (uint32_t)__popcll(peers & lt_mask);
+            if (ok[s] && rank[s] == 0) cnt[s][w][dig[s]] = (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        {
+            uint32_t off = base[t];
+#pragma unroll
+            for (int s = 0; s < kRsItems; ++s)
+#pragma unroll
+                for (int ww = 0; ww < kRsWaves; ++ww) {
+                    const uint32_t c = cnt[s][ww][t];
+                    cnt[s][ww][t] = off;
+                    off += c;
+                }
+            base[t] = off;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kRsItems; ++s) {
+            if (ok[s]) {
+                const uint32_t dst = cnt[s][w][dig[s]] + rank[s];
+                kout[dst] = key[s];
+                vout[dst] = val[s];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+RadixPlan radix_plan(int64_t n) {
+    RadixPlan p;
+    const int64_t tiles = (n + kRsTile - 1) / kRsTile;
+    p.blocks = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), kRadixMaxBlocks);
+    p.tiles_per_block = (tiles + p.blocks - 1) / p.blocks;
+    if (p.tiles_per_block < 1) p.tiles_per_block = 1;
+    return p;
+}
+
+hipError_t radix_sort_pairs(hipStream_t stream, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                            uint32_t* hist, int64_t n, const int* shifts, int nshifts, int* result_in_1) {
+    *result_in_1 = 0;
+    if (n <= 1 || nshifts == 0) return hipSuccess;
+    const RadixPlan p = radix_plan(n);
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    for (int q = 0; q < nshifts; ++q) {
+        rs_upsweep<<<p.blocks, kRsThreads, 0, stream>>>(ka, n, shifts[q], p.tiles_per_block, hist, p.blocks);
+        rs_scan<<<1, 1024, 0, stream>>>(hist, 256 * p.blocks);
+        rs_downsweep<<<p.blocks, kRsThreads, 0, stream>>>(ka, va, kb, vb, n, shifts[q], p.tiles_per_block,
+                                                           hist, p.blocks);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    *result_in_1 = (nshifts & 1);
+    return hipGetLastError();
+}
+
+}  // namespace emst

@@ -1,0 +1,66 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+the headers declare, and its host-only logic (workspace sizing) behaves.
+No GPU work is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2207_00514_amd as emst
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(emst_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_headers_declare_the_binding_exports():
+    assert set(declared_functions()) == set(emst.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(emst.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_library_is_built_for_gfx950():
+    data = open(emst.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_workspace_bytes():
+    wb = emst.workspace_bytes
+    assert wb(-1, 3) == 0 and wb(10, 4) == 0 and wb(10, 1) == 0 and wb(2 ** 31, 3) == 0
+    assert wb(0, 3) > 0 and wb(1, 2) > 0
+    prev = 0
+    for n in (2, 10, 1000, 10 ** 5, 10 ** 6, 37 * 10 ** 6):
+        b = wb(n, 3)
+        assert b > prev and b % 256 == 0
+        prev = b
+    # linear growth, about 150-200 bytes per 3D point
+    per_pt = (wb(10 ** 7, 3) - wb(10 ** 6, 3)) / 9e6
+    assert 120 < per_pt < 220
+    assert wb(10 ** 6, 2) < wb(10 ** 6, 3)
+
+
+def test_error_strings_without_a_context():
+    L = emst.lib()
+    assert L.emst_last_error(None) == b"null context"
+    assert L.emst_build(None, None, 0, 3, None, None, None, None, 0, None) == -1
+
+
+def test_oracle_is_not_imported_by_the_product_path():
+    src = open(os.path.join(ROOT, "paper_2207_00514_amd", "__init__.py")).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
+    for f in os.listdir(os.path.join(ROOT, "paper_2207_00514_amd", "csrc")):
+        assert "oracle" not in open(os.path.join(ROOT, "paper_2207_00514_amd", "csrc", f)).read().lower()

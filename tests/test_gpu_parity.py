@@ -1,0 +1,263 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: the edge set, the squared distances and the weights are bit-exact
+(integer indices equal, float32 bit patterns equal), and the FP64 total
+weight is equal; edges come in canonical (D, min, max) order."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_00514_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2207_00514_amd as emst
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    return emst.Context(0)
+
+
+def run(ctx, pts, variant=None):
+    if variant is not None:
+        ctx.set_traversal(variant)
+    e, w, d2 = ctx.build(torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda())
+    torch.cuda.synchronize()
+    return e.cpu().numpy(), w.cpu().numpy(), d2.cpu().numpy()
+
+
+def assert_same(got, ref, tag=""):
+    e, w, d2 = got
+    assert e.shape == ref.edges.shape, tag
+    bad = np.nonzero((e != ref.edges).any(axis=1))[0]
+    assert bad.size == 0, f"{tag}: {bad.size} edges differ, first at {bad[:5]}: {e[bad[:3]]} vs {ref.edges[bad[:3]]}"
+    np.testing.assert_array_equal(d2.view(np.uint32), ref.d2.view(np.uint32), err_msg=tag)
+    np.testing.assert_array_equal(w.view(np.uint32), ref.w.view(np.uint32), err_msg=tag)
+    total = float(np.cumsum(w.astype(np.float64))[-1]) if len(w) else 0.0
+    assert total == ref.total_weight, tag
+
+
+SMALL = [(n, dim, seed, kind)
+         for kind in ("uniform", "int", "dup", "outlier")
+         for dim in (2, 3)
+         for n, seed in ((2, 1), (3, 2), (5, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4099, 8))]
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("n,dim,seed,kind", SMALL)
+def test_small_clouds(ctx, n, dim, seed, kind, variant):
+    pts = W.small_random(n, dim, seed, kind)
+    print(f"case n={n} dim={dim} seed={seed} kind={kind} variant={variant}", flush=True)
+    assert_same(run(ctx, pts, variant), oracle.prim(pts), f"{kind} n={n} d={dim}")
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_closed_forms(ctx, variant):
+    cases = {
+        "identical": W.identical(1000),
+        "grid2d": W.integer_grid(40, 2, seed=1),
+        "grid3d": W.integer_grid(13, 3, seed=2),
+        "collinear": W.collinear(3000, 2, seed=3),
+        "dups": W.duplicates(300, 7, 3, seed=4),
+        "two_clusters": W.two_clusters(2000, 3, seed=5),
+    }
+    for name, pts in cases.items():
+        print(f"case {name} variant={variant}", flush=True)
+        assert_same(run(ctx, pts, variant), oracle.emst(pts, threads=8), name)
+
+
+def test_denormal_and_wide_range_coordinates(ctx):
+    rng = np.random.default_rng(3)
+    tiny = (rng.random((500, 3)) * 1e-19).astype(np.float32)   # D is denormal
+    assert_same(run(ctx, tiny), oracle.prim(tiny), "denormal")
+    big = (rng.random((500, 3)) * 1e18).astype(np.float32)     # D near 1e36, finite
+    assert_same(run(ctx, big), oracle.prim(big), "large")
+    neg = (rng.standard_normal((800, 2)) * 1e3).astype(np.float32)
+    assert_same(run(ctx, neg), oracle.prim(neg), "negative")
+
+
+def test_fewer_than_two_points(ctx):
+    for n in (0, 1):
+        e, w, d2 = run(ctx, np.zeros((n, 3), np.float32))
+        assert e.shape == (0, 2) and w.shape == (0,)
+
+
+def test_errors(ctx):
+    import paper_2207_00514_amd as emst
+    bad = np.zeros((10, 3), np.float32)
+    bad[4, 1] = np.nan
+    with pytest.raises(emst.EmstError) as ei:
+        run(ctx, bad)
+    assert ei.value.name == "EMST_ENONFINITE"
+    bad[4, 1] = np.inf
+    with pytest.raises(emst.EmstError) as ei:
+        run(ctx, bad)
+    assert ei.value.name == "EMST_ENONFINITE"
+    huge = np.zeros((10, 3), np.float32)
+    huge[0, 0] = 3e38
+    huge[1, 0] = -3e38
+    with pytest.raises(emst.EmstError) as ei:
+        run(ctx, huge)
+    assert ei.value.name == "EMST_ERANGE"
+    with pytest.raises(emst.EmstError) as ei:
+        run(ctx, np.zeros((10, 4), np.float32))
+    assert ei.value.name == "EMST_EINVAL"
+    # undersized workspace through the raw ABI
+    import ctypes
+    pts = torch.rand(100, 3, device="cuda")
+    out = [torch.empty(99, 2, dtype=torch.int32, device="cuda"), torch.empty(99, device="cuda")]
+    ws = torch.empty(emst.workspace_bytes(100, 3), dtype=torch.uint8, device="cuda")
+    rc = emst.lib().emst_build(ctx._h, ctypes.c_void_p(pts.data_ptr()), 100, 3,
+                               ctypes.c_void_p(out[0].data_ptr()), ctypes.c_void_p(out[1].data_ptr()),
+                               None, ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(1000),
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == -4
+    # the context still works afterwards
+    pts = W.small_random(300, 3, 1)
+    assert_same(run(ctx, pts), oracle.prim(pts), "after errors")
+
+
+def test_variants_counting_and_repeats_agree(ctx):
+    pts = W.clustered3d(60_000, seed=9)
+    ref = oracle.kdboruvka(pts, threads=8)
+    for variant in (0, 1):
+        for counting in (False, True):
+            ctx.set_counting(counting)
+            print(f"variant={variant} counting={counting}", flush=True)
+            for rep in range(2):
+                assert_same(run(ctx, pts, variant), ref, f"v{variant} c{counting} r{rep}")
+            if counting:
+                st = ctx.stats()
+                assert st["child_tests"] > 0 and st["leaf_tests"] > 0
+    ctx.set_counting(False)
+
+
+def test_round_structure(ctx):
+    pts = W.clustered3d(100_000, seed=10)
+    run(ctx, pts)
+    st = ctx.stats()
+    n = len(pts)
+    assert 1 <= st["rounds"] <= math.ceil(math.log2(n))
+    c = st["components"] + [1]
+    assert c[0] == n
+    for a, b in zip(c[:-1], c[1:]):
+        assert b <= a // 2
+    assert st["tree_height"] <= 96
+
+
+# ---------------------------------------------------------------------------
+# stages
+
+
+def test_fig4_tree_and_label_propagation(ctx):
+    g = json.load(open(os.path.join(GOLDEN, "fig4_label_reduction.json")))
+    codes = torch.tensor(g["codes"], dtype=torch.int64, device="cuda")
+    colours = {"green": 0, "red": 4, "orange": 5}
+    leaf = torch.tensor([colours[c] for c in g["leaf_colours"]], dtype=torch.int32, device="cuda")
+    left, right, label, root = ctx.test_tree_from_codes(codes, leaf)
+    left, right, label = left.cpu().tolist(), right.cpu().tolist(), label.cpu().numpy().view(np.uint32)
+    ref = oracle.radix_tree(g["codes"])
+    ref_lab = oracle.reduce_labels(ref, [colours[c] for c in g["leaf_colours"]])
+
+    def rng(ref_child):
+        return (-ref_child - 1, -ref_child - 1) if ref_child < 0 else (ref_child,)
+
+    ranges = {}
+
+    def span(k):
+        if k < 0:
+            return (-k - 1, -k - 1)
+        lo = span(left[k])[0]
+        hi = span(right[k])[1]
+        ranges[k] = (lo, hi)
+        return (lo, hi)
+
+    assert span(root) == (0, 7)
+    assert set(ranges.values()) == set(ref)
+    for k, rr in ranges.items():
+        assert (span(left[k]), span(right[k])) == ref[rr]
+        want = ref_lab[rr]
+        assert (label[k] == 0xFFFFFFFF) if want == oracle.INVALID else (label[k] == want)
+        # node k splits between leaves k and k+1
+        assert span(left[k])[1] == k
+
+
+def test_tree_and_labels_on_random_codes(ctx):
+    rng = np.random.default_rng(4)
+    for trial in range(20):
+        n = int(rng.integers(2, 3000))
+        hi = [4, 64, 2 ** 20, 2 ** 62][trial % 4]
+        codes = np.sort(rng.integers(0, hi, n, dtype=np.int64))
+        leaf = rng.integers(0, 1 + trial, n).astype(np.int32)
+        left, right, label, root = ctx.test_tree_from_codes(torch.from_numpy(codes).cuda(),
+                                                            torch.from_numpy(leaf).cuda())
+        left, right = left.cpu().numpy(), right.cpu().numpy()
+        label = label.cpu().numpy().view(np.uint32)
+        # ranges bottom-up via the split rule: node k covers [lo, hi] with k in it
+        ref = oracle.radix_tree(codes.tolist()) if n <= 400 else None
+        stack = [(root, None)]
+        spans = {}
+
+        def span(k):
+            if k < 0:
+                return (-k - 1, -k - 1)
+            if k in spans:
+                return spans[k]
+            a, b = span(left[k]), span(right[k])
+            assert a[1] + 1 == b[0] and a[1] == k
+            spans[k] = (a[0], b[1])
+            return spans[k]
+
+        import sys
+        sys.setrecursionlimit(100000)
+        assert span(root) == (0, n - 1)
+        assert len(spans) == n - 1
+        for k, (lo, hi_) in spans.items():
+            s = set(leaf[lo:hi_ + 1].tolist())
+            assert label[k] == (s.pop() if len(s) == 1 else 0xFFFFFFFF)
+            if ref is not None:
+                assert (span(left[k]), span(right[k])) == ref[(lo, hi_)]
+
+
+def test_radix_sort(ctx):
+    rng = np.random.default_rng(5)
+    for n in (2, 100, 2047, 2048, 2049, 100_000, 3_000_001):
+        keys = rng.integers(0, 2 ** 63, n, dtype=np.int64)
+        keys[: n // 3] = keys[0]  # many equal keys: stability matters
+        if n > 10:
+            keys[5] = -1  # top bit set (uint64 0xFFFF...)
+        vals = np.arange(n, dtype=np.int32)
+        k = torch.from_numpy(keys).cuda()
+        v = torch.from_numpy(vals).cuda()
+        ctx.test_radix_sort(k, v)
+        order = np.argsort(keys.view(np.uint64), kind="stable")
+        np.testing.assert_array_equal(k.cpu().numpy(), keys[order])
+        np.testing.assert_array_equal(v.cpu().numpy(), vals[order])
+
+
+# ---------------------------------------------------------------------------
+# full workloads
+
+
+def test_uniform2d_10k(ctx):
+    pts = W.uniform2d()
+    ref = oracle.prim(pts)
+    for variant in (0, 1):
+        assert_same(run(ctx, pts, variant), ref, f"uniform2d_10k v{variant}")
+
+
+def test_clustered3d_2m(ctx):
+    pts = W.clustered3d()
+    ref = oracle.kdboruvka(pts, threads=16)
+    for variant in (0, 1):
+        print(f"clustered3d_2m variant={variant}", flush=True)
+        assert_same(run(ctx, pts, variant), ref, f"clustered3d_2m v{variant}")
