@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""EMST throughput on one MI355X.
+
+One step = one emst_build of the whole synthetic cloud (tree construction,
+every Boruvka round, canonical edge order), points resident in HBM before
+the timed region starts.  Prints one JSON line:
+
+  value      Mpoints/s over the K timed steps (n * K / seconds)
+  roofline   the traversal kernel (the dominant kernel): algorithmic bytes
+             per launch / average launch duration (HIP events on the
+             library's stream, live in this run), against 8 TB/s HBM
+  cpu_baseline  the CPU oracle (kd-tree Boruvka, OpenMP) on the same cloud
+
+Algorithmic bytes of one traversal launch (one Boruvka round), from the
+instrumented traversal's counts of children examined:
+  internal child  2*dim*4 + 8 bytes  (box, reference, label)
+  leaf child      dim*4 + 8 bytes    (coordinates, label, original index)
+  per query       dim*4 + 16 bytes   (own coordinates, label, bound, candidate)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "EMST Mpoints/sec at 1 GPU + HBM roofline fraction; batched p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(dim: int, n: int, internal: int, leaf: int) -> int:
+    return internal * (8 * dim + 8) + leaf * (4 * dim + 8) + n * (4 * dim + 16)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="clustered3d_2m",
+                    choices=["uniform2d_10k", "clustered3d_2m", "cosmology3d_37m"])
+    ap.add_argument("--n", type=int, default=None, help="resize the workload (same recipe)")
+    ap.add_argument("--variant", type=int, default=None, help="traversal variant (default: library's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=None)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described but not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2207_00514_amd as emst
+    from paper_2207_00514_amd import workloads as W
+
+    spec = W.WORKLOADS[args.workload]
+    pts_np = W.make(args.workload, args.n)
+    n, dim = pts_np.shape
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(pts_np).to(dev)
+    m = n - 1
+    out = (torch.empty((m, 2), dtype=torch.int32, device=dev), torch.empty(m, dtype=torch.float32, device=dev),
+           torch.empty(m, dtype=torch.float32, device=dev))
+    ctx = emst.Context(0)
+    if args.variant is not None:
+        ctx.set_traversal(args.variant)
+    ctx.workspace(n, dim)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # instrumented (untimed) run: children examined per round
+    ctx.set_counting(True)
+    ctx.build(pts, out=out)
+    torch.cuda.synchronize()
+    cst = ctx.stats()
+    ctx.set_counting(False)
+
+    ctx.set_profiling(True)
+    for _ in range(args.warmup):
+        ctx.build(pts, out=out)
+    torch.cuda.synchronize()
+
+    trav_ms = 0.0
+    launches = 0
+    phases = {"tree_ms": 0.0, "rounds_ms": 0.0, "finalize_ms": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.build(pts, out=out)
+        st = ctx.stats()
+        trav_ms += st["traversal_ms"]
+        launches += st["traversal_launches"] if "traversal_launches" in st else st["rounds"]
+        for k in phases:
+            phases[k] += st[k]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    ms_per_step = 1e3 * secs / args.steps
+    value = n * args.steps / secs / 1e6
+
+    rounds = cst["rounds"]
+    bytes_per_step = sum(algorithmic_bytes(dim, n, ci, li)
+                         for ci, li in zip(cst["child_tests_round"], cst["leaf_tests_round"]))
+    avg_launch_ms = trav_ms / max(launches, 1)
+    bytes_per_launch = bytes_per_step / max(rounds, 1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
+
+    edges, w, d2 = (t.cpu().numpy() for t in out)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": int(n), "dim": int(dim), "seed": spec["seed"],
+                   "traversal_variant": args.variant if args.variant is not None else "default"},
+        "mfeatures_per_s": round(value * dim, 3),
+        "rounds": rounds,
+        "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in phases.items()},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "k_traverse",
+            "avg_launch_ms": round(avg_launch_ms, 4),
+            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "children_examined_per_query_round": round((cst["child_tests"] + cst["leaf_tests"]) / (n * rounds), 2),
+            "dist_evals_per_query_round": round(cst["dist_evals"] / (n * rounds), 2),
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        c0 = time.perf_counter()
+        ref = oracle.kdboruvka(pts_np, threads=threads)
+        c1 = time.perf_counter()
+        parity = (np.array_equal(edges, ref.edges) and np.array_equal(d2.view(np.uint32), ref.d2.view(np.uint32))
+                  and np.array_equal(w.view(np.uint32), ref.w.view(np.uint32)))
+        line["cpu_baseline"] = {
+            "value": round(n / (c1 - c0) / 1e6, 4),
+            "unit": "Mpoints/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"the full {args.workload} cloud (n={n}), one run of kd-tree Boruvka "
+                      f"with {threads} OpenMP threads, {c1 - c0:.2f} s",
+        }
+        line["parity"] = "bit-exact" if parity else "MISMATCH"
+
+    print(json.dumps(line), flush=True)
+    return 0 if line.get("parity", "bit-exact") == "bit-exact" else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -111,13 +111,15 @@ typedef struct emst_stats {
     double rounds_ms;               /* all rounds, every kernel */
     double finalize_ms;             /* canonical edge sort and weights */
     double total_ms;                /* whole call on the stream */
-    /* filled only when counting is on (emst_set_counting): child-box tests
-     * of internal nodes and of leaves (distance evaluations), summed over
-     * all points of all rounds, and per round */
+    /* filled only when counting is on (emst_set_counting): children
+     * examined by the traversal, internal nodes and leaves separately,
+     * summed over all points of all rounds, and per round */
     int64_t child_tests;
     int64_t leaf_tests;
     int64_t child_tests_round[64];
     int64_t leaf_tests_round[64];
+    int64_t dist_evals;             /* leaf children outside the query's
+                                       component: point distances computed */
 } emst_stats;
 
 /* Time every phase with HIP events (adds synchronisation; off by default). */

@@ -50,7 +50,7 @@ class Stats(ctypes.Structure):
         ("rounds_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
         ("total_ms", ctypes.c_double), ("child_tests", ctypes.c_int64),
         ("leaf_tests", ctypes.c_int64), ("child_tests_round", ctypes.c_int64 * 64),
-        ("leaf_tests_round", ctypes.c_int64 * 64),
+        ("leaf_tests_round", ctypes.c_int64 * 64), ("dist_evals", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -61,6 +61,8 @@ class Stats(ctypes.Structure):
             traversal_ms_round=list(self.traversal_ms_round[:r]), tree_ms=self.tree_ms,
             rounds_ms=self.rounds_ms, finalize_ms=self.finalize_ms, total_ms=self.total_ms,
             child_tests=self.child_tests, leaf_tests=self.leaf_tests,
+            child_tests_round=list(self.child_tests_round[:r]),
+            leaf_tests_round=list(self.leaf_tests_round[:r]), dist_evals=self.dist_evals,
         )
 
 

@@ -26,6 +26,8 @@ namespace emst {
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts, int64_t n, Ctrl* ctrl) {
+    __shared__ float s_lo[4][DIM], s_hi[4][DIM];
+    __shared__ uint32_t s_bad[4];
     float lo[DIM], hi[DIM];
     bool bad = false;
 #pragma unroll
@@ -46,7 +48,20 @@ __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts, int
             hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
         }
     const bool any_bad = __ballot(bad) != 0ull;
+    const int w = threadIdx.x / 64;
     if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) { s_lo[w][k] = lo[k]; s_hi[w][k] = hi[k]; }
+        s_bad[w] = any_bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int v = 0; v < 4; ++v) {
+            b |= s_bad[v];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) { lo[k] = fminf(lo[k], s_lo[v][k]); hi[k] = fmaxf(hi[k], s_hi[v][k]); }
+        }
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             if (lo[k] <= hi[k]) {
@@ -54,7 +69,7 @@ __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts, int
                 atomicMax(&ctrl->bb_max[k], ord_enc(hi[k]));
             }
         }
-        if (any_bad) atomicOr(&ctrl->nonfinite, 1u);
+        if (b) atomicOr(&ctrl->nonfinite, 1u);
     }
 }
 
@@ -100,9 +115,9 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, int64_t n, MortonParams mp,
                                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                 Ctrl* ctrl) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t code = 0, kor = 0, kand = ~0ull;
-    if (i < n) {
+    __shared__ uint64_t s_or[4], s_and[4];
+    uint64_t kor = 0, kand = ~0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t q[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -110,17 +125,23 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, i
             t = fmin(fmax(t, 0.0), mp.qmax);
             q[k] = (uint64_t)t;
         }
+        uint64_t code;
         if (DIM == 3) code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2 % DIM]);
         else code = (spread2(q[0]) << 1) | spread2(q[1 % DIM]);
         keys[i] = code;
         vals[i] = (uint32_t)i;
-        kor = kand = code;
+        kor |= code;
+        kand &= code;
     }
     for (int off = 32; off > 0; off >>= 1) {
         kor |= __shfl_xor(kor, off);
         kand &= __shfl_xor(kand, off);
     }
-    if (lane_id() == 0) {
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) { s_or[w] = kor; s_and[w] = kand; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; ++v) { kor |= s_or[v]; kand &= s_and[v]; }
         atomicOr((unsigned long long*)&ctrl->key_or, (unsigned long long)kor);
         atomicAnd((unsigned long long*)&ctrl->key_and, (unsigned long long)kand);
     }
@@ -135,7 +156,7 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, c
                                                 uint32_t* __restrict__ pos, uint32_t* __restrict__ labels,
                                                 uint32_t* __restrict__ ub, uint64_t* __restrict__ compkey,
                                                 uint32_t* __restrict__ compmax, uint64_t* __restrict__ exch,
-                                                uint32_t* __restrict__ flags) {
+                                                uint32_t* __restrict__ boxacc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t o = perm[i];
@@ -149,7 +170,11 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, c
     compmax[i] = kNone;
     if (i + 1 < n) {
         exch[i] = ~0ull;
-        flags[i] = 0u;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            boxacc[i * 2 * DIM + k] = 0xFFFFFFFFu;   // min accumulators
+            boxacc[i * 2 * DIM + DIM + k] = 0u;      // max accumulators
+        }
     }
 }
 
@@ -169,12 +194,21 @@ __device__ __forceinline__ int split_bit(const uint64_t* __restrict__ codes, int
 // (r, r+1) shares a longer prefix than its left neighbour pair (l-1, l),
 // else the right child of node l-1.  The first of the two children to reach
 // a parent parks its range end and height there and stops; the second
-// combines both boxes and continues upwards.
+// combines both and continues upwards.
+//
+// Data crosses between the two children only through device-scope atomics:
+// the range end and height travel in the exchanged 64-bit word, and each
+// child merges its box into the parent's min/max accumulators with atomics
+// that it waits on before the exchange; the second arrival issues its own
+// box atomics only after its exchange returned, and reads the merged box
+// from their return values.  (Agent-scope acquire/release would write back
+// and invalidate the per-XCD L2 caches at every step.)
 template <int DIM>
 __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ codes,
                                                const uint32_t* __restrict__ orig, const float* __restrict__ spts,
-                                               int64_t n, Rec<DIM>* recs, uint32_t* __restrict__ leaf_parent,
-                                               uint32_t* __restrict__ node_parent, uint64_t* exch, Ctrl* ctrl) {
+                                               int64_t n, Rec<DIM>* recs, uint32_t* __restrict__ node_parent,
+                                               uint64_t* exch, uint32_t* boxacc,
+                                               uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi, Ctrl* ctrl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float lo[DIM], hi[DIM];
@@ -198,16 +232,23 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         const uint32_t parent = (uint32_t)(left_child ? r : l - 1);
         const int side = left_child ? 0 : 1;
         store_child_box<DIM>(&recs[parent], side, lo, hi, self_ref);
-        const uint32_t link = (parent << 1) | (uint32_t)side;
-        if (leaf) leaf_parent[i] = link;
-        else node_parent[self] = link;
-        const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
-        const uint64_t other = atomic_xchg_acqrel(&exch[parent], mine);
-        if (other == ~0ull) return;
-        float slo[DIM], shi[DIM];
-        load_child_box<DIM>(&recs[parent], 1 - side, slo, shi);
+        if (!leaf) node_parent[self] = (parent << 1) | (uint32_t)side;
+        uint32_t* acc = boxacc + (size_t)parent * 2 * DIM;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) { lo[k] = fminf(lo[k], slo[k]); hi[k] = fmaxf(hi[k], shi[k]); }
+        for (int k = 0; k < DIM; ++k) {
+            atomicMin(&acc[k], ord_enc(lo[k]));
+            atomicMax(&acc[DIM + k], ord_enc(hi[k]));
+        }
+        // the box atomics are performed before the exchange is issued
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
+        const uint64_t other = atomicExch((unsigned long long*)&exch[parent], (unsigned long long)mine);
+        if (other == ~0ull) return;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = fminf(lo[k], ord_dec(atomicMin(&acc[k], ord_enc(lo[k]))));
+            hi[k] = fmaxf(hi[k], ord_dec(atomicMax(&acc[DIM + k], ord_enc(hi[k]))));
+        }
         const int64_t oend = (int64_t)(other >> 32);
         if (left_child) r = oend;
         else l = oend;
@@ -215,6 +256,8 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         self = parent;
         self_ref = parent;
         leaf = false;
+        rlo[parent] = (uint32_t)l;
+        rhi[parent] = (uint32_t)r;
         if (l == 0 && r == n - 1) {
             ctrl->root = parent;
             ctrl->height = h;
@@ -228,31 +271,99 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
 // one Boruvka round
 
 // Optimization 1 (Section 3): every internal node gets its leaves' common
-// component label, or kInvalid.  One thread per leaf climbs the tree; the
-// first arrival at a node stops, the second combines the two child labels
-// and goes on.  Labels live in the parent's record next to each child's box.
-// The per-node arrival counter grows by 2 every round, so its parity tells
-// first from second arrival without a reset.
-template <int DIM>
-__global__ __launch_bounds__(256) void k_reduce_labels(const uint32_t* __restrict__ labels,
-                                                       const uint32_t* __restrict__ leaf_parent,
-                                                       const uint32_t* __restrict__ node_parent, Rec<DIM>* recs,
-                                                       uint32_t* flags, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t lab = labels[i];
-    uint32_t link = leaf_parent[i];
-    for (int step = 0; step <= 128; ++step) {
-        const uint32_t node = link >> 1;
-        const int side = (int)(link & 1u);
-        *label_slot<DIM>(&recs[node], side) = lab;
-        const uint32_t old = atomic_add_acqrel(&flags[node], 1u);
-        if ((old & 1u) == 0u) return;
-        const uint32_t other = *label_slot<DIM>(&recs[node], 1 - side);
-        lab = (other == lab) ? lab : kInvalid;
-        link = node_parent[node];
-        if (link == kNone) return;
+// component label, or kInvalid.  The paper propagates labels bottom-up with
+// first/second-arrival threads; here the same labels come from the leaf
+// ranges instead: in Morton order a node's leaves are the range [lo, hi],
+// and they share one label exactly when the run of equal labels containing
+// hi starts at or before lo.  run_start[p] is a max-scan of the positions
+// where the label changes, so the pass is three streaming kernels plus one
+// thread per record, with no inter-thread hand-off.
+
+constexpr int kRunTile = 4096;  // 256 threads x 16 positions
+
+__device__ __forceinline__ uint32_t run_head(const uint32_t* __restrict__ labels, int64_t p) {
+    return (p == 0 || labels[p - 1] != labels[p]) ? (uint32_t)p : 0u;
+}
+
+// Inclusive max-scan over the block (blockDim.x a multiple of 64, at most
+// 1024); s_w holds one slot per wave.
+__device__ __forceinline__ uint32_t block_max_scan_incl(uint32_t x, uint32_t* s_w) {
+    const int lane = lane_id(), w = threadIdx.x / 64;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x = max(x, y);
     }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before = max(before, s_w[k]);
+    __syncthreads();
+    return max(x, before);
+}
+
+__global__ __launch_bounds__(256) void k_runs_reduce(const uint32_t* __restrict__ labels, int64_t n,
+                                                     uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kRunTile;
+    uint32_t m = 0;
+    for (int q = 0; q < kRunTile / 256; ++q) {
+        const int64_t p = base + (int64_t)q * 256 + threadIdx.x;
+        if (p < n) m = max(m, run_head(labels, p));
+    }
+    m = block_max_scan_incl(m, s_w);
+    if (threadIdx.x == 255) part[blockIdx.x] = m;
+}
+
+// part[b] <- max(part[0..b-1]) (0 for b = 0); one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_runs_scan(uint32_t* part, int nb) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_incl[1024];
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int b = b0 + (int)threadIdx.x;
+        const uint32_t incl = block_max_scan_incl(b < nb ? part[b] : 0u, s_w);
+        s_incl[threadIdx.x] = incl;
+        __syncthreads();
+        const uint32_t excl = threadIdx.x > 0 ? s_incl[threadIdx.x - 1] : 0u;
+        if (b < nb) part[b] = max(carry, excl);
+        carry = max(carry, s_incl[1023]);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_runs_down(const uint32_t* __restrict__ labels, int64_t n,
+                                                   const uint32_t* __restrict__ part,
+                                                   uint32_t* __restrict__ run_start) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_last;
+    const int64_t base = (int64_t)blockIdx.x * kRunTile;
+    uint32_t carry = part[blockIdx.x];
+    for (int q = 0; q < kRunTile / 256; ++q) {
+        const int64_t p = base + (int64_t)q * 256 + threadIdx.x;
+        const uint32_t v = (p < n) ? run_head(labels, p) : 0u;
+        const uint32_t x = max(block_max_scan_incl(v, s_w), carry);
+        if (p < n) run_start[p] = x;
+        if (threadIdx.x == 255) s_last = x;
+        __syncthreads();
+        carry = s_last;
+        __syncthreads();
+    }
+}
+
+// Record k holds the children [lo_k, k] and [k+1, hi_k].
+template <int DIM>
+__global__ __launch_bounds__(256) void k_record_labels(const uint32_t* __restrict__ labels,
+                                                       const uint32_t* __restrict__ run_start,
+                                                       const uint32_t* __restrict__ rlo,
+                                                       const uint32_t* __restrict__ rhi, Rec<DIM>* recs,
+                                                       int64_t m) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const uint32_t lo = rlo[k], hi = rhi[k];
+    const uint32_t a = labels[k], b = labels[k + 1];
+    *label_slot<DIM>(&recs[k], 0) = (run_start[k] <= lo) ? a : kInvalid;
+    *label_slot<DIM>(&recs[k], 1) = (run_start[hi] <= (uint32_t)(k + 1)) ? b : kInvalid;
 }
 
 // Optimization 2 (Section 3): a Morton-adjacent pair with different labels
@@ -324,17 +435,30 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
                                                       uint32_t* __restrict__ eu, uint32_t* __restrict__ ev,
                                                       uint32_t* __restrict__ ed, Ctrl* ctrl, int64_t n) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n || labels[c] != (uint32_t)c) return;
-    const uint32_t s = succ[c];
-    const bool root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
-    par[c] = root ? (uint32_t)c : s;
+    const bool comp = c < n && labels[c] == (uint32_t)c;
+    bool root = false;
+    if (comp) {
+        const uint32_t s = succ[c];
+        root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
+        par[c] = root ? (uint32_t)c : s;
+    }
+    // one counter update per wave
+    const uint64_t rmask = __ballot(comp && root), emask = __ballot(comp && !root);
+    const int lane = lane_id();
+    uint32_t base = 0;
+    if (lane == 0) {
+        if (rmask) atomicAdd(&ctrl->ncomp_next, (uint32_t)__popcll(rmask));
+        if (emask) base = atomicAdd(&ctrl->edge_count, (uint32_t)__popcll(emask));
+    }
+    base = __shfl(base, 0);
+    if (!comp) return;
     if (root) {
-        atomicAdd(&ctrl->ncomp_next, 1u);
         ub[c] = kInfBits;
         compkey[c] = kKeyMax;
         compmax[c] = kNone;
     } else {
-        const uint32_t slot = atomicAdd(&ctrl->edge_count, 1u);
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const uint32_t slot = base + (uint32_t)__popcll(emask & lt);
         if (slot >= (uint32_t)(n - 1)) {
             atomicOr(&ctrl->error, kErrNoEdge);
             return;
@@ -419,8 +543,8 @@ __global__ __launch_bounds__(256) void k_edge_write(const uint32_t* __restrict__
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, leaf_parent, node_parent, exch, flags, labels, ub,
-        compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, node_parent, exch, boxacc, rlo, rhi, run_start,
+        run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -444,10 +568,13 @@ static Layout make_layout(int64_t n, int dim) {
     L.orig = take(4 * N);
     L.pos = take(4 * N);
     L.recs = take(M * (dim == 3 ? sizeof(Rec<3>) : sizeof(Rec<2>)));
-    L.leaf_parent = take(4 * N);
     L.node_parent = take(4 * M);
     L.exch = take(8 * M);
-    L.flags = take(4 * M);
+    L.boxacc = take(4 * 2 * (size_t)dim * M);
+    L.rlo = take(4 * M);
+    L.rhi = take(4 * M);
+    L.run_start = take(4 * N);
+    L.run_part = take(4 * (N / kRunTile + 2));
     L.labels = take(4 * N);
     L.ub = take(4 * N);
     L.compkey = take(8 * N);
@@ -566,6 +693,17 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }
 
 template <int DIM>
+hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_start, uint32_t* run_part, const uint32_t* rlo,
+                            const uint32_t* rhi, Rec<DIM>* recs, int64_t n, hipStream_t st) {
+    const int nb = (int)((n + kRunTile - 1) / kRunTile);
+    k_runs_reduce<<<nb, 256, 0, st>>>(labels, n, run_part);
+    k_runs_scan<<<1, 1024, 0, st>>>(run_part, nb);
+    k_runs_down<<<nb, 256, 0, st>>>(labels, n, run_part, run_start);
+    k_record_labels<DIM><<<grid_for(n - 1), 256, 0, st>>>(labels, run_start, rlo, rhi, recs, n - 1);
+    return hipGetLastError();
+}
+
+template <int DIM>
 int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float* weights, float* d2, char* ws,
                hipStream_t st) {
     const Layout L = make_layout(n, DIM);
@@ -579,10 +717,13 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     uint32_t* orig = reinterpret_cast<uint32_t*>(ws + L.orig);
     uint32_t* pos = reinterpret_cast<uint32_t*>(ws + L.pos);
     Rec<DIM>* recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
-    uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
     uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
-    uint32_t* flags = reinterpret_cast<uint32_t*>(ws + L.flags);
+    uint32_t* boxacc = reinterpret_cast<uint32_t*>(ws + L.boxacc);
+    uint32_t* rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
+    uint32_t* rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
+    uint32_t* run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
+    uint32_t* run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
     uint32_t* labels = reinterpret_cast<uint32_t*>(ws + L.labels);
     uint32_t* ub = reinterpret_cast<uint32_t*>(ws + L.ub);
     uint64_t* compkey = reinterpret_cast<uint64_t*>(ws + L.compkey);
@@ -605,7 +746,7 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     if (prof) HIP_TRY(hipEventRecord(E[0], st));
     // ---- validation + scene box
     k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
-    k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 4096), 256, 0, st>>>(pts, n, ctrl);
+    k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, ctrl);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -634,7 +775,7 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
         const double ext = k < DIM ? (double)hi[k] - (double)lo[k] : 0.0;
         mp.scale[k] = ext > 0.0 ? mp.qmax / ext : 0.0;
     }
-    k_morton<DIM><<<grid_for(n), 256, 0, st>>>(pts, n, mp, k0, v0, ctrl);
+    k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, mp, k0, v0, ctrl);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -650,8 +791,9 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     const uint32_t* perm = in1 ? v1 : v0;
     // ---- hierarchy + boxes
     k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, spts, orig, pos, labels, ub, compkey, compmax, exch,
-                                               flags);
-    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, leaf_parent, node_parent, exch, ctrl);
+                                               boxacc);
+    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, node_parent, exch, boxacc, rlo, rhi,
+                                              ctrl);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -670,7 +812,7 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     while (ncomp > 1) {
         if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
         S.components[round] = ncomp;
-        k_reduce_labels<DIM><<<grid_for(n), 256, 0, st>>>(labels, leaf_parent, node_parent, recs, flags, n);
+        HIP_TRY(propagate_labels<DIM>(labels, run_start, run_part, rlo, rhi, recs, n, st));
         k_bounds<DIM><<<grid_for(n), 256, 0, st>>>(spts, labels, n, ub, ctrl);
         if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
         HIP_TRY(launch_traverse<DIM>(ta, S.tree_height, ctx->traversal, ctx->counting, st));
@@ -687,6 +829,14 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
         if (ctx->h_ctrl->error & kErrStack) return fail(ctx, EMST_EINTERNAL, "traversal stack overflow");
         if (ctx->h_ctrl->error & kErrJump) return fail(ctx, EMST_EINTERNAL, "component merge did not converge");
         if (ctx->h_ctrl->error) return fail(ctx, EMST_EINTERNAL, "a component found no outgoing edge");
+        if (ctx->counting) {
+            const int64_t it = (int64_t)ctx->h_ctrl->internal_tests, lt = (int64_t)ctx->h_ctrl->leaf_tests;
+            S.child_tests_round[round] = it - S.child_tests;
+            S.leaf_tests_round[round] = lt - S.leaf_tests;
+            S.child_tests = it;
+            S.leaf_tests = lt;
+            S.dist_evals = (int64_t)ctx->h_ctrl->dist_evals;
+        }
         const int64_t next = ctx->h_ctrl->ncomp_next;
         if (next >= ncomp || next < 1) return fail(ctx, EMST_EINTERNAL, "round made no progress");
         ncomp = next;
@@ -695,10 +845,6 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     S.rounds = round;
     S.traversal_launches = round;
     if (ctx->h_ctrl->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
-    if (ctx->counting) {
-        S.child_tests = (int64_t)ctx->h_ctrl->internal_tests;
-        S.leaf_tests = (int64_t)ctx->h_ctrl->leaf_tests;
-    }
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
 
     // ---- canonical order: by (u, v) first, then stably by D bits
@@ -766,7 +912,7 @@ namespace emst {
 __global__ __launch_bounds__(256) void k_test_prep(const uint32_t* __restrict__ leaf_labels, int64_t n,
                                                    float* __restrict__ spts, uint32_t* __restrict__ orig,
                                                    uint32_t* __restrict__ labels, uint64_t* __restrict__ exch,
-                                                   uint32_t* __restrict__ flags) {
+                                                   uint32_t* __restrict__ boxacc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     spts[3 * i] = spts[3 * i + 1] = spts[3 * i + 2] = 0.f;
@@ -774,7 +920,10 @@ __global__ __launch_bounds__(256) void k_test_prep(const uint32_t* __restrict__ 
     labels[i] = leaf_labels[i];
     if (i + 1 < n) {
         exch[i] = ~0ull;
-        flags[i] = 0u;
+        for (int k = 0; k < 3; ++k) {
+            boxacc[i * 6 + k] = 0xFFFFFFFFu;
+            boxacc[i * 6 + 3 + k] = 0u;
+        }
     }
 }
 
@@ -819,14 +968,17 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint32_t* orig = reinterpret_cast<uint32_t*>(ws + L.orig);
     uint32_t* labels = reinterpret_cast<uint32_t*>(ws + L.labels);
     uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
-    uint32_t* flags = reinterpret_cast<uint32_t*>(ws + L.flags);
+    uint32_t* boxacc = reinterpret_cast<uint32_t*>(ws + L.boxacc);
+    uint32_t* rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
+    uint32_t* rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
+    uint32_t* run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
+    uint32_t* run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
     Rec<3>* recs = reinterpret_cast<Rec<3>*>(ws + L.recs);
-    uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
     k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
-    k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch, flags);
-    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, leaf_parent, node_parent, exch, ctrl);
-    k_reduce_labels<3><<<grid_for(n), 256, 0, st>>>(labels, leaf_parent, node_parent, recs, flags, n);
+    k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch, boxacc);
+    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, node_parent, exch, boxacc, rlo, rhi, ctrl);
+    HIP_TRY(propagate_labels<3>(labels, run_start, run_part, rlo, rhi, recs, n, st));
     k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, node_parent, n - 1, d_left, d_right, d_label);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));

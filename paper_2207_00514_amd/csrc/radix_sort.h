@@ -17,8 +17,8 @@ struct RadixPlan {
 
 RadixPlan radix_plan(int64_t n);
 
-// Count table the sort needs: uint32[256 * kRadixMaxBlocks].
-constexpr size_t radix_hist_elems() { return (size_t)256 * kRadixMaxBlocks; }
+// Count table the sort needs: uint32[256 * kRadixMaxBlocks] plus 256 row totals.
+constexpr size_t radix_hist_elems() { return (size_t)256 * kRadixMaxBlocks + 256; }
 
 // Sort n pairs stably by the 8-bit digits at `shifts` (least significant
 // digit first).  Input in (k0, v0); (k1, v1) is scratch of the same size.

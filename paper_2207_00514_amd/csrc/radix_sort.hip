@@ -4,13 +4,15 @@
 // One pass = three launches:
 //   upsweep    every block counts the digits of its contiguous chunk of
 //              tiles into an LDS histogram (one sub-histogram per wave);
-//   scan       one block turns the digit-major [256][blocks] count table
-//              into exclusive global offsets;
+//   rowscan    one block per digit scans that digit's counts across the
+//              blocks (exclusive) and records the digit total;
 //   downsweep  every block walks its chunk tile by tile; inside a tile the
 //              stable rank of each item among equal digits comes from 8
 //              wave ballots (lanes with the same digit), per-(slot, wave)
 //              digit counts are staged in LDS and prefix-summed per digit,
-//              and the items are scattered to their global positions.
+//              and the items are scattered to their global positions
+//              (every block first turns the 256 digit totals into digit
+//              start offsets itself).
 // Items are loaded striped (item s of thread t is tile element s*256 + t),
 // so the (slot, wave, lane) order equals the input order and the sort is
 // stable.
@@ -43,28 +45,35 @@ __global__ __launch_bounds__(kRsThreads) void rs_upsweep(const uint64_t* __restr
     hist[(int64_t)t * nb + blockIdx.x] = s;
 }
 
-// Exclusive scan of `total` counts in place, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void rs_scan(uint32_t* __restrict__ hist, int total) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (total + 1023) / 1024;
-    const int b = min(total, t * per), e = min(total, b + per);
-    uint32_t s = 0;
-    for (int k = b; k < e; ++k) s += hist[k];
-    part[t] = s;
+// Exclusive scan of every digit's row of the count table across the blocks
+// (one block per digit, one entry per thread); the row total goes to
+// row_total[digit].  Rows have at most kRadixMaxBlocks = 1024 entries.
+__global__ __launch_bounds__(1024) void rs_rowscan(uint32_t* __restrict__ hist, int nb,
+                                                   uint32_t* __restrict__ row_total) {
+    __shared__ uint32_t wsum[16];
+    const int d = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t v = (t < nb) ? hist[(int64_t)d * nb + t] : 0u;
+    uint32_t x = v;  // inclusive scan inside the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = (t >= off) ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    if (t < 16) {
+        uint32_t s = wsum[t];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t y = __shfl_up(s, off);
+            if (t >= off) s += y;
+        }
+        wsum[t] = s;
     }
-    uint32_t run = part[t] - s;
-    for (int k = b; k < e; ++k) {
-        uint32_t c = hist[k];
-        hist[k] = run;
-        run += c;
-    }
+    __syncthreads();
+    const uint32_t incl = x + (w > 0 ? wsum[w - 1] : 0u);
+    if (t < nb) hist[(int64_t)d * nb + t] = incl - v;
+    if (t == 1023) row_total[d] = incl;
 }
 
 __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __restrict__ kin,
@@ -72,12 +81,28 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
                                                            uint64_t* __restrict__ kout,
                                                            uint32_t* __restrict__ vout, int64_t n, int shift,
                                                            int64_t tiles_per_block,
-                                                           const uint32_t* __restrict__ hist, int nb) {
+                                                           const uint32_t* __restrict__ hist, int nb,
+                                                           const uint32_t* __restrict__ row_total) {
     __shared__ uint32_t base[256];
+    __shared__ uint32_t wsum[kRsWaves];
     __shared__ uint32_t cnt[kRsItems][kRsWaves][256];
     const int t = threadIdx.x, w = t / 64, lane = t & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    base[t] = hist[(int64_t)t * nb + blockIdx.x];
+    {
+        // global start of digit t = sum of the totals of the smaller digits
+        const uint32_t v = row_total[t];
+        uint32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        base[t] = (x - v) + before + hist[(int64_t)t * nb + blockIdx.x];
+    }
     const int64_t first_tile = (int64_t)blockIdx.x * tiles_per_block;
     const int64_t num_tiles = (n + kRsTile - 1) / kRsTile;
     const int64_t last_tile = min(num_tiles, first_tile + tiles_per_block);
@@ -152,9 +177,9 @@ hipError_t radix_sort_pairs(hipStream_t stream, uint64_t* k0, uint32_t* v0, uint
     uint32_t *va = v0, *vb = v1;
     for (int q = 0; q < nshifts; ++q) {
         rs_upsweep<<<p.blocks, kRsThreads, 0, stream>>>(ka, n, shifts[q], p.tiles_per_block, hist, p.blocks);
-        rs_scan<<<1, 1024, 0, stream>>>(hist, 256 * p.blocks);
+        rs_rowscan<<<256, 1024, 0, stream>>>(hist, p.blocks, hist + 256 * kRadixMaxBlocks);
         rs_downsweep<<<p.blocks, kRsThreads, 0, stream>>>(ka, va, kb, vb, n, shifts[q], p.tiles_per_block,
-                                                           hist, p.blocks);
+                                                           hist, p.blocks, hist + 256 * kRadixMaxBlocks);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
