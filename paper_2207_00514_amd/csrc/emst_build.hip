@@ -156,7 +156,8 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, c
                                                 uint32_t* __restrict__ pos, uint32_t* __restrict__ labels,
                                                 uint32_t* __restrict__ ub, uint64_t* __restrict__ compkey,
                                                 uint32_t* __restrict__ compmax, uint64_t* __restrict__ exch,
-                                                uint32_t* __restrict__ boxacc) {
+                                                uint32_t* __restrict__ eu,
+                                                uint32_t* __restrict__ ev, uint32_t* __restrict__ ed) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t o = perm[i];
@@ -168,14 +169,8 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, c
     ub[i] = kInfBits;
     compkey[i] = kKeyMax;
     compmax[i] = kNone;
-    if (i + 1 < n) {
-        exch[i] = ~0ull;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            boxacc[i * 2 * DIM + k] = 0xFFFFFFFFu;   // min accumulators
-            boxacc[i * 2 * DIM + DIM + k] = 0u;      // max accumulators
-        }
-    }
+    eu[i] = ev[i] = ed[i] = kNone;   // the final root's slot keeps these and sorts last
+    if (i + 1 < n) exch[i] = ~0ull;
 }
 
 // Highest differing bit between sorted augmented keys (code, index) k and
@@ -196,18 +191,18 @@ __device__ __forceinline__ int split_bit(const uint64_t* __restrict__ codes, int
 // a parent parks its range end and height there and stops; the second
 // combines both and continues upwards.
 //
-// Data crosses between the two children only through device-scope atomics:
-// the range end and height travel in the exchanged 64-bit word, and each
-// child merges its box into the parent's min/max accumulators with atomics
-// that it waits on before the exchange; the second arrival issues its own
-// box atomics only after its exchange returned, and reads the merged box
-// from their return values.  (Agent-scope acquire/release would write back
-// and invalidate the per-XCD L2 caches at every step.)
+// Data crosses between the two children only through device-scope atomic
+// operations: the range end and height travel in the exchanged 64-bit word;
+// each child writes its box into the parent's record with device-scope
+// stores and waits for them to complete before the exchange, and the second
+// arrival reads its sibling's box with device-scope loads issued after its
+// exchange returned.  (Agent-scope acquire/release would write back and
+// invalidate the per-XCD L2 caches at every step.)
 template <int DIM>
 __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ codes,
                                                const uint32_t* __restrict__ orig, const float* __restrict__ spts,
                                                int64_t n, Rec<DIM>* recs, uint32_t* __restrict__ node_parent,
-                                               uint64_t* exch, uint32_t* boxacc,
+                                               uint64_t* exch,
                                                uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi, Ctrl* ctrl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -231,23 +226,19 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         else left_child = split_bit(codes, r) < split_bit(codes, l - 1);
         const uint32_t parent = (uint32_t)(left_child ? r : l - 1);
         const int side = left_child ? 0 : 1;
-        store_child_box<DIM>(&recs[parent], side, lo, hi, self_ref);
+        store_child_box_coherent<DIM>(&recs[parent], side, lo, hi, self_ref);
         if (!leaf) node_parent[self] = (parent << 1) | (uint32_t)side;
-        uint32_t* acc = boxacc + (size_t)parent * 2 * DIM;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            atomicMin(&acc[k], ord_enc(lo[k]));
-            atomicMax(&acc[DIM + k], ord_enc(hi[k]));
-        }
-        // the box atomics are performed before the exchange is issued
+        // the box is stored before the exchange is issued
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
         const uint64_t other = atomicExch((unsigned long long*)&exch[parent], (unsigned long long)mine);
         if (other == ~0ull) return;
+        float slo[DIM], shi[DIM];
+        load_child_box_coherent<DIM>(&recs[parent], 1 - side, slo, shi);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            lo[k] = fminf(lo[k], ord_dec(atomicMin(&acc[k], ord_enc(lo[k]))));
-            hi[k] = fmaxf(hi[k], ord_dec(atomicMax(&acc[DIM + k], ord_enc(hi[k]))));
+            lo[k] = fminf(lo[k], slo[k]);
+            hi[k] = fmaxf(hi[k], shi[k]);
         }
         const int64_t oend = (int64_t)(other >> 32);
         if (left_child) r = oend;
@@ -367,21 +358,42 @@ __global__ __launch_bounds__(256) void k_record_labels(const uint32_t* __restric
 }
 
 // Optimization 2 (Section 3): a Morton-adjacent pair with different labels
-// bounds the shortest outgoing edge of both components by its D.
-template <int DIM>
+// bounds the shortest outgoing edge of both components by its D.  Every
+// position takes the smaller D to its neighbours outside its component; in
+// the first round every point is its own component and writes its bound
+// directly, later the positions of a run of equal labels within a wave
+// combine first and one lane per run updates the component.
+template <int DIM, bool FIRST>
 __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, const uint32_t* __restrict__ labels,
                                                 int64_t n, uint32_t* ub, Ctrl* ctrl) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) ctrl->ncomp_next = 0u;
-    if (k + 1 >= n) return;
-    const uint32_t a = labels[k], b = labels[k + 1];
-    if (a == b) return;
-    float p[DIM], q[DIM];
+    uint32_t lab = kNone, v = kInfBits;
+    if (k < n) {
+        lab = labels[k];
+        float p[DIM];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) { p[c] = spts[k * DIM + c]; q[c] = spts[(k + 1) * DIM + c]; }
-    const uint32_t d = fbits(sqdist<DIM>(p, q));
-    atomicMin(&ub[a], d);
-    atomicMin(&ub[b], d);
+        for (int c = 0; c < DIM; ++c) p[c] = spts[k * DIM + c];
+        if (k > 0 && labels[k - 1] != lab) {
+            float q[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) q[c] = spts[(k - 1) * DIM + c];
+            v = min(v, fbits(sqdist<DIM>(q, p)));
+        }
+        if (k + 1 < n && labels[k + 1] != lab) {
+            float q[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) q[c] = spts[(k + 1) * DIM + c];
+            v = min(v, fbits(sqdist<DIM>(p, q)));
+        }
+    }
+    if (FIRST) {
+        if (k < n) ub[k] = v;
+        return;
+    }
+    bool run_end;
+    v = wave_seg_min<uint32_t>(lab, v, &run_end);
+    if (k < n && run_end && v != kInfBits) atomicMin(&ub[lab], v);
 }
 
 // Stage B of the component minimum: among the points whose candidate matches
@@ -434,39 +446,42 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
                                                       uint64_t* compkey, uint32_t* compmax, uint32_t* ub,
                                                       uint32_t* __restrict__ eu, uint32_t* __restrict__ ev,
                                                       uint32_t* __restrict__ ed, Ctrl* ctrl, int64_t n) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool comp = c < n && labels[c] == (uint32_t)c;
-    bool root = false;
-    if (comp) {
+    __shared__ uint32_t s_cnt[2];
+    if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t roots = 0, emitted = 0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        if (labels[c] != (uint32_t)c) continue;
         const uint32_t s = succ[c];
-        root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
+        const bool root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
         par[c] = root ? (uint32_t)c : s;
-    }
-    // one counter update per wave
-    const uint64_t rmask = __ballot(comp && root), emask = __ballot(comp && !root);
-    const int lane = lane_id();
-    uint32_t base = 0;
-    if (lane == 0) {
-        if (rmask) atomicAdd(&ctrl->ncomp_next, (uint32_t)__popcll(rmask));
-        if (emask) base = atomicAdd(&ctrl->edge_count, (uint32_t)__popcll(emask));
-    }
-    base = __shfl(base, 0);
-    if (!comp) return;
-    if (root) {
-        ub[c] = kInfBits;
-        compkey[c] = kKeyMax;
-        compmax[c] = kNone;
-    } else {
-        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        const uint32_t slot = base + (uint32_t)__popcll(emask & lt);
-        if (slot >= (uint32_t)(n - 1)) {
-            atomicOr(&ctrl->error, kErrNoEdge);
-            return;
+        if (root) {
+            ++roots;
+            ub[c] = kInfBits;
+            compkey[c] = kKeyMax;
+            compmax[c] = kNone;
+        } else {
+            // a component id stops being one once it is merged, so every id
+            // emits at most once over the whole run: its slot is its own
+            ++emitted;
+            const uint64_t key = compkey[c];
+            eu[c] = (uint32_t)(key & 0xFFFFFFFFu);
+            ev[c] = compmax[c];
+            ed[c] = (uint32_t)(key >> 32);
         }
-        const uint64_t key = compkey[c];
-        eu[slot] = (uint32_t)(key & 0xFFFFFFFFu);
-        ev[slot] = compmax[c];
-        ed[slot] = (uint32_t)(key >> 32);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        roots += __shfl_xor(roots, off);
+        emitted += __shfl_xor(emitted, off);
+    }
+    if (lane_id() == 0) {
+        if (roots) atomicAdd(&s_cnt[0], roots);
+        if (emitted) atomicAdd(&s_cnt[1], emitted);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_cnt[0]) atomicAdd(&ctrl->ncomp_next, s_cnt[0]);
+        if (s_cnt[1]) atomicAdd(&ctrl->edge_count, s_cnt[1]);
     }
 }
 
@@ -543,8 +558,7 @@ __global__ __launch_bounds__(256) void k_edge_write(const uint32_t* __restrict__
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, node_parent, exch, boxacc, rlo, rhi, run_start,
-        run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, node_parent, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -570,7 +584,6 @@ static Layout make_layout(int64_t n, int dim) {
     L.recs = take(M * (dim == 3 ? sizeof(Rec<3>) : sizeof(Rec<2>)));
     L.node_parent = take(4 * M);
     L.exch = take(8 * M);
-    L.boxacc = take(4 * 2 * (size_t)dim * M);
     L.rlo = take(4 * M);
     L.rhi = take(4 * M);
     L.run_start = take(4 * N);
@@ -719,7 +732,6 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     Rec<DIM>* recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
     uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
-    uint32_t* boxacc = reinterpret_cast<uint32_t*>(ws + L.boxacc);
     uint32_t* rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
     uint32_t* rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
     uint32_t* run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
@@ -791,9 +803,8 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     const uint32_t* perm = in1 ? v1 : v0;
     // ---- hierarchy + boxes
     k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, spts, orig, pos, labels, ub, compkey, compmax, exch,
-                                               boxacc);
-    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, node_parent, exch, boxacc, rlo, rhi,
-                                              ctrl);
+                                               eu, ev, ed);
+    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, node_parent, exch, rlo, rhi, ctrl);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -806,20 +817,23 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     // ---- Boruvka rounds
     TraverseArgs<DIM> ta;
     ta.spts = spts; ta.labels = labels; ta.orig = orig; ta.ub = ub; ta.recs = recs; ta.root = root; ta.n = n;
-    ta.cand_d = cand_d; ta.cand_j = cand_j; ta.compkey = compkey; ta.ctrl = ctrl;
+    ta.cand_d = cand_d; ta.cand_j = cand_j; ta.compkey = compkey; ta.compmax = compmax; ta.ctrl = ctrl;
     int64_t ncomp = n;
     int round = 0;
     while (ncomp > 1) {
         if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
         S.components[round] = ncomp;
         HIP_TRY(propagate_labels<DIM>(labels, run_start, run_part, rlo, rhi, recs, n, st));
-        k_bounds<DIM><<<grid_for(n), 256, 0, st>>>(spts, labels, n, ub, ctrl);
+        if (round == 0) k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(spts, labels, n, ub, ctrl);
+        else k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(spts, labels, n, ub, ctrl);
         if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
+        ta.first = round == 0;
         HIP_TRY(launch_traverse<DIM>(ta, S.tree_height, ctx->traversal, ctx->counting, st));
         if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
-        k_resolve<<<grid_for(n), 256, 0, st>>>(cand_d, cand_j, labels, orig, compkey, compmax, n);
+        if (round > 0) k_resolve<<<grid_for(n), 256, 0, st>>>(cand_d, cand_j, labels, orig, compkey, compmax, n);
         k_merge_succ<<<grid_for(n), 256, 0, st>>>(labels, pos, compkey, compmax, succ, ctrl, n);
-        k_merge_parent<<<grid_for(n), 256, 0, st>>>(labels, succ, par, compkey, compmax, ub, eu, ev, ed, ctrl, n);
+        k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(labels, succ, par, compkey, compmax,
+                                                                              ub, eu, ev, ed, ctrl, n);
         HIP_TRY(hipGetLastError());
         k_merge_jump<<<grid_for(n), 256, 0, st>>>(labels, par, n, 1024);
         k_relabel<<<grid_for(n), 256, 0, st>>>(labels, par, n, 4096, ctrl);
@@ -848,20 +862,22 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
 
     // ---- canonical order: by (u, v) first, then stably by D bits
+    // n slots, one per component id; the final root's slot is empty and its
+    // key (all ones) sorts after every edge
     const int64_t m = n - 1;
-    k_edge_keys<<<grid_for(m), 256, 0, st>>>(eu, ev, m, k0, v0);
+    k_edge_keys<<<grid_for(n), 256, 0, st>>>(eu, ev, n, k0, v0);
     int sh[16], q = 0;
     const int ib = 32 - __builtin_clz((unsigned)(n - 1));  // bits of the largest index
     for (int s = 0; s < ib; s += 8) sh[q++] = s;
     for (int s = 0; s < ib; s += 8) sh[q++] = 32 + s;
-    HIP_TRY(radix_sort_pairs(st, k0, v0, k1, v1, hist, m, sh, q, &in1));
+    HIP_TRY(radix_sort_pairs(st, k0, v0, k1, v1, hist, n, sh, q, &in1));
     uint32_t* p1 = in1 ? v1 : v0;
     uint64_t* kd = in1 ? k1 : k0;
     uint64_t* kd_alt = in1 ? k0 : k1;
     uint32_t* p1_alt = in1 ? v0 : v1;
-    k_edge_dkeys<<<grid_for(m), 256, 0, st>>>(ed, p1, m, kd);
+    k_edge_dkeys<<<grid_for(n), 256, 0, st>>>(ed, p1, n, kd);
     const int dsh[4] = {0, 8, 16, 24};
-    HIP_TRY(radix_sort_pairs(st, kd, p1, kd_alt, p1_alt, hist, m, dsh, 4, &in1));
+    HIP_TRY(radix_sort_pairs(st, kd, p1, kd_alt, p1_alt, hist, n, dsh, 4, &in1));
     const uint32_t* pfin = in1 ? p1_alt : p1;
     k_edge_write<<<grid_for(m), 256, 0, st>>>(eu, ev, ed, pfin, m, edges, weights, d2);
     HIP_TRY(hipGetLastError());
@@ -911,20 +927,13 @@ namespace emst {
 
 __global__ __launch_bounds__(256) void k_test_prep(const uint32_t* __restrict__ leaf_labels, int64_t n,
                                                    float* __restrict__ spts, uint32_t* __restrict__ orig,
-                                                   uint32_t* __restrict__ labels, uint64_t* __restrict__ exch,
-                                                   uint32_t* __restrict__ boxacc) {
+                                                   uint32_t* __restrict__ labels, uint64_t* __restrict__ exch) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     spts[3 * i] = spts[3 * i + 1] = spts[3 * i + 2] = 0.f;
     orig[i] = (uint32_t)i;
     labels[i] = leaf_labels[i];
-    if (i + 1 < n) {
-        exch[i] = ~0ull;
-        for (int k = 0; k < 3; ++k) {
-            boxacc[i * 6 + k] = 0xFFFFFFFFu;
-            boxacc[i * 6 + 3 + k] = 0u;
-        }
-    }
+    if (i + 1 < n) exch[i] = ~0ull;
 }
 
 __global__ __launch_bounds__(256) void k_test_extract(const Rec<3>* __restrict__ recs,
@@ -968,7 +977,6 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint32_t* orig = reinterpret_cast<uint32_t*>(ws + L.orig);
     uint32_t* labels = reinterpret_cast<uint32_t*>(ws + L.labels);
     uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
-    uint32_t* boxacc = reinterpret_cast<uint32_t*>(ws + L.boxacc);
     uint32_t* rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
     uint32_t* rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
     uint32_t* run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
@@ -976,8 +984,8 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     Rec<3>* recs = reinterpret_cast<Rec<3>*>(ws + L.recs);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
     k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
-    k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch, boxacc);
-    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, node_parent, exch, boxacc, rlo, rhi, ctrl);
+    k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch);
+    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, node_parent, exch, rlo, rhi, ctrl);
     HIP_TRY(propagate_labels<3>(labels, run_start, run_part, rlo, rhi, recs, n, st));
     k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, node_parent, n - 1, d_left, d_right, d_label);
     HIP_TRY(hipGetLastError());

@@ -88,6 +88,41 @@ __device__ __forceinline__ void store_child_box<2>(Rec<2>* r, int side, const fl
     reinterpret_cast<uint32_t*>(r)[8 + 2 * side + 1] = ref;
 }
 
+// The same two operations with device-scope (agent) relaxed atomic stores
+// and loads, which are coherent across the XCDs' L2 caches without any
+// cache-wide writeback or invalidation.
+__device__ __forceinline__ void store_coherent(float* p, float v) {
+    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float load_coherent(const float* p) {
+    return __uint_as_float(__hip_atomic_load(reinterpret_cast<uint32_t*>(const_cast<float*>(p)), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
+}
+
+template <int DIM>
+__device__ __forceinline__ void store_child_box_coherent(Rec<DIM>* r, int side, const float* lo, const float* hi,
+                                                         uint32_t ref) {
+    float* f = reinterpret_cast<float*>(r) + (DIM == 3 ? 8 : 4) * side;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        store_coherent(f + k, lo[k]);
+        store_coherent(f + (DIM == 3 ? 4 : 2) + k, hi[k]);
+    }
+    if (DIM == 3) f[7] = __uint_as_float(ref);
+    else reinterpret_cast<uint32_t*>(r)[8 + 2 * side + 1] = ref;
+}
+
+template <int DIM>
+__device__ __forceinline__ void load_child_box_coherent(const Rec<DIM>* r, int side, float* lo, float* hi) {
+    const float* f = reinterpret_cast<const float*>(r) + (DIM == 3 ? 8 : 4) * side;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        lo[k] = load_coherent(f + k);
+        hi[k] = load_coherent(f + (DIM == 3 ? 4 : 2) + k);
+    }
+}
+
 template <int DIM>
 __device__ __forceinline__ uint32_t* label_slot(Rec<DIM>* r, int side);
 
@@ -153,12 +188,6 @@ __device__ __forceinline__ float boxdist(const float* p, const float* lo, const 
 // ---------------------------------------------------------------------------
 // atomics with explicit scope / ordering
 
-__device__ __forceinline__ uint64_t atomic_xchg_acqrel(uint64_t* p, uint64_t v) {
-    return __hip_atomic_exchange(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t atomic_add_acqrel(uint32_t* p, uint32_t v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
     return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -167,5 +196,24 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Segmented inclusive min-scan over the lanes of a wave, segments = runs of
+// equal `lab` in lane order.  Lanes only ever combine values carrying the
+// same label, and the last lane of a run ends up with the minimum of the
+// whole run; *run_end tells whether this lane is that last lane.  Every lane
+// of the wave must call it.
+template <typename T>
+__device__ __forceinline__ T wave_seg_min(uint32_t lab, T v, bool* run_end) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t ol = __shfl_up(lab, off);
+        const T ov = __shfl_up(v, off);
+        if (lane >= off && ol == lab && ov < v) v = ov;
+    }
+    const uint32_t next = __shfl_down(lab, 1);
+    *run_end = (lane == 63) || (next != lab);
+    return v;
+}
 
 }  // namespace emst

@@ -36,7 +36,9 @@ struct TraverseArgs {
     uint32_t* cand_d;
     uint32_t* cand_j;
     uint64_t* compkey;
+    uint32_t* compmax;
     Ctrl* ctrl;
+    bool first;  // first round: every point is its own component
 };
 
 // Candidate order of Algorithm 2's leaf update, made strict: (D, j).
@@ -59,20 +61,33 @@ __device__ __forceinline__ void flush_counts(Ctrl* ctrl, uint64_t internal, uint
     }
 }
 
+// Stage A of the component minimum.  In the first round the point is the
+// whole component, so it writes the component's key (and, being the only
+// candidate, its max index) directly.  Later the queries of a run of equal
+// labels within the wave combine first and one lane per run updates the
+// component with a 64-bit atomicMin.  Every lane of the wave must call it.
 template <int DIM>
 __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t i, uint32_t c, float best_d,
                                              uint32_t best_j) {
-    const uint32_t oi = a.orig[i];
-    if (best_j == kNone) {
-        a.cand_d[i] = kNone;
-        a.cand_j[i] = kNone;
-        return;
+    const bool valid = i < a.n;
+    const bool found = valid && best_j != kNone;
+    uint64_t key = kKeyMax;
+    if (valid) {
+        const uint32_t oi = a.orig[i];
+        const uint32_t db = found ? fbits(best_d) : kNone;
+        a.cand_d[i] = db;
+        a.cand_j[i] = best_j;
+        if (found) key = ((uint64_t)db << 32) | (uint64_t)min(oi, best_j);
+        if (a.first) {
+            a.compkey[c] = key;
+            a.compmax[c] = found ? max(oi, best_j) : kNone;
+        }
     }
-    const uint32_t db = fbits(best_d);
-    a.cand_d[i] = db;
-    a.cand_j[i] = best_j;
-    const uint64_t key = ((uint64_t)db << 32) | (uint64_t)min(oi, best_j);
-    if (key < load_relaxed64(&a.compkey[c])) atomicMin((unsigned long long*)&a.compkey[c], (unsigned long long)key);
+    if (a.first) return;
+    bool run_end;
+    key = wave_seg_min<uint64_t>(valid ? c : kNone, key, &run_end);
+    if (valid && run_end && key != kKeyMax && key < load_relaxed64(&a.compkey[c]))
+        atomicMin((unsigned long long*)&a.compkey[c], (unsigned long long)key);
 }
 
 // ---------------------------------------------------------------------------
@@ -82,6 +97,8 @@ template <int DIM, int STACK, bool COUNT>
 __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
+    uint32_t c_out = kNone, bj_out = kNone;
+    float bd_out = INFINITY;
     if (i < a.n) {
         float p[DIM];
 #pragma unroll
@@ -148,8 +165,11 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
                 if (!found) break;
             }
         }
-        finish_query<DIM>(a, i, c, best_d, best_j);
+        c_out = c;
+        bd_out = best_d;
+        bj_out = best_j;
     }
+    finish_query<DIM>(a, i, c_out, bd_out, bj_out);
     flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
 }
 
@@ -260,7 +280,7 @@ __global__ __launch_bounds__(256) void k_traverse_wave(TraverseArgs<DIM> a) {
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (valid) finish_query<DIM>(a, i, c, best_d, best_j);
+    finish_query<DIM>(a, i, c, best_d, best_j);
     flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
 }
 
