@@ -129,9 +129,15 @@ int emst_set_profiling(emst_ctx *ctx, int on);
  * distance evaluations (same result, slower; off by default). */
 int emst_set_counting(emst_ctx *ctx, int on);
 
-/* Traversal variant: 0 = one lane per query with a per-lane stack,
- * 1 = wavefront-cooperative (the 64 Morton-ordered queries of a wave walk
- * the tree together).  Results are identical; the default is the faster one. */
+/* Traversal launch shape.  All compute the same result:
+ *   0  one lane per query, top-down from the root, stack in private memory
+ *   1  wavefront-cooperative: the 64 Morton-ordered queries of a wave walk
+ *      the union of their paths with one node load per wave
+ *   2  one lane per query, walking up from the query's own leaf and stopping
+ *      at the first ancestor whose Morton cell holds the search ball
+ *   3, 4  as 0 and 2 on persistent waves that refill finished lanes
+ *   5  as 0 with a branch-free inner loop and an LDS stack (default)
+ *   6  as 2 with the loop of 5 */
 int emst_set_traversal(emst_ctx *ctx, int variant);
 
 int emst_get_stats(const emst_ctx *ctx, emst_stats *out);

@@ -79,7 +79,7 @@ __global__ void k_init_ctrl(Ctrl* ctrl) {
         ctrl->nonfinite = 0; ctrl->root = kNone; ctrl->height = 0;
         ctrl->ncomp_next = 0; ctrl->edge_count = 0; ctrl->error = 0;
         ctrl->key_or = 0ull; ctrl->key_and = ~0ull;
-        ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0;
+        ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0; ctrl->trav_next = 0;
     }
 }
 
@@ -201,8 +201,8 @@ __device__ __forceinline__ int split_bit(const uint64_t* __restrict__ codes, int
 template <int DIM>
 __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ codes,
                                                const uint32_t* __restrict__ orig, const float* __restrict__ spts,
-                                               int64_t n, Rec<DIM>* recs, uint32_t* __restrict__ node_parent,
-                                               uint64_t* exch,
+                                               int64_t n, Rec<DIM>* recs, uint32_t* __restrict__ leaf_parent,
+                                               uint32_t* __restrict__ node_parent, uint64_t* exch,
                                                uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi, Ctrl* ctrl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -227,7 +227,8 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         const uint32_t parent = (uint32_t)(left_child ? r : l - 1);
         const int side = left_child ? 0 : 1;
         store_child_box_coherent<DIM>(&recs[parent], side, lo, hi, self_ref);
-        if (!leaf) node_parent[self] = (parent << 1) | (uint32_t)side;
+        if (leaf) leaf_parent[i] = (parent << 1) | (uint32_t)side;
+        else node_parent[self] = (parent << 1) | (uint32_t)side;
         // the box is stored before the exchange is issued
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
@@ -256,6 +257,68 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
             return;
         }
     }
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10C30C30C30C30C3ull;
+    x = (x ^ (x >> 4)) & 0x100F00F00F00F00Full;
+    x = (x ^ (x >> 8)) & 0x1F0000FF0000FFull;
+    x = (x ^ (x >> 16)) & 0x1F00000000FFFFull;
+    x = (x ^ (x >> 32)) & 0x1FFFFFull;
+    return (uint32_t)x;
+}
+__device__ __forceinline__ uint32_t compact2(uint64_t x) {
+    x &= 0x5555555555555555ull;
+    x = (x ^ (x >> 1)) & 0x3333333333333333ull;
+    x = (x ^ (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x ^ (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x ^ (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x ^ (x >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)x;
+}
+
+// Morton cell of every internal node.  A node that splits on a code bit t
+// holds exactly the points whose codes agree with its leaves above bit t, so
+// its cell is the box of quantised coordinates with those bits fixed.  In
+// real coordinates the cell is [lo + Q/scale, lo + (Q + 2^m)/scale) per
+// axis (m = free low bits of that axis); the stored box is shrunk by a
+// margin far above every rounding in the quantisation, so any point inside
+// the stored box has codes with the node's prefix.  Axes at the scene edge
+// stay open, nodes that split equal codes get an empty cell.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_cells(const uint64_t* __restrict__ codes,
+                                               const uint32_t* __restrict__ node_parent, int64_t m,
+                                               MortonParams mp, Up* __restrict__ up) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const uint64_t x = codes[k] ^ codes[k + 1];
+    if (x) {
+        const int t = 63 - __clzll(x);  // highest differing code bit = the node's split bit
+        const uint64_t code = codes[k];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const int off = DIM - 1 - d;   // bit offset of axis d inside a Morton digit
+            const uint32_t q = (DIM == 3) ? compact3(code >> off) : compact2(code >> off);
+            const int free_bits = (t >= off) ? (t - off) / DIM + 1 : 0;
+            if (mp.scale[d] <= 0.0) {
+                clo[d] = -INFINITY;
+                chi[d] = INFINITY;
+                continue;
+            }
+            const double Q = (double)(free_bits >= 32 ? 0u : (q >> free_bits) << free_bits);
+            const double W = (double)(1ull << free_bits);
+            const double ext = mp.qmax / mp.scale[d];
+            const double margin = 1e-6 * (fabs(mp.lo[d]) + ext);
+            clo[d] = (Q <= 0.0) ? -INFINITY : (float)(mp.lo[d] + Q / mp.scale[d] + margin);
+            chi[d] = (Q + W > mp.qmax) ? INFINITY : (float)(mp.lo[d] + (Q + W) / mp.scale[d] - margin);
+        }
+    }
+    Up u;
+    u.a = make_float4(clo[0], clo[1], clo[2], __uint_as_float(node_parent[k]));
+    u.b = make_float4(chi[0], chi[1], chi[2], 0.f);
+    up[k] = u;
 }
 
 // ===========================================================================
@@ -367,7 +430,10 @@ template <int DIM, bool FIRST>
 __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, const uint32_t* __restrict__ labels,
                                                 int64_t n, uint32_t* ub, Ctrl* ctrl) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0) ctrl->ncomp_next = 0u;
+    if (k == 0) {
+        ctrl->ncomp_next = 0u;
+        ctrl->trav_next = 0ull;
+    }
     uint32_t lab = kNone, v = kInfBits;
     if (k < n) {
         lab = labels[k];
@@ -558,7 +624,7 @@ __global__ __launch_bounds__(256) void k_edge_write(const uint32_t* __restrict__
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, node_parent, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -583,6 +649,8 @@ static Layout make_layout(int64_t n, int dim) {
     L.pos = take(4 * N);
     L.recs = take(M * (dim == 3 ? sizeof(Rec<3>) : sizeof(Rec<2>)));
     L.node_parent = take(4 * M);
+    L.leaf_parent = take(4 * N);
+    L.up = take(sizeof(Up) * M);
     L.exch = take(8 * M);
     L.rlo = take(4 * M);
     L.rhi = take(4 * M);
@@ -615,7 +683,7 @@ struct emst_ctx {
     std::string err;
     bool profiling = false;
     bool counting = false;
-    int traversal = 0;
+    int traversal = 5;
     emst_stats stats;
     Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
     hipEvent_t ev[2 * 64 + 8];
@@ -687,7 +755,7 @@ extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
     return EMST_OK;
 }
 extern "C" int emst_set_traversal(emst_ctx* ctx, int variant) {
-    if (!ctx || variant < 0 || variant > 1) return EMST_EINVAL;
+    if (!ctx || variant < 0 || variant > 6) return EMST_EINVAL;
     ctx->traversal = variant;
     return EMST_OK;
 }
@@ -731,6 +799,8 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     uint32_t* pos = reinterpret_cast<uint32_t*>(ws + L.pos);
     Rec<DIM>* recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
+    uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
+    Up* up = reinterpret_cast<Up*>(ws + L.up);
     uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
     uint32_t* rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
     uint32_t* rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
@@ -804,7 +874,8 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     // ---- hierarchy + boxes
     k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, spts, orig, pos, labels, ub, compkey, compmax, exch,
                                                eu, ev, ed);
-    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, node_parent, exch, rlo, rhi, ctrl);
+    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, leaf_parent, node_parent, exch, rlo, rhi,
+                                              ctrl);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -812,12 +883,15 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     S.tree_height = (int32_t)ctx->h_ctrl->height;
     if (root == kNone || root >= (uint32_t)(n - 1) || ctx->h_ctrl->error)
         return fail(ctx, EMST_EINTERNAL, "tree construction failed");
+    k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, node_parent, n - 1, mp, up);
+    HIP_TRY(hipGetLastError());
     if (prof) HIP_TRY(hipEventRecord(E[1], st));
 
     // ---- Boruvka rounds
     TraverseArgs<DIM> ta;
     ta.spts = spts; ta.labels = labels; ta.orig = orig; ta.ub = ub; ta.recs = recs; ta.root = root; ta.n = n;
     ta.cand_d = cand_d; ta.cand_j = cand_j; ta.compkey = compkey; ta.compmax = compmax; ta.ctrl = ctrl;
+    ta.leaf_parent = leaf_parent; ta.up = up;
     int64_t ncomp = n;
     int round = 0;
     while (ncomp > 1) {
@@ -983,9 +1057,11 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint32_t* run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
     Rec<3>* recs = reinterpret_cast<Rec<3>*>(ws + L.recs);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
+    uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
     k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
     k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch);
-    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, node_parent, exch, rlo, rhi, ctrl);
+    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, leaf_parent, node_parent, exch, rlo, rhi,
+                                            ctrl);
     HIP_TRY(propagate_labels<3>(labels, run_start, run_part, rlo, rhi, recs, n, st));
     k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, node_parent, n - 1, d_left, d_right, d_label);
     HIP_TRY(hipGetLastError());

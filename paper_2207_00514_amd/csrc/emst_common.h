@@ -39,6 +39,16 @@ template <> struct alignas(16) Rec<2> {
 static_assert(sizeof(Rec<3>) == 64, "3D record is 64 bytes");
 static_assert(sizeof(Rec<2>) == 48, "2D record is 48 bytes");
 
+// Upward-walk metadata of an internal node (32 B): the node's Morton cell
+// shrunk by a safety margin (every point whose coordinates lie inside it is
+// a leaf of the node; an empty cell, lo = +inf, for nodes that split equal
+// codes by index), and the link to its parent ((parent << 1) | side, or
+// kNone at the root).
+struct alignas(16) Up {
+    float4 a;  // cell lo x, y, z, parent link (bits)
+    float4 b;  // cell hi x, y, z, unused
+};
+
 template <int DIM> struct Child {
     float lo[DIM], hi[DIM];
     uint32_t lab, ref;
@@ -67,6 +77,25 @@ __device__ __forceinline__ void unpack<2>(const Rec<2>& r, Child<2>& c0, Child<2
 
 // Write the box and reference of child `side` of record r (labels are
 // written separately, every round).
+template <int DIM>
+__device__ __forceinline__ void load_child(const Rec<DIM>* r, int side, Child<DIM>& c);
+
+template <>
+__device__ __forceinline__ void load_child<3>(const Rec<3>* r, int side, Child<3>& c) {
+    const float4* f = reinterpret_cast<const float4*>(r) + 2 * side;
+    const float4 u = f[0], v = f[1];
+    c.lo[0] = u.x; c.lo[1] = u.y; c.lo[2] = u.z; c.lab = fbits(u.w);
+    c.hi[0] = v.x; c.hi[1] = v.y; c.hi[2] = v.z; c.ref = fbits(v.w);
+}
+
+template <>
+__device__ __forceinline__ void load_child<2>(const Rec<2>* r, int side, Child<2>& c) {
+    const float4 u = reinterpret_cast<const float4*>(r)[side];
+    const uint2 m = reinterpret_cast<const uint2*>(r)[4 + side];
+    c.lo[0] = u.x; c.lo[1] = u.y; c.hi[0] = u.z; c.hi[1] = u.w;
+    c.lab = m.x; c.ref = m.y;
+}
+
 template <int DIM>
 __device__ __forceinline__ void store_child_box(Rec<DIM>* r, int side, const float* lo, const float* hi,
                                                 uint32_t ref);
@@ -196,6 +225,17 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// gfx950 hands workgroups to its 8 XCDs round-robin (workgroup w runs on
+// XCD w % 8), and every XCD has its own L2.  For a grid whose size is a
+// multiple of 8 this maps the hardware workgroup id to a logical one so
+// that each XCD sweeps one contiguous eighth of the logical range: queries
+// that are neighbours in Morton order then share one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t hw, int64_t grid) {
+    const int64_t per = grid / kXcds;
+    return (hw % kXcds) * per + hw / kXcds;
+}
 
 // Segmented inclusive min-scan over the lanes of a wave, segments = runs of
 // equal `lab` in lane order.  Lanes only ever combine values carrying the

@@ -21,7 +21,8 @@ struct Ctrl {
     unsigned long long internal_tests;
     unsigned long long leaf_tests;
     unsigned long long dist_evals;
-    uint32_t pad[8];
+    unsigned long long trav_next;   // next query handed out by the persistent traversal
+    uint32_t pad[6];
 };
 
 constexpr uint32_t kErrStack = 1u;

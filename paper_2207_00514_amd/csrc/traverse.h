@@ -11,8 +11,14 @@
 // against the radius when it is taken back.  At the end the point offers
 // (D bits, min(orig i, orig j)) to its component with a 64-bit atomicMin.
 //
-// Two launch shapes compute the same result:
+// Three launch shapes compute the same result:
 //   variant 0  one lane per query, private stack (nearer child first);
+//   variant 2  one lane per query, walking UP from the query's own leaf:
+//              at every ancestor the other child's subtree is searched
+//              top-down as in variant 0, and the walk stops at the first
+//              ancestor whose Morton cell contains the ball of the current
+//              radius (every point within the radius is then a leaf of that
+//              ancestor, all of which have been searched);
 //   variant 1  wavefront-cooperative: the 64 Morton-adjacent queries of a
 //              wave walk the tree together, the wave visits a node if any of
 //              its lanes needs it, node records are read once per wave
@@ -39,6 +45,8 @@ struct TraverseArgs {
     uint32_t* compmax;
     Ctrl* ctrl;
     bool first;  // first round: every point is its own component
+    const uint32_t* leaf_parent;
+    const Up* up;
 };
 
 // Candidate order of Algorithm 2's leaf update, made strict: (D, j).
@@ -93,27 +101,117 @@ __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t
 // ---------------------------------------------------------------------------
 // variant 0: one lane per query
 
+// Top-down search of the subtree below internal node `node` (nearer child
+// first, deferred children re-checked against the radius when popped).
+template <int DIM, int STACK, bool COUNT>
+__device__ __forceinline__ void descend(const TraverseArgs<DIM>& a, uint32_t node, const float* p, uint32_t c,
+                                        float& radius, float& best_d, uint32_t& best_j, uint64_t& n_int,
+                                        uint64_t& n_leaf, uint64_t& n_eval) {
+    uint32_t st_node[STACK];
+    float st_d[STACK];
+    int sp = 0;
+    // a search visits every internal node at most once
+    for (int64_t guard = 0;; ++guard) {
+        if (guard >= a.n) {
+            atomicOr(&a.ctrl->error, kErrStack);
+            return;
+        }
+        const Rec<DIM> r = a.recs[node];
+        Child<DIM> ch[2];
+        unpack<DIM>(r, ch[0], ch[1]);
+        bool go[2] = {false, false};
+        float dd[2] = {0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const bool leaf = (ch[s].ref & kLeafFlag) != 0u;
+            if (COUNT) { if (leaf) ++n_leaf; else ++n_int; }
+            if (ch[s].lab == c) continue;
+            const float d = boxdist<DIM>(p, ch[s].lo, ch[s].hi);
+            if (COUNT && leaf) ++n_eval;
+            if (d > radius) continue;
+            if (leaf) {
+                const uint32_t j = ch[s].ref & ~kLeafFlag;
+                if (better(d, j, best_d, best_j)) { best_d = d; best_j = j; radius = d; }
+            } else {
+                go[s] = true;
+                dd[s] = d;
+            }
+        }
+        if (go[0] && go[1]) {
+            const int near = (dd[1] < dd[0]) ? 1 : 0;
+            if (sp >= STACK) {
+                atomicOr(&a.ctrl->error, kErrStack);
+                return;
+            }
+            st_node[sp] = ch[1 - near].ref;
+            st_d[sp] = dd[1 - near];
+            ++sp;
+            node = ch[near].ref;
+        } else if (go[0]) {
+            node = ch[0].ref;
+        } else if (go[1]) {
+            node = ch[1].ref;
+        } else {
+            bool found = false;
+            while (sp > 0) {
+                --sp;
+                if (st_d[sp] <= radius) {
+                    node = st_node[sp];
+                    found = true;
+                    break;
+                }
+            }
+            if (!found) return;
+        }
+    }
+}
+
 template <int DIM, int STACK, bool COUNT>
 __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
-    uint32_t c_out = kNone, bj_out = kNone;
-    float bd_out = INFINITY;
+    uint32_t c = kNone, best_j = kNone;
+    float best_d = INFINITY;
     if (i < a.n) {
         float p[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
-        const uint32_t c = a.labels[i];
+        c = a.labels[i];
         float radius = bitsf(a.ub[c]);
-        float best_d = INFINITY;
-        uint32_t best_j = kNone;
+        descend<DIM, STACK, COUNT>(a, a.root, p, c, radius, best_d, best_j, n_int, n_leaf, n_eval);
+    }
+    finish_query<DIM>(a, i, c, best_d, best_j);
+    flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
+}
+
+// ---------------------------------------------------------------------------
+// variant 2: upward walk from the query's leaf with the Morton-cell stop
+
+template <int DIM, int STACK, bool COUNT>
+__global__ __launch_bounds__(256) void k_traverse_up(TraverseArgs<DIM> a) {
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
+    uint32_t c = kNone, best_j = kNone;
+    float best_d = INFINITY;
+    if (i < a.n) {
+        float p[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
+        c = a.labels[i];
+        float radius = bitsf(a.ub[c]);
         uint32_t st_node[STACK];
         float st_d[STACK];
         int sp = 0;
-        uint32_t node = a.root;
-        // a query visits every internal node at most once
+        // One flat loop; every iteration processes one record.  Climbing,
+        // the record is the current ancestor's and only the child off the
+        // walked path is tested (mask); descending, both children are.
+        uint32_t link = a.leaf_parent[i];
+        uint32_t anc = link >> 1;              // current ancestor
+        uint32_t node = anc;                   // record processed next
+        uint32_t mask = 2u >> (link & 1u);     // child 1 - side
+        Up u = a.up[anc];                      // cell + parent of the ancestor, loaded with its record
         for (int64_t guard = 0;; ++guard) {
-            if (guard >= a.n) {
+            if (guard >= 2 * a.n + 128) {
                 atomicOr(&a.ctrl->error, kErrStack);
                 break;
             }
@@ -124,6 +222,7 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
             float dd[2] = {0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
+                if (!((mask >> s) & 1u)) continue;
                 const bool leaf = (ch[s].ref & kLeafFlag) != 0u;
                 if (COUNT) { if (leaf) ++n_leaf; else ++n_int; }
                 if (ch[s].lab == c) continue;
@@ -138,6 +237,7 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
                     dd[s] = d;
                 }
             }
+            mask = 3u;
             if (go[0] && go[1]) {
                 const int near = (dd[1] < dd[0]) ? 1 : 0;
                 if (sp >= STACK) {
@@ -148,28 +248,42 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
                 st_d[sp] = dd[1 - near];
                 ++sp;
                 node = ch[near].ref;
-            } else if (go[0]) {
-                node = ch[0].ref;
-            } else if (go[1]) {
-                node = ch[1].ref;
-            } else {
-                bool found = false;
-                while (sp > 0) {
-                    --sp;
-                    if (st_d[sp] <= radius) {
-                        node = st_node[sp];
-                        found = true;
-                        break;
-                    }
-                }
-                if (!found) break;
+                continue;
             }
+            if (go[0] || go[1]) {
+                node = go[0] ? ch[0].ref : ch[1].ref;
+                continue;
+            }
+            bool found = false;
+            while (sp > 0) {
+                --sp;
+                if (st_d[sp] <= radius) {
+                    node = st_node[sp];
+                    found = true;
+                    break;
+                }
+            }
+            if (found) continue;
+            // The subtree off the path at `anc` is done, so every leaf of
+            // `anc` has been searched.  A candidate j with D(p, j) <= radius
+            // lies within sqrt(radius) (1 + 2^-22) of p on every axis, or
+            // within ~5e-23 where squares underflow; r covers both and the
+            // rounding of sqrtf.  If that ball lies in the Morton cell of
+            // `anc`, every candidate is a leaf of `anc`: stop.
+            const float rr = sqrtf(radius) * 1.000001f + 1e-22f;
+            bool inside = (p[0] - rr >= u.a.x) && (p[0] + rr <= u.b.x);
+            if (DIM > 1) inside = inside && (p[1 % DIM] - rr >= u.a.y) && (p[1 % DIM] + rr <= u.b.y);
+            if (DIM > 2) inside = inside && (p[2 % DIM] - rr >= u.a.z) && (p[2 % DIM] + rr <= u.b.z);
+            if (inside) break;
+            link = fbits(u.a.w);
+            if (link == kNone) break;
+            anc = link >> 1;
+            node = anc;
+            mask = 2u >> (link & 1u);
+            u = a.up[anc];
         }
-        c_out = c;
-        bd_out = best_d;
-        bj_out = best_j;
     }
-    finish_query<DIM>(a, i, c_out, bd_out, bj_out);
+    finish_query<DIM>(a, i, c, best_d, best_j);
     flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
 }
 
@@ -183,7 +297,7 @@ __global__ __launch_bounds__(256) void k_traverse_wave(TraverseArgs<DIM> a) {
     __shared__ uint64_t s_mask[W][STACK];
     __shared__ float s_box[W][STACK][2 * DIM];
     const int w = threadIdx.x / 64, lane = lane_id();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool valid = i < a.n;
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
     float p[DIM];
@@ -285,13 +399,340 @@ __global__ __launch_bounds__(256) void k_traverse_wave(TraverseArgs<DIM> a) {
 }
 
 // ---------------------------------------------------------------------------
+// variants 3 and 4: persistent waves with per-lane refill
+//
+// A query's cost varies a lot (how far its walk climbs, how many subtrees it
+// opens), and a wave runs as long as its slowest lane.  Here a wave takes
+// chunks of consecutive (Morton-ordered) queries and a lane that finishes
+// takes the next query of the chunk at once, so lanes stay busy until the
+// queue is empty.  Variant 3 searches top-down from the root (as variant 0),
+// variant 4 walks up from the query's leaf (as variant 2).
+
+template <int DIM>
+__device__ __forceinline__ void finish_one(const TraverseArgs<DIM>& a, int64_t i, uint32_t c, float best_d,
+                                           uint32_t best_j) {
+    const uint32_t oi = a.orig[i];
+    const bool found = best_j != kNone;
+    const uint32_t db = found ? fbits(best_d) : kNone;
+    a.cand_d[i] = db;
+    a.cand_j[i] = best_j;
+    const uint64_t key = found ? (((uint64_t)db << 32) | (uint64_t)min(oi, best_j)) : kKeyMax;
+    if (a.first) {
+        a.compkey[c] = key;
+        a.compmax[c] = found ? max(oi, best_j) : kNone;
+    } else if (found && key < load_relaxed64(&a.compkey[c])) {
+        atomicMin((unsigned long long*)&a.compkey[c], (unsigned long long)key);
+    }
+}
+
+template <int DIM, int STACK, bool COUNT, bool UPWARD>
+__global__ __launch_bounds__(256) void k_traverse_pool(TraverseArgs<DIM> a) {
+    constexpr int64_t kChunk = 512;
+    const int lane = lane_id();
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
+    int64_t cpos = 0, cend = 0;    // wave-uniform: the current chunk of queries
+    bool drained = false;          // wave-uniform: no chunk left
+    bool active = false;
+    int64_t i = 0;
+    float p[DIM];
+    uint32_t c = kNone, best_j = kNone, anc = 0, node = 0, mask = 3u;
+    float radius = 0.f, best_d = INFINITY;
+    uint32_t st_node[STACK];
+    float st_d[STACK];
+    int sp = 0;
+    int64_t steps = 0;
+    Up u;
+    u.a = u.b = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) p[k] = 0.f;
+    while (true) {
+        // ---- refill idle lanes from the chunk
+        const uint64_t idle = __ballot(!active);
+        if (idle && !drained) {
+            if (cpos >= cend) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(&a.ctrl->trav_next, (unsigned long long)kChunk);
+                base = __shfl(base, 0);
+                cpos = (int64_t)base;
+                cend = min((int64_t)base + kChunk, a.n);
+                drained = cpos >= a.n;
+            }
+            if (!drained) {
+                const int64_t take = min((int64_t)__popcll(idle), cend - cpos);
+                const int64_t rank = __popcll(idle & lt);
+                if (!active && rank < take) {
+                    i = cpos + rank;
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
+                    c = a.labels[i];
+                    radius = bitsf(a.ub[c]);
+                    best_d = INFINITY;
+                    best_j = kNone;
+                    sp = 0;
+                    steps = 0;
+                    if (UPWARD) {
+                        const uint32_t link = a.leaf_parent[i];
+                        anc = link >> 1;
+                        node = anc;
+                        mask = 2u >> (link & 1u);
+                        u = a.up[anc];
+                    } else {
+                        node = a.root;
+                        mask = 3u;
+                    }
+                    active = true;
+                }
+                cpos += take;
+            }
+        }
+        if (__ballot(active) == 0ull) {
+            if (drained) break;
+            continue;
+        }
+        if (!active) continue;
+        // a query processes every record at most twice (once climbing, once
+        // descending), so this bound only trips on a malformed tree
+        if (++steps > 2 * a.n + 256) {
+            atomicOr(&a.ctrl->error, kErrStack);
+            finish_one<DIM>(a, i, c, best_d, best_j);
+            active = false;
+            continue;
+        }
+        // ---- one record
+        const Rec<DIM> r = a.recs[node];
+        Child<DIM> ch[2];
+        unpack<DIM>(r, ch[0], ch[1]);
+        bool go[2] = {false, false};
+        float dd[2] = {0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (!((mask >> s) & 1u)) continue;
+            const bool leaf = (ch[s].ref & kLeafFlag) != 0u;
+            if (COUNT) { if (leaf) ++n_leaf; else ++n_int; }
+            if (ch[s].lab == c) continue;
+            const float d = boxdist<DIM>(p, ch[s].lo, ch[s].hi);
+            if (COUNT && leaf) ++n_eval;
+            if (d > radius) continue;
+            if (leaf) {
+                const uint32_t j = ch[s].ref & ~kLeafFlag;
+                if (better(d, j, best_d, best_j)) { best_d = d; best_j = j; radius = d; }
+            } else {
+                go[s] = true;
+                dd[s] = d;
+            }
+        }
+        mask = 3u;
+        bool done = false;
+        if (go[0] && go[1]) {
+            const int near = (dd[1] < dd[0]) ? 1 : 0;
+            if (sp >= STACK) {
+                atomicOr(&a.ctrl->error, kErrStack);
+                done = true;
+            } else {
+                st_node[sp] = ch[1 - near].ref;
+                st_d[sp] = dd[1 - near];
+                ++sp;
+                node = ch[near].ref;
+            }
+        } else if (go[0] || go[1]) {
+            node = go[0] ? ch[0].ref : ch[1].ref;
+        } else {
+            bool found = false;
+            while (sp > 0) {
+                --sp;
+                if (st_d[sp] <= radius) {
+                    node = st_node[sp];
+                    found = true;
+                    break;
+                }
+            }
+            if (!found) {
+                if (!UPWARD) {
+                    done = true;
+                } else {
+                    // the subtree off the path at `anc` is done: stop if the
+                    // ball of the radius lies in the Morton cell of `anc`
+                    const float rr = sqrtf(radius) * 1.000001f + 1e-22f;
+                    bool inside = (p[0] - rr >= u.a.x) && (p[0] + rr <= u.b.x);
+                    if (DIM > 1) inside = inside && (p[1 % DIM] - rr >= u.a.y) && (p[1 % DIM] + rr <= u.b.y);
+                    if (DIM > 2) inside = inside && (p[2 % DIM] - rr >= u.a.z) && (p[2 % DIM] + rr <= u.b.z);
+                    const uint32_t link = fbits(u.a.w);
+                    if (inside || link == kNone) {
+                        done = true;
+                    } else {
+                        anc = link >> 1;
+                        node = anc;
+                        mask = 2u >> (link & 1u);
+                        u = a.up[anc];
+                    }
+                }
+            }
+        }
+        if (done) {
+            finish_one<DIM>(a, i, c, best_d, best_j);
+            active = false;
+        }
+    }
+    flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
+}
+
+// ---------------------------------------------------------------------------
+// variants 5 and 6: the same searches as 0 and 2 with a tighter loop
+//
+// One record per iteration; both child distances are computed without
+// branching, leaf updates and the choice of the next node are selects, and
+// the stack lives in LDS (kLdsDepth entries per lane, laid out [depth][lane]
+// so a wave's accesses fall in distinct banks) with the deeper entries
+// spilled to a private array only when a search nests deeper than that.
+
+constexpr int kLdsDepth = 16;
+
+template <int DIM, int STACK, bool COUNT, bool UPWARD>
+__global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
+    __shared__ uint2 lds[kLdsDepth][256];
+    const int t = threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + t;
+    uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
+    uint32_t c = kNone, best_j = kNone;
+    float best_d = INFINITY;
+    if (i < a.n) {
+        float p[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
+        c = a.labels[i];
+        float radius = bitsf(a.ub[c]);
+        uint2 spill[STACK];
+        int sp = 0, base = 0;  // entries [0, base) spilled, [base, sp) in the LDS ring
+        uint32_t node, mask, anc = 0;
+        Up u;
+        if (UPWARD) {
+            const uint32_t link = a.leaf_parent[i];
+            anc = link >> 1;
+            node = anc;
+            mask = 2u >> (link & 1u);
+            u = a.up[anc];
+        } else {
+            node = a.root;
+            mask = 3u;
+        }
+        for (int64_t guard = 0;; ++guard) {
+            if (guard > 2 * a.n + 256) {
+                atomicOr(&a.ctrl->error, kErrStack);
+                break;
+            }
+            const Rec<DIM> r = a.recs[node];
+            Child<DIM> c0, c1;
+            unpack<DIM>(r, c0, c1);
+            const float d0 = boxdist<DIM>(p, c0.lo, c0.hi);
+            const float d1 = boxdist<DIM>(p, c1.lo, c1.hi);
+            const bool in0 = (mask & 1u) && c0.lab != c;
+            const bool in1 = (mask & 2u) && c1.lab != c;
+            const bool l0 = (c0.ref & kLeafFlag) != 0u, l1 = (c1.ref & kLeafFlag) != 0u;
+            if (COUNT) {
+                n_leaf += ((mask & 1u) && l0) + ((mask & 2u) && l1);
+                n_int += ((mask & 1u) && !l0) + ((mask & 2u) && !l1);
+                n_eval += (in0 && l0) + (in1 && l1);
+            }
+            // leaf candidates: (D, j) order, radius follows the best
+            {
+                const uint32_t j0 = c0.ref & ~kLeafFlag;
+                const bool b0 = in0 && l0 && d0 <= radius && better(d0, j0, best_d, best_j);
+                best_d = b0 ? d0 : best_d;
+                best_j = b0 ? j0 : best_j;
+                const uint32_t j1 = c1.ref & ~kLeafFlag;
+                const bool b1 = in1 && l1 && d1 <= radius && better(d1, j1, best_d, best_j);
+                best_d = b1 ? d1 : best_d;
+                best_j = b1 ? j1 : best_j;
+                radius = fminf(radius, best_d);
+            }
+            const bool go0 = in0 && !l0 && d0 <= radius;
+            const bool go1 = in1 && !l1 && d1 <= radius;
+            mask = 3u;
+            if (go0 && go1) {
+                const bool near1 = d1 < d0;
+                const uint2 far = make_uint2(near1 ? c0.ref : c1.ref, fbits(near1 ? d0 : d1));
+                node = near1 ? c1.ref : c0.ref;
+                if (sp - base == kLdsDepth) {  // ring full: move its oldest entry out
+                    if (base >= STACK) {
+                        atomicOr(&a.ctrl->error, kErrStack);
+                        break;
+                    }
+                    spill[base] = lds[base % kLdsDepth][t];
+                    ++base;
+                }
+                lds[sp % kLdsDepth][t] = far;
+                ++sp;
+                continue;
+            }
+            if (go0 || go1) {
+                node = go0 ? c0.ref : c1.ref;
+                continue;
+            }
+            bool found = false;
+            while (sp > 0) {
+                --sp;
+                uint2 e;
+                if (sp < base) {
+                    base = sp;
+                    e = spill[sp];
+                } else {
+                    e = lds[sp % kLdsDepth][t];
+                }
+                if (bitsf(e.y) <= radius) {
+                    node = e.x;
+                    found = true;
+                    break;
+                }
+            }
+            if (found) continue;
+            if (!UPWARD) break;
+            // every leaf of `anc` has been searched: stop if the ball of the
+            // radius lies in its Morton cell (see variant 2)
+            const float rr = sqrtf(radius) * 1.000001f + 1e-22f;
+            bool inside = (p[0] - rr >= u.a.x) && (p[0] + rr <= u.b.x);
+            if (DIM > 1) inside = inside && (p[1 % DIM] - rr >= u.a.y) && (p[1 % DIM] + rr <= u.b.y);
+            if (DIM > 2) inside = inside && (p[2 % DIM] - rr >= u.a.z) && (p[2 % DIM] + rr <= u.b.z);
+            const uint32_t link = fbits(u.a.w);
+            if (inside || link == kNone) break;
+            anc = link >> 1;
+            node = anc;
+            mask = 2u >> (link & 1u);
+            u = a.up[anc];
+        }
+    }
+    finish_query<DIM>(a, i, c, best_d, best_j);
+    flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
+}
+
+// ---------------------------------------------------------------------------
 
 template <int DIM, int STACK>
 hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count, hipStream_t st) {
-    const unsigned grid = (unsigned)((a.n + 255) / 256);
+    // a multiple of the XCD count, for the XCD-contiguous block mapping
+    const unsigned grid = (unsigned)(((a.n + 255) / 256 + kXcds - 1) / kXcds * kXcds);
     if (variant == 1) {
         if (count) k_traverse_wave<DIM, STACK, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_wave<DIM, STACK, false><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 2) {
+        if (count) k_traverse_up<DIM, STACK, true><<<grid, 256, 0, st>>>(a);
+        else k_traverse_up<DIM, STACK, false><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 5) {
+        if (count) k_traverse_fast<DIM, STACK, true, false><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 6) {
+        if (count) k_traverse_fast<DIM, STACK, true, true><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, true><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 3 || variant == 4) {
+        // persistent: enough waves to fill every CU several times over
+        const unsigned pgrid = std::min<unsigned>(grid, 2048u);
+        if (variant == 3) {
+            if (count) k_traverse_pool<DIM, STACK, true, false><<<pgrid, 256, 0, st>>>(a);
+            else k_traverse_pool<DIM, STACK, false, false><<<pgrid, 256, 0, st>>>(a);
+        } else {
+            if (count) k_traverse_pool<DIM, STACK, true, true><<<pgrid, 256, 0, st>>>(a);
+            else k_traverse_pool<DIM, STACK, false, true><<<pgrid, 256, 0, st>>>(a);
+        }
     } else {
         if (count) k_traverse_lane<DIM, STACK, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_lane<DIM, STACK, false><<<grid, 256, 0, st>>>(a);

@@ -52,7 +52,7 @@ SMALL = [(n, dim, seed, kind)
          for n, seed in ((2, 1), (3, 2), (5, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4099, 8))]
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("n,dim,seed,kind", SMALL)
 def test_small_clouds(ctx, n, dim, seed, kind, variant):
     pts = W.small_random(n, dim, seed, kind)
@@ -60,7 +60,7 @@ def test_small_clouds(ctx, n, dim, seed, kind, variant):
     assert_same(run(ctx, pts, variant), oracle.prim(pts), f"{kind} n={n} d={dim}")
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_closed_forms(ctx, variant):
     cases = {
         "identical": W.identical(1000),
@@ -75,14 +75,19 @@ def test_closed_forms(ctx, variant):
         assert_same(run(ctx, pts, variant), oracle.emst(pts, threads=8), name)
 
 
-def test_denormal_and_wide_range_coordinates(ctx):
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+def test_denormal_and_wide_range_coordinates(ctx, variant):
     rng = np.random.default_rng(3)
     tiny = (rng.random((500, 3)) * 1e-19).astype(np.float32)   # D is denormal
-    assert_same(run(ctx, tiny), oracle.prim(tiny), "denormal")
+    assert_same(run(ctx, tiny, variant), oracle.prim(tiny), "denormal")
+    under = (rng.random((500, 3)) * 1e-22).astype(np.float32)  # many D underflow to 0
+    assert_same(run(ctx, under, variant), oracle.prim(under), "underflow")
     big = (rng.random((500, 3)) * 1e18).astype(np.float32)     # D near 1e36, finite
-    assert_same(run(ctx, big), oracle.prim(big), "large")
+    assert_same(run(ctx, big, variant), oracle.prim(big), "large")
     neg = (rng.standard_normal((800, 2)) * 1e3).astype(np.float32)
-    assert_same(run(ctx, neg), oracle.prim(neg), "negative")
+    assert_same(run(ctx, neg, variant), oracle.prim(neg), "negative")
+    off = (1000.0 + rng.random((800, 3)) * 1e-3).astype(np.float32)  # small extent far from 0
+    assert_same(run(ctx, off, variant), oracle.prim(off), "offset")
 
 
 def test_fewer_than_two_points(ctx):
@@ -129,7 +134,7 @@ def test_errors(ctx):
 def test_variants_counting_and_repeats_agree(ctx):
     pts = W.clustered3d(60_000, seed=9)
     ref = oracle.kdboruvka(pts, threads=8)
-    for variant in (0, 1):
+    for variant in (0, 1, 2, 3, 4, 5, 6):
         for counting in (False, True):
             ctx.set_counting(counting)
             print(f"variant={variant} counting={counting}", flush=True)
@@ -251,13 +256,13 @@ def test_radix_sort(ctx):
 def test_uniform2d_10k(ctx):
     pts = W.uniform2d()
     ref = oracle.prim(pts)
-    for variant in (0, 1):
+    for variant in (0, 1, 2, 3, 4, 5, 6):
         assert_same(run(ctx, pts, variant), ref, f"uniform2d_10k v{variant}")
 
 
 def test_clustered3d_2m(ctx):
     pts = W.clustered3d()
     ref = oracle.kdboruvka(pts, threads=16)
-    for variant in (0, 1):
+    for variant in (0, 1, 2, 3, 4, 5, 6):
         print(f"clustered3d_2m variant={variant}", flush=True)
         assert_same(run(ctx, pts, variant), ref, f"clustered3d_2m v{variant}")
