@@ -95,7 +95,41 @@ int emst_build(emst_ctx *ctx, const float *d_points, int64_t n, int dim,
                int32_t *d_edges, float *d_weights, float *d_d2,
                void *d_workspace, size_t ws_bytes, void *stream);
 
-/* Per-call statistics of the last successful emst_build on this context.
+/* Exact workspace bytes emst_build_batched needs for `total_points` points
+ * in `n_clouds` clouds (0 for invalid arguments). */
+size_t emst_workspace_bytes_batched(int64_t total_points, int32_t n_clouds);
+
+/*
+ * emst_build_batched -- EMSTs of many independent clouds in one pass.
+ *
+ * The clouds are built as one tree in which every cloud is its own
+ * subtree; one round loop serves all of them and a query only searches its
+ * own cloud.  The result of every cloud is exactly what emst_build returns
+ * for that cloud alone.
+ *
+ *  d_points       float32, the clouds one after the other; cloud c holds
+ *                 n_c = h_offsets[c+1] - h_offsets[c] points of h_dims[c]
+ *                 coordinates each (row-major), starting at float index
+ *                 sum_{c' < c} n_c' * h_dims[c'].
+ *  h_offsets      [n_clouds + 1] host, h_offsets[0] = 0, non-decreasing;
+ *                 h_offsets[n_clouds] <= 2^31 - 1 points in total.
+ *  h_dims         [n_clouds] host, each 2 or 3 (mixed dims are fine).
+ *  d_edges        [sum max(n_c - 1, 0)][2] int32 out: cloud c's edges start
+ *                 at edge h_edge_offsets[c], with cloud-local indices
+ *                 (0 .. n_c - 1), u < v, sorted by K within the cloud.
+ *  d_weights, d_d2  as in emst_build, same edge order (d_d2 nullable).
+ *  h_edge_offsets [n_clouds + 1] host out (nullable): first edge of every
+ *                 cloud; h_edge_offsets[n_clouds] = total edges.
+ *
+ * Errors as emst_build, for any cloud (the message names the cloud).
+ */
+int emst_build_batched(emst_ctx *ctx, const float *d_points, const int64_t *h_offsets,
+                       const int32_t *h_dims, int32_t n_clouds, int32_t *d_edges,
+                       float *d_weights, float *d_d2, int64_t *h_edge_offsets,
+                       void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Per-call statistics of the last successful emst_build or
+ * emst_build_batched on this context.
  * Timings are measured with HIP events on the call's stream when profiling
  * is on (emst_set_profiling), else they are 0. */
 typedef struct emst_stats {

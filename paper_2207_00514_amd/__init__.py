@@ -31,6 +31,7 @@ EXPORTS = [
     "emst_create", "emst_destroy", "emst_last_error", "emst_workspace_bytes", "emst_build",
     "emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_get_stats",
     "emst_test_tree_from_codes", "emst_test_radix_sort",
+    "emst_workspace_bytes_batched", "emst_build_batched",
 ]
 
 
@@ -93,6 +94,11 @@ def lib():
             getattr(L, f).restype = i32
         L.emst_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.emst_get_stats.restype = i32
+        L.emst_workspace_bytes_batched.argtypes = [i64, ctypes.c_int32]
+        L.emst_workspace_bytes_batched.restype = sz
+        L.emst_build_batched.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.c_int32, vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
+        L.emst_build_batched.restype = i32
         L.emst_test_tree_from_codes.argtypes = [vp, vp, i64, vp, vp, vp, vp,
                                                 ctypes.POINTER(ctypes.c_int32), vp, sz, vp]
         L.emst_test_tree_from_codes.restype = i32
@@ -104,6 +110,10 @@ def lib():
 
 def workspace_bytes(n: int, dim: int) -> int:
     return int(lib().emst_workspace_bytes(int(n), int(dim)))
+
+
+def workspace_bytes_batched(total_points: int, n_clouds: int) -> int:
+    return int(lib().emst_workspace_bytes_batched(int(total_points), int(n_clouds)))
 
 
 def _stream_handle(stream):
@@ -222,6 +232,52 @@ class Context:
                               _stream_handle(stream))
         self._check(rc)
         return edges, weights, d2
+
+
+    def build_batched(self, clouds, want_d2: bool = True, stream=None):
+        """EMSTs of a list of clouds ([n_c, dim_c] float32 tensors on this
+        device, dims 2 or 3, mixed allowed) in one batched pass.  Returns a
+        list of (edges, weights, d2) per cloud (views into shared outputs,
+        cloud-local indices)."""
+        import torch
+        dev = torch.device(f"cuda:{self.device}")
+        flat = [c.contiguous().reshape(-1) for c in clouds]
+        sizes = [int(c.shape[0]) for c in clouds]
+        dims = [int(c.shape[1]) if c.dim() == 2 else 0 for c in clouds]
+        points = torch.cat(flat) if flat else torch.empty(0, device=dev)
+        return self.build_batched_flat(points, sizes, dims, want_d2=want_d2, stream=stream)
+
+    def build_batched_flat(self, points, sizes, dims, want_d2: bool = True, stream=None):
+        """Low-level form: `points` is the flat float32 concatenation, `sizes`
+        and `dims` the per-cloud point counts and dimensions."""
+        import torch
+        B = len(sizes)
+        offs = (ctypes.c_int64 * (B + 1))()
+        for c in range(B):
+            offs[c + 1] = offs[c] + int(sizes[c])
+        dims_c = (ctypes.c_int32 * max(B, 1))(*[int(d) for d in dims])
+        eoffs = (ctypes.c_int64 * (B + 1))()
+        total = int(offs[B])
+        m = sum(max(int(n) - 1, 0) for n in sizes)
+        dev = points.device
+        edges = torch.empty((m, 2), dtype=torch.int32, device=dev)
+        weights = torch.empty(m, dtype=torch.float32, device=dev)
+        d2 = torch.empty(m, dtype=torch.float32, device=dev) if want_d2 else None
+        wsb = workspace_bytes_batched(total, max(B, 1))
+        if self._ws is None or self._ws.numel() < wsb + 256:
+            self._ws = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
+        base = (self._ws.data_ptr() + 255) & ~255
+        rc = lib().emst_build_batched(
+            self._h, ctypes.c_void_p(points.data_ptr() if points.numel() else 0), offs, dims_c, int(B),
+            ctypes.c_void_p(edges.data_ptr() if m else 0), ctypes.c_void_p(weights.data_ptr() if m else 0),
+            ctypes.c_void_p(d2.data_ptr() if (d2 is not None and m) else 0), eoffs, ctypes.c_void_p(base),
+            ctypes.c_size_t(wsb), _stream_handle(stream))
+        self._check(rc)
+        out = []
+        for c in range(B):
+            a, b = int(eoffs[c]), int(eoffs[c + 1])
+            out.append((edges[a:b], weights[a:b], d2[a:b] if d2 is not None else None))
+        return out
 
 
 _default = {}

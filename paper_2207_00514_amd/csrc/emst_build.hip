@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/emst.h"
 #include "../../include/emst_test.h"
@@ -428,7 +429,8 @@ __global__ __launch_bounds__(256) void k_record_labels(const uint32_t* __restric
 // combine first and one lane per run updates the component.
 template <int DIM, bool FIRST>
 __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, const uint32_t* __restrict__ labels,
-                                                int64_t n, uint32_t* ub, Ctrl* ctrl) {
+                                                const uint32_t* __restrict__ cloud_of, int64_t n, uint32_t* ub,
+                                                Ctrl* ctrl) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) {
         ctrl->ncomp_next = 0u;
@@ -440,13 +442,14 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, 
         float p[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) p[c] = spts[k * DIM + c];
-        if (k > 0 && labels[k - 1] != lab) {
+        const uint32_t cl = cloud_of ? cloud_of[k] : 0u;
+        if (k > 0 && labels[k - 1] != lab && (!cloud_of || cloud_of[k - 1] == cl)) {
             float q[DIM];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) q[c] = spts[(k - 1) * DIM + c];
             v = min(v, fbits(sqdist<DIM>(q, p)));
         }
-        if (k + 1 < n && labels[k + 1] != lab) {
+        if (k + 1 < n && labels[k + 1] != lab && (!cloud_of || cloud_of[k + 1] == cl)) {
             float q[DIM];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) q[c] = spts[(k + 1) * DIM + c];
@@ -486,13 +489,14 @@ __global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ pos,
                                                     const uint64_t* __restrict__ compkey,
                                                     const uint32_t* __restrict__ compmax, uint32_t* succ,
-                                                    Ctrl* ctrl, int64_t n) {
+                                                    Ctrl* ctrl, int64_t n, bool allow_isolated) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n || labels[c] != (uint32_t)c) return;
     const uint64_t key = compkey[c];
     const uint32_t v = compmax[c];
     if (key == kKeyMax || v == kNone) {
-        atomicOr(&ctrl->error, kErrNoEdge);
+        // only a component that is a whole cloud of a batch has no edge
+        if (!allow_isolated) atomicOr(&ctrl->error, kErrNoEdge);
         succ[c] = (uint32_t)c;
         return;
     }
@@ -621,6 +625,175 @@ __global__ __launch_bounds__(256) void k_edge_write(const uint32_t* __restrict__
 }
 
 // ===========================================================================
+// batches: many independent clouds in one pass
+//
+// Every cloud gets its own scene box and Morton quantisation, and its cloud
+// id becomes the top bits of its codes.  One sort then groups each cloud in
+// a contiguous range of sorted positions, and in the one radix tree built
+// over all codes every cloud with two or more points is exactly one subtree
+// (all keys with the cloud-id prefix, and only those).
+
+struct CloudIn {       // host -> device, per cloud
+    int64_t off;       // first point (input order = sorted order per cloud)
+    int64_t n;         // points
+    int64_t foff;      // first float of the cloud in the input array
+    int64_t eoff;      // first output edge
+    int32_t dim;
+    int32_t pad;
+};
+struct CloudBox {      // device -> host, per cloud
+    uint32_t mn[3], mx[3];
+    uint32_t bad;
+    uint32_t pad;
+};
+struct CloudMorton {   // host -> device, per cloud
+    double lo[3], scale[3], qmax;
+    int32_t dim, bits;
+};
+
+// One block per cloud: unpack to 3D (z = 0 for 2D clouds; + 0 adds exactly,
+// so D is unchanged), record each point's cloud, reduce the cloud's box.
+__global__ __launch_bounds__(256) void k_batch_unpack(const float* __restrict__ pts, const CloudIn* __restrict__ cin,
+                                                      float* __restrict__ pts3, uint32_t* __restrict__ cloud_of,
+                                                      CloudBox* __restrict__ cbox) {
+    __shared__ float s_lo[4][3], s_hi[4][3];
+    __shared__ uint32_t s_bad[4];
+    const int b = blockIdx.x;
+    const CloudIn ci = cin[b];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    for (int64_t q = threadIdx.x; q < ci.n; q += blockDim.x) {
+        float x[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < ci.dim; ++k) x[k] = pts[ci.foff + q * ci.dim + k];
+        const int64_t g = ci.off + q;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            pts3[3 * g + k] = x[k];
+            bad |= !isfinite(x[k]);
+            lo[k] = fminf(lo[k], x[k]);
+            hi[k] = fmaxf(hi[k], x[k]);
+        }
+        cloud_of[g] = (uint32_t)b;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+        }
+    const bool any_bad = __ballot(bad) != 0ull;
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { s_lo[w][k] = lo[k]; s_hi[w][k] = hi[k]; }
+        s_bad[w] = any_bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        CloudBox cb;
+        cb.bad = 0;
+        cb.pad = 0;
+        for (int v = 0; v < 4; ++v) {
+            cb.bad |= s_bad[v];
+            for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo[k], s_lo[v][k]); hi[k] = fmaxf(hi[k], s_hi[v][k]); }
+        }
+        for (int k = 0; k < 3; ++k) {
+            cb.mn[k] = ord_enc(ci.n > 0 ? lo[k] : 0.f);
+            cb.mx[k] = ord_enc(ci.n > 0 ? hi[k] : 0.f);
+        }
+        cbox[b] = cb;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_morton(const float* __restrict__ pts3,
+                                                      const uint32_t* __restrict__ cloud_of,
+                                                      const CloudMorton* __restrict__ cm, int64_t n, int cloud_shift,
+                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                      Ctrl* ctrl) {
+    __shared__ uint64_t s_or[4], s_and[4];
+    uint64_t kor = 0, kand = ~0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = cloud_of[i];
+        const CloudMorton m = cm[b];
+        uint64_t q[3];
+        for (int k = 0; k < 3; ++k) {
+            double t = ((double)pts3[3 * i + k] - m.lo[k]) * m.scale[k];
+            t = fmin(fmax(t, 0.0), m.qmax);
+            q[k] = (uint64_t)t;
+        }
+        uint64_t code = (m.dim == 3) ? ((spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]))
+                                     : ((spread2(q[0]) << 1) | spread2(q[1]));
+        if (cloud_shift < 64) code |= (uint64_t)b << cloud_shift;
+        keys[i] = code;
+        vals[i] = (uint32_t)i;
+        kor |= code;
+        kand &= code;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        kor |= __shfl_xor(kor, off);
+        kand &= __shfl_xor(kand, off);
+    }
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) { s_or[w] = kor; s_and[w] = kand; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; ++v) { kor |= s_or[v]; kand &= s_and[v]; }
+        atomicOr((unsigned long long*)&ctrl->key_or, (unsigned long long)kor);
+        atomicAnd((unsigned long long*)&ctrl->key_and, (unsigned long long)kand);
+    }
+}
+
+// Cloud of every sorted position (sorting keeps clouds contiguous and in
+// order, so it is also the cloud of every component slot).
+__global__ __launch_bounds__(256) void k_batch_sorted_cloud(const uint32_t* __restrict__ cloud_of,
+                                                            const uint32_t* __restrict__ perm, int64_t n,
+                                                            uint32_t* __restrict__ cloud_sorted) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cloud_sorted[i] = cloud_of[perm[i]];
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// The subtree root of a cloud is the internal node whose leaf range is
+// exactly the cloud's range of sorted positions.
+__global__ __launch_bounds__(256) void k_cloud_roots(const uint32_t* __restrict__ rlo, const uint32_t* __restrict__ rhi,
+                                                     const uint32_t* __restrict__ cloud_sorted,
+                                                     const CloudIn* __restrict__ cin, int64_t m,
+                                                     uint32_t* __restrict__ cloud_root) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const uint32_t lo = rlo[k], hi = rhi[k];
+    const uint32_t b = cloud_sorted[lo];
+    const CloudIn ci = cin[b];
+    if ((int64_t)lo == ci.off && (int64_t)hi == ci.off + ci.n - 1) cloud_root[b] = (uint32_t)k;
+}
+
+// Sorted slot i -> output edge of its cloud, with cloud-local indices.
+__global__ __launch_bounds__(256) void k_batch_edge_write(const uint32_t* __restrict__ eu,
+                                                          const uint32_t* __restrict__ ev,
+                                                          const uint32_t* __restrict__ ed,
+                                                          const uint32_t* __restrict__ order,
+                                                          const uint32_t* __restrict__ cloud_sorted,
+                                                          const CloudIn* __restrict__ cin, int64_t n,
+                                                          int32_t* __restrict__ edges, float* __restrict__ w,
+                                                          float* __restrict__ d2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t e = order[i];
+    if (ed[e] == kNone) return;
+    const CloudIn ci = cin[cloud_sorted[e]];
+    const int64_t o = ci.eoff + (i - ci.off);
+    const float d = bitsf(ed[e]);
+    edges[2 * o] = (int32_t)((int64_t)eu[e] - ci.off);
+    edges[2 * o + 1] = (int32_t)((int64_t)ev[e] - ci.off);
+    w[o] = sqrtf(d);
+    if (d2) d2[o] = d;
+}
+
+// ===========================================================================
 // workspace layout
 
 struct Layout {
@@ -628,6 +801,13 @@ struct Layout {
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    Layout base;
+    size_t pts3, cloud_of, cloud_sorted, cin, cbox, cm, croot, total;
+};
+
+static BatchLayout make_batch_layout(int64_t n, int64_t clouds);
 
 static Layout make_layout(int64_t n, int dim) {
     Layout L;
@@ -671,6 +851,27 @@ static Layout make_layout(int64_t n, int dim) {
     return L;
 }
 
+static BatchLayout make_batch_layout(int64_t n, int64_t clouds) {
+    BatchLayout B;
+    B.base = make_layout(n, 3);
+    size_t o = B.base.total;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += align_up(bytes);
+        return r;
+    };
+    const size_t N = (size_t)(n > 0 ? n : 1), C = (size_t)(clouds > 0 ? clouds : 1);
+    B.pts3 = take(12 * N);
+    B.cloud_of = take(4 * N);
+    B.cloud_sorted = take(4 * N);
+    B.cin = take(sizeof(CloudIn) * C);
+    B.cbox = take(sizeof(CloudBox) * C);
+    B.cm = take(sizeof(CloudMorton) * C);
+    B.croot = take(4 * C);
+    B.total = o;
+    return B;
+}
+
 }  // namespace emst
 
 // ===========================================================================
@@ -688,7 +889,21 @@ struct emst_ctx {
     Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
     hipEvent_t ev[2 * 64 + 8];
     bool ev_ok = false;
+    void* h_stage = nullptr;       // pinned host staging for per-cloud tables
+    size_t h_stage_bytes = 0;
 };
+
+// Pinned host memory of at least `bytes` (host memory only; the library
+// never allocates device memory).
+static void* stage(emst_ctx* ctx, size_t bytes) {
+    if (ctx->h_stage_bytes >= bytes) return ctx->h_stage;
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    ctx->h_stage = nullptr;
+    ctx->h_stage_bytes = 0;
+    if (hipHostMalloc(&ctx->h_stage, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    ctx->h_stage_bytes = bytes;
+    return ctx->h_stage;
+}
 
 #define HIP_TRY(expr)                                                                    \
     do {                                                                                 \
@@ -734,6 +949,7 @@ extern "C" void emst_destroy(emst_ctx* ctx) {
     if (!ctx) return;
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     delete ctx;
 }
 
@@ -773,6 +989,29 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+// Every D is at most the squared extent of the box, evaluated in the same
+// order, so a finite squared extent means no D overflows.
+bool extent_ok(const float* lo, const float* hi, int dim) {
+    volatile float s = 0.f;
+    for (int k = 0; k < dim; ++k) {
+        volatile float g = hi[k] - lo[k];
+        volatile float g2 = g * g;
+        s = (k == 0) ? (float)g2 : (float)(s + g2);
+    }
+    return isfinite((float)s);
+}
+
+MortonParams morton_params(const float* lo, const float* hi, int dim, int bits) {
+    MortonParams mp;
+    mp.qmax = (double)((1ull << bits) - 1ull);
+    for (int k = 0; k < 3; ++k) {
+        mp.lo[k] = k < dim ? (double)lo[k] : 0.0;
+        const double ext = k < dim ? (double)hi[k] - (double)lo[k] : 0.0;
+        mp.scale[k] = ext > 0.0 ? mp.qmax / ext : 0.0;
+    }
+    return mp;
+}
+
 template <int DIM>
 hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_start, uint32_t* run_part, const uint32_t* rlo,
                             const uint32_t* rhi, Rec<DIM>* recs, int64_t n, hipStream_t st) {
@@ -784,83 +1023,210 @@ hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_start, uint32_
     return hipGetLastError();
 }
 
+// All device arrays of one build, carved from the workspace.
+template <int DIM>
+struct Bufs {
+    Ctrl* ctrl;
+    uint64_t *k0, *k1;
+    uint32_t *v0, *v1, *hist;
+    float* spts;
+    uint32_t *orig, *pos;
+    Rec<DIM>* recs;
+    uint32_t *node_parent, *leaf_parent;
+    Up* up;
+    uint64_t* exch;
+    uint32_t *rlo, *rhi, *run_start, *run_part, *labels, *ub;
+    uint64_t* compkey;
+    uint32_t *compmax, *succ, *par, *cand_d, *cand_j, *eu, *ev, *ed;
+};
+
+template <int DIM>
+Bufs<DIM> carve(char* ws, const Layout& L) {
+    Bufs<DIM> b;
+    b.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+    b.k0 = reinterpret_cast<uint64_t*>(ws + L.k0);
+    b.k1 = reinterpret_cast<uint64_t*>(ws + L.k1);
+    b.v0 = reinterpret_cast<uint32_t*>(ws + L.v0);
+    b.v1 = reinterpret_cast<uint32_t*>(ws + L.v1);
+    b.hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+    b.spts = reinterpret_cast<float*>(ws + L.spts);
+    b.orig = reinterpret_cast<uint32_t*>(ws + L.orig);
+    b.pos = reinterpret_cast<uint32_t*>(ws + L.pos);
+    b.recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
+    b.node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
+    b.leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
+    b.up = reinterpret_cast<Up*>(ws + L.up);
+    b.exch = reinterpret_cast<uint64_t*>(ws + L.exch);
+    b.rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
+    b.rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
+    b.run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
+    b.run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
+    b.labels = reinterpret_cast<uint32_t*>(ws + L.labels);
+    b.ub = reinterpret_cast<uint32_t*>(ws + L.ub);
+    b.compkey = reinterpret_cast<uint64_t*>(ws + L.compkey);
+    b.compmax = reinterpret_cast<uint32_t*>(ws + L.compmax);
+    b.succ = reinterpret_cast<uint32_t*>(ws + L.succ);
+    b.par = reinterpret_cast<uint32_t*>(ws + L.par);
+    b.cand_d = reinterpret_cast<uint32_t*>(ws + L.cand_d);
+    b.cand_j = reinterpret_cast<uint32_t*>(ws + L.cand_j);
+    b.eu = reinterpret_cast<uint32_t*>(ws + L.eu);
+    b.ev = reinterpret_cast<uint32_t*>(ws + L.ev);
+    b.ed = reinterpret_cast<uint32_t*>(ws + L.ed);
+    return b;
+}
+
+template <int DIM>
+TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
+    TraverseArgs<DIM> ta;
+    ta.spts = b.spts; ta.labels = b.labels; ta.orig = b.orig; ta.ub = b.ub; ta.recs = b.recs; ta.root = root;
+    ta.n = n; ta.cand_d = b.cand_d; ta.cand_j = b.cand_j; ta.compkey = b.compkey; ta.compmax = b.compmax;
+    ta.ctrl = b.ctrl; ta.first = true; ta.leaf_parent = b.leaf_parent; ta.up = b.up;
+    ta.cloud_of = nullptr; ta.cloud_root = nullptr;
+    return ta;
+}
+
+int read_ctrl(emst_ctx* ctx, Ctrl* ctrl, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return EMST_OK;
+}
+
+// Boruvka rounds until the component count reaches `target` (1 for one
+// cloud, the number of non-empty clouds for a batch).  With cloud_of set,
+// Morton neighbours in different clouds bound nothing, every query searches
+// its own cloud's subtree, and a component without an outgoing edge (its
+// cloud is finished) becomes a root.
+template <int DIM>
+int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int64_t target, int height,
+               int variant, const uint32_t* cloud_of, emst_stats& S, hipStream_t st) {
+    const bool prof = ctx->profiling && ctx->ev_ok;
+    hipEvent_t* E = ctx->ev;
+    int64_t ncomp = n;
+    int round = 0;
+    while (ncomp > target) {
+        if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
+        S.components[round] = ncomp;
+        HIP_TRY(propagate_labels<DIM>(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.recs, n, st));
+        if (round == 0) k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, n, b.ub, b.ctrl);
+        else k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, n, b.ub, b.ctrl);
+        if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
+        ta.first = round == 0;
+        HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
+        if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
+        if (round > 0)
+            k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n);
+        k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.succ, b.ctrl, n,
+                                                  cloud_of != nullptr);
+        k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(
+            b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eu, b.ev, b.ed, b.ctrl, n);
+        HIP_TRY(hipGetLastError());
+        k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024);
+        k_relabel<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 4096, b.ctrl);
+        HIP_TRY(hipGetLastError());
+        if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+        const Ctrl* h = ctx->h_ctrl;
+        if (h->error & kErrStack) return fail(ctx, EMST_EINTERNAL, "traversal stack overflow");
+        if (h->error & kErrJump) return fail(ctx, EMST_EINTERNAL, "component merge did not converge");
+        if (h->error) return fail(ctx, EMST_EINTERNAL, "a component found no outgoing edge");
+        if (ctx->counting) {
+            const int64_t it = (int64_t)h->internal_tests, lt = (int64_t)h->leaf_tests;
+            S.child_tests_round[round] = it - S.child_tests;
+            S.leaf_tests_round[round] = lt - S.leaf_tests;
+            S.child_tests = it;
+            S.leaf_tests = lt;
+            S.dist_evals = (int64_t)h->dist_evals;
+        }
+        const int64_t next = h->ncomp_next;
+        if (next >= ncomp || next < target) return fail(ctx, EMST_EINTERNAL, "round made no progress");
+        ncomp = next;
+        ++round;
+    }
+    S.rounds = round;
+    S.traversal_launches = round;
+    return EMST_OK;
+}
+
+// Canonical edge order over the n component slots (the slots of the final
+// roots are empty and sort last): by (u, v), then stably by D bits, then --
+// for a batch -- stably by cloud.  Writes sorted slot ids to *order.
+template <int DIM>
+int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_cloud, int cloud_bits,
+               const uint32_t** order, hipStream_t st) {
+    int in1 = 0;
+    k_edge_keys<<<grid_for(n), 256, 0, st>>>(b.eu, b.ev, n, b.k0, b.v0);
+    int sh[16], q = 0;
+    const int ib = 32 - __builtin_clz((unsigned)(n - 1));  // bits of the largest index
+    for (int s = 0; s < ib; s += 8) sh[q++] = s;
+    for (int s = 0; s < ib; s += 8) sh[q++] = 32 + s;
+    HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, sh, q, &in1));
+    uint32_t* p = in1 ? b.v1 : b.v0;
+    uint64_t* kd = in1 ? b.k1 : b.k0;
+    uint64_t* kd_alt = in1 ? b.k0 : b.k1;
+    uint32_t* p_alt = in1 ? b.v0 : b.v1;
+    k_edge_dkeys<<<grid_for(n), 256, 0, st>>>(b.ed, p, n, kd);
+    const int dsh[4] = {0, 8, 16, 24};
+    HIP_TRY(radix_sort_pairs(st, kd, p, kd_alt, p_alt, b.hist, n, dsh, 4, &in1));
+    if (in1) {
+        std::swap(p, p_alt);
+        std::swap(kd, kd_alt);
+    }
+    if (slot_cloud && cloud_bits > 0) {
+        k_edge_dkeys<<<grid_for(n), 256, 0, st>>>(slot_cloud, p, n, kd);
+        int csh[4], cq = 0;
+        for (int s = 0; s < cloud_bits; s += 8) csh[cq++] = s;
+        HIP_TRY(radix_sort_pairs(st, kd, p, kd_alt, p_alt, b.hist, n, csh, cq, &in1));
+        if (in1) std::swap(p, p_alt);
+    }
+    HIP_TRY(hipGetLastError());
+    *order = p;
+    return EMST_OK;
+}
+
+void finish_stats(emst_ctx* ctx, emst_stats& S) {
+    if (ctx->profiling && ctx->ev_ok) {
+        hipEvent_t* E = ctx->ev;
+        S.tree_ms = elapsed(E[0], E[1]);
+        S.rounds_ms = elapsed(E[1], E[2]);
+        S.finalize_ms = elapsed(E[2], E[3]);
+        S.total_ms = elapsed(E[0], E[3]);
+        for (int r = 0; r < S.rounds; ++r) {
+            S.traversal_ms_round[r] = elapsed(E[8 + 2 * r], E[9 + 2 * r]);
+            S.traversal_ms += S.traversal_ms_round[r];
+        }
+    }
+    ctx->stats = S;
+}
+
 template <int DIM>
 int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float* weights, float* d2, char* ws,
                hipStream_t st) {
     const Layout L = make_layout(n, DIM);
-    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
-    uint64_t* k0 = reinterpret_cast<uint64_t*>(ws + L.k0);
-    uint64_t* k1 = reinterpret_cast<uint64_t*>(ws + L.k1);
-    uint32_t* v0 = reinterpret_cast<uint32_t*>(ws + L.v0);
-    uint32_t* v1 = reinterpret_cast<uint32_t*>(ws + L.v1);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
-    float* spts = reinterpret_cast<float*>(ws + L.spts);
-    uint32_t* orig = reinterpret_cast<uint32_t*>(ws + L.orig);
-    uint32_t* pos = reinterpret_cast<uint32_t*>(ws + L.pos);
-    Rec<DIM>* recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
-    uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
-    uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
-    Up* up = reinterpret_cast<Up*>(ws + L.up);
-    uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
-    uint32_t* rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
-    uint32_t* rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
-    uint32_t* run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
-    uint32_t* run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
-    uint32_t* labels = reinterpret_cast<uint32_t*>(ws + L.labels);
-    uint32_t* ub = reinterpret_cast<uint32_t*>(ws + L.ub);
-    uint64_t* compkey = reinterpret_cast<uint64_t*>(ws + L.compkey);
-    uint32_t* compmax = reinterpret_cast<uint32_t*>(ws + L.compmax);
-    uint32_t* succ = reinterpret_cast<uint32_t*>(ws + L.succ);
-    uint32_t* par = reinterpret_cast<uint32_t*>(ws + L.par);
-    uint32_t* cand_d = reinterpret_cast<uint32_t*>(ws + L.cand_d);
-    uint32_t* cand_j = reinterpret_cast<uint32_t*>(ws + L.cand_j);
-    uint32_t* eu = reinterpret_cast<uint32_t*>(ws + L.eu);
-    uint32_t* ev = reinterpret_cast<uint32_t*>(ws + L.ev);
-    uint32_t* ed = reinterpret_cast<uint32_t*>(ws + L.ed);
-
+    Bufs<DIM> b = carve<DIM>(ws, L);
     emst_stats S;
     memset(&S, 0, sizeof(S));
     S.n = n;
     S.dim = DIM;
     const bool prof = ctx->profiling && ctx->ev_ok;
-    hipEvent_t* E = ctx->ev;  // E[0..7] phases, E[8 + 2r], E[9 + 2r] traversal of round r
+    hipEvent_t* E = ctx->ev;  // E[0..3] phases, E[8 + 2r], E[9 + 2r] traversal of round r
 
     if (prof) HIP_TRY(hipEventRecord(E[0], st));
     // ---- validation + scene box
-    k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
-    k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, ctrl);
+    k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
+    k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, b.ctrl);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
     if (ctx->h_ctrl->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     for (int k = 0; k < DIM; ++k) {
         lo[k] = ord_dec(ctx->h_ctrl->bb_min[k]);
         hi[k] = ord_dec(ctx->h_ctrl->bb_max[k]);
     }
-    {
-        // every D is at most the squared extent, evaluated in the same order
-        volatile float s = 0.f;
-        for (int k = 0; k < DIM; ++k) {
-            volatile float g = hi[k] - lo[k];
-            volatile float g2 = g * g;
-            s = (k == 0) ? (float)g2 : (float)(s + g2);
-        }
-        if (!isfinite((float)s)) return fail(ctx, EMST_ERANGE, "squared extent of the cloud overflows float32");
-    }
+    if (!extent_ok(lo, hi, DIM)) return fail(ctx, EMST_ERANGE, "squared extent of the cloud overflows float32");
     // ---- Morton codes + sort
-    MortonParams mp;
-    const int bits = DIM == 3 ? 21 : 32;
-    mp.qmax = (double)((1ull << bits) - 1ull);
-    for (int k = 0; k < 3; ++k) {
-        mp.lo[k] = k < DIM ? (double)lo[k] : 0.0;
-        const double ext = k < DIM ? (double)hi[k] - (double)lo[k] : 0.0;
-        mp.scale[k] = ext > 0.0 ? mp.qmax / ext : 0.0;
-    }
-    k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, mp, k0, v0, ctrl);
+    const MortonParams mp = morton_params(lo, hi, DIM, DIM == 3 ? 21 : 32);
+    k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, mp, b.k0, b.v0, b.ctrl);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
     int shifts[8], ns = 0;
     {
         const uint64_t vary = ctx->h_ctrl->key_or ^ ctx->h_ctrl->key_and;
@@ -868,106 +1234,161 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
             if ((vary >> s) & 0xFFull) shifts[ns++] = s;
     }
     int in1 = 0;
-    HIP_TRY(radix_sort_pairs(st, k0, v0, k1, v1, hist, n, shifts, ns, &in1));
-    const uint64_t* codes = in1 ? k1 : k0;
-    const uint32_t* perm = in1 ? v1 : v0;
+    HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, ns, &in1));
+    const uint64_t* codes = in1 ? b.k1 : b.k0;
+    const uint32_t* perm = in1 ? b.v1 : b.v0;
     // ---- hierarchy + boxes
-    k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, spts, orig, pos, labels, ub, compkey, compmax, exch,
-                                               eu, ev, ed);
-    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, orig, spts, n, recs, leaf_parent, node_parent, exch, rlo, rhi,
-                                              ctrl);
+    k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
+                                               b.compmax, b.exch, b.eu, b.ev, b.ed);
+    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, b.orig, b.spts, n, b.recs, b.leaf_parent, b.node_parent,
+                                              b.exch, b.rlo, b.rhi, b.ctrl);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
     const uint32_t root = ctx->h_ctrl->root;
     S.tree_height = (int32_t)ctx->h_ctrl->height;
     if (root == kNone || root >= (uint32_t)(n - 1) || ctx->h_ctrl->error)
         return fail(ctx, EMST_EINTERNAL, "tree construction failed");
-    k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, node_parent, n - 1, mp, up);
+    k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, mp, b.up);
     HIP_TRY(hipGetLastError());
     if (prof) HIP_TRY(hipEventRecord(E[1], st));
 
     // ---- Boruvka rounds
-    TraverseArgs<DIM> ta;
-    ta.spts = spts; ta.labels = labels; ta.orig = orig; ta.ub = ub; ta.recs = recs; ta.root = root; ta.n = n;
-    ta.cand_d = cand_d; ta.cand_j = cand_j; ta.compkey = compkey; ta.compmax = compmax; ta.ctrl = ctrl;
-    ta.leaf_parent = leaf_parent; ta.up = up;
-    int64_t ncomp = n;
-    int round = 0;
-    while (ncomp > 1) {
-        if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
-        S.components[round] = ncomp;
-        HIP_TRY(propagate_labels<DIM>(labels, run_start, run_part, rlo, rhi, recs, n, st));
-        if (round == 0) k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(spts, labels, n, ub, ctrl);
-        else k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(spts, labels, n, ub, ctrl);
-        if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
-        ta.first = round == 0;
-        HIP_TRY(launch_traverse<DIM>(ta, S.tree_height, ctx->traversal, ctx->counting, st));
-        if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
-        if (round > 0) k_resolve<<<grid_for(n), 256, 0, st>>>(cand_d, cand_j, labels, orig, compkey, compmax, n);
-        k_merge_succ<<<grid_for(n), 256, 0, st>>>(labels, pos, compkey, compmax, succ, ctrl, n);
-        k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(labels, succ, par, compkey, compmax,
-                                                                              ub, eu, ev, ed, ctrl, n);
-        HIP_TRY(hipGetLastError());
-        k_merge_jump<<<grid_for(n), 256, 0, st>>>(labels, par, n, 1024);
-        k_relabel<<<grid_for(n), 256, 0, st>>>(labels, par, n, 4096, ctrl);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (ctx->h_ctrl->error & kErrStack) return fail(ctx, EMST_EINTERNAL, "traversal stack overflow");
-        if (ctx->h_ctrl->error & kErrJump) return fail(ctx, EMST_EINTERNAL, "component merge did not converge");
-        if (ctx->h_ctrl->error) return fail(ctx, EMST_EINTERNAL, "a component found no outgoing edge");
-        if (ctx->counting) {
-            const int64_t it = (int64_t)ctx->h_ctrl->internal_tests, lt = (int64_t)ctx->h_ctrl->leaf_tests;
-            S.child_tests_round[round] = it - S.child_tests;
-            S.leaf_tests_round[round] = lt - S.leaf_tests;
-            S.child_tests = it;
-            S.leaf_tests = lt;
-            S.dist_evals = (int64_t)ctx->h_ctrl->dist_evals;
-        }
-        const int64_t next = ctx->h_ctrl->ncomp_next;
-        if (next >= ncomp || next < 1) return fail(ctx, EMST_EINTERNAL, "round made no progress");
-        ncomp = next;
-        ++round;
-    }
-    S.rounds = round;
-    S.traversal_launches = round;
+    TraverseArgs<DIM> ta = traverse_args<DIM>(b, n, root);
+    if (int rc = run_rounds<DIM>(ctx, b, ta, n, 1, S.tree_height, ctx->traversal, nullptr, S, st)) return rc;
     if (ctx->h_ctrl->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
 
-    // ---- canonical order: by (u, v) first, then stably by D bits
-    // n slots, one per component id; the final root's slot is empty and its
-    // key (all ones) sorts after every edge
-    const int64_t m = n - 1;
-    k_edge_keys<<<grid_for(n), 256, 0, st>>>(eu, ev, n, k0, v0);
-    int sh[16], q = 0;
-    const int ib = 32 - __builtin_clz((unsigned)(n - 1));  // bits of the largest index
-    for (int s = 0; s < ib; s += 8) sh[q++] = s;
-    for (int s = 0; s < ib; s += 8) sh[q++] = 32 + s;
-    HIP_TRY(radix_sort_pairs(st, k0, v0, k1, v1, hist, n, sh, q, &in1));
-    uint32_t* p1 = in1 ? v1 : v0;
-    uint64_t* kd = in1 ? k1 : k0;
-    uint64_t* kd_alt = in1 ? k0 : k1;
-    uint32_t* p1_alt = in1 ? v0 : v1;
-    k_edge_dkeys<<<grid_for(n), 256, 0, st>>>(ed, p1, n, kd);
-    const int dsh[4] = {0, 8, 16, 24};
-    HIP_TRY(radix_sort_pairs(st, kd, p1, kd_alt, p1_alt, hist, n, dsh, 4, &in1));
-    const uint32_t* pfin = in1 ? p1_alt : p1;
-    k_edge_write<<<grid_for(m), 256, 0, st>>>(eu, ev, ed, pfin, m, edges, weights, d2);
+    // ---- canonical order
+    const uint32_t* order = nullptr;
+    if (int rc = sort_edges<DIM>(ctx, b, n, nullptr, 0, &order, st)) return rc;
+    k_edge_write<<<grid_for(n - 1), 256, 0, st>>>(b.eu, b.ev, b.ed, order, n - 1, edges, weights, d2);
     HIP_TRY(hipGetLastError());
     if (prof) HIP_TRY(hipEventRecord(E[3], st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (prof) {
-        S.tree_ms = elapsed(E[0], E[1]);
-        S.rounds_ms = elapsed(E[1], E[2]);
-        S.finalize_ms = elapsed(E[2], E[3]);
-        S.total_ms = elapsed(E[0], E[3]);
-        for (int r = 0; r < round; ++r) {
-            S.traversal_ms_round[r] = elapsed(E[8 + 2 * r], E[9 + 2 * r]);
-            S.traversal_ms += S.traversal_ms_round[r];
-        }
+    finish_stats(ctx, S);
+    return EMST_OK;
+}
+
+
+int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, const int32_t* h_dims, int32_t B,
+                 int32_t* edges, float* weights, float* d2, int64_t* h_edge_offsets, char* ws, hipStream_t st) {
+    const int64_t n = h_offsets[B];
+    const BatchLayout BL = make_batch_layout(n, B);
+    Bufs<3> b = carve<3>(ws, BL.base);
+    float* pts3 = reinterpret_cast<float*>(ws + BL.pts3);
+    uint32_t* cloud_of = reinterpret_cast<uint32_t*>(ws + BL.cloud_of);
+    uint32_t* cloud_sorted = reinterpret_cast<uint32_t*>(ws + BL.cloud_sorted);
+    CloudIn* d_cin = reinterpret_cast<CloudIn*>(ws + BL.cin);
+    CloudBox* d_cbox = reinterpret_cast<CloudBox*>(ws + BL.cbox);
+    CloudMorton* d_cm = reinterpret_cast<CloudMorton*>(ws + BL.cm);
+    uint32_t* d_croot = reinterpret_cast<uint32_t*>(ws + BL.croot);
+    emst_stats S;
+    memset(&S, 0, sizeof(S));
+    S.n = n;
+    S.dim = 3;
+    const bool prof = ctx->profiling && ctx->ev_ok;
+    hipEvent_t* E = ctx->ev;
+
+    // ---- per-cloud table (host) -> device
+    const size_t tbl = std::max(sizeof(CloudIn), std::max(sizeof(CloudBox), sizeof(CloudMorton))) * (size_t)B;
+    char* h = reinterpret_cast<char*>(stage(ctx, tbl));
+    if (!h) return fail(ctx, EMST_EHIP, "hipHostMalloc failed");
+    CloudIn* cin = reinterpret_cast<CloudIn*>(h);
+    int64_t foff = 0, eoff = 0, nonempty = 0;
+    for (int32_t c = 0; c < B; ++c) {
+        cin[c].off = h_offsets[c];
+        cin[c].n = h_offsets[c + 1] - h_offsets[c];
+        cin[c].foff = foff;
+        cin[c].eoff = eoff;
+        cin[c].dim = h_dims[c];
+        cin[c].pad = 0;
+        foff += cin[c].n * h_dims[c];
+        if (h_edge_offsets) h_edge_offsets[c] = eoff;
+        eoff += cin[c].n > 1 ? cin[c].n - 1 : 0;
+        nonempty += cin[c].n > 0;
     }
-    ctx->stats = S;
+    if (h_edge_offsets) h_edge_offsets[B] = eoff;
+    if (prof) HIP_TRY(hipEventRecord(E[0], st));
+    HIP_TRY(hipMemcpyAsync(d_cin, cin, sizeof(CloudIn) * B, hipMemcpyHostToDevice, st));
+    // ---- unpack + per-cloud boxes, validation
+    k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
+    k_batch_unpack<<<B, 256, 0, st>>>(pts, d_cin, pts3, cloud_of, d_cbox);
+    HIP_TRY(hipGetLastError());
+    CloudBox* cbox = reinterpret_cast<CloudBox*>(h);  // reuses the staging area
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpyAsync(cbox, d_cbox, sizeof(CloudBox) * B, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int cloud_bits = B > 1 ? 64 - __builtin_clzll((unsigned long long)(B - 1)) : 0;
+    const int avail = 64 - cloud_bits;
+    std::vector<CloudMorton> cm(B);
+    for (int32_t c = 0; c < B; ++c) {
+        if (cbox[c].bad) {
+            ctx->err = "non-finite coordinate in cloud " + std::to_string(c);
+            return EMST_ENONFINITE;
+        }
+        float lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) { lo[k] = ord_dec(cbox[c].mn[k]); hi[k] = ord_dec(cbox[c].mx[k]); }
+        if (!extent_ok(lo, hi, 3)) {
+            ctx->err = "squared extent of cloud " + std::to_string(c) + " overflows float32";
+            return EMST_ERANGE;
+        }
+        const int dim = h_dims[c];
+        const int bits = std::min(dim == 3 ? 21 : 32, avail / dim);
+        const MortonParams mp = morton_params(lo, hi, dim, bits);
+        for (int k = 0; k < 3; ++k) { cm[c].lo[k] = mp.lo[k]; cm[c].scale[k] = mp.scale[k]; }
+        cm[c].qmax = mp.qmax;
+        cm[c].dim = dim;
+        cm[c].bits = bits;
+    }
+    memcpy(h, cm.data(), sizeof(CloudMorton) * B);
+    HIP_TRY(hipMemcpyAsync(d_cm, h, sizeof(CloudMorton) * B, hipMemcpyHostToDevice, st));
+    // ---- codes (cloud id on top) + sort
+    k_batch_morton<<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts3, cloud_of, d_cm, n, avail, b.k0,
+                                                                           b.v0, b.ctrl);
+    HIP_TRY(hipGetLastError());
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+    int shifts[8], ns = 0;
+    {
+        const uint64_t vary = ctx->h_ctrl->key_or ^ ctx->h_ctrl->key_and;
+        for (int s = 0; s < 64; s += 8)
+            if ((vary >> s) & 0xFFull) shifts[ns++] = s;
+    }
+    int in1 = 0;
+    HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, ns, &in1));
+    const uint64_t* codes = in1 ? b.k1 : b.k0;
+    const uint32_t* perm = in1 ? b.v1 : b.v0;
+    // ---- one tree over all clouds
+    k_gather<3><<<grid_for(n), 256, 0, st>>>(pts3, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
+                                             b.compmax, b.exch, b.eu, b.ev, b.ed);
+    k_batch_sorted_cloud<<<grid_for(n), 256, 0, st>>>(cloud_of, perm, n, cloud_sorted);
+    k_build<3><<<grid_for(n), 256, 0, st>>>(codes, b.orig, b.spts, n, b.recs, b.leaf_parent, b.node_parent, b.exch,
+                                            b.rlo, b.rhi, b.ctrl);
+    k_fill_u32<<<grid_for(B), 256, 0, st>>>(d_croot, B, kNone);
+    k_cloud_roots<<<grid_for(n - 1), 256, 0, st>>>(b.rlo, b.rhi, cloud_sorted, d_cin, n - 1, d_croot);
+    HIP_TRY(hipGetLastError());
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+    S.tree_height = (int32_t)ctx->h_ctrl->height;
+    if (ctx->h_ctrl->root == kNone || ctx->h_ctrl->error) return fail(ctx, EMST_EINTERNAL, "tree construction failed");
+    if (prof) HIP_TRY(hipEventRecord(E[1], st));
+
+    // ---- rounds, every query inside its own cloud's subtree (top-down)
+    TraverseArgs<3> ta = traverse_args<3>(b, n, ctx->h_ctrl->root);
+    ta.cloud_of = cloud_sorted;
+    ta.cloud_root = d_croot;
+    const int variant = (ctx->traversal == 0) ? 0 : 5;
+    if (int rc = run_rounds<3>(ctx, b, ta, n, nonempty, S.tree_height, variant, cloud_sorted, S, st)) return rc;
+    if ((int64_t)ctx->h_ctrl->edge_count != eoff) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
+    if (prof) HIP_TRY(hipEventRecord(E[2], st));
+
+    // ---- per-cloud canonical order
+    const uint32_t* order = nullptr;
+    if (int rc = sort_edges<3>(ctx, b, n, cloud_sorted, cloud_bits, &order, st)) return rc;
+    k_batch_edge_write<<<grid_for(n), 256, 0, st>>>(b.eu, b.ev, b.ed, order, cloud_sorted, d_cin, n, edges, weights,
+                                                    d2);
+    HIP_TRY(hipGetLastError());
+    if (prof) HIP_TRY(hipEventRecord(E[3], st));
+    HIP_TRY(hipStreamSynchronize(st));
+    finish_stats(ctx, S);
     return EMST_OK;
 }
 
@@ -992,6 +1413,44 @@ extern "C" int emst_build(emst_ctx* ctx, const float* d_points, int64_t n, int d
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (dim == 3) return build_impl<3>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st);
     return build_impl<2>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st);
+}
+
+
+extern "C" size_t emst_workspace_bytes_batched(int64_t total_points, int32_t n_clouds) {
+    if (total_points < 0 || total_points > 0x7FFFFFFFll || n_clouds < 1) return 0;
+    return make_batch_layout(total_points, n_clouds).total;
+}
+
+extern "C" int emst_build_batched(emst_ctx* ctx, const float* d_points, const int64_t* h_offsets,
+                                  const int32_t* h_dims, int32_t n_clouds, int32_t* d_edges, float* d_weights,
+                                  float* d_d2, int64_t* h_edge_offsets, void* d_workspace, size_t ws_bytes,
+                                  void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n_clouds < 1 || !h_offsets || !h_dims) return fail(ctx, EMST_EINVAL, "bad batch description");
+    if (h_offsets[0] != 0) return fail(ctx, EMST_EINVAL, "offsets must start at 0");
+    for (int32_t c = 0; c < n_clouds; ++c) {
+        if (h_offsets[c + 1] < h_offsets[c]) return fail(ctx, EMST_EINVAL, "offsets must not decrease");
+        if (h_dims[c] != 2 && h_dims[c] != 3) return fail(ctx, EMST_EINVAL, "dim must be 2 or 3");
+    }
+    const int64_t n = h_offsets[n_clouds];
+    if (n > 0x7FFFFFFFll) return fail(ctx, EMST_EINVAL, "too many points");
+    if (n < 2) {
+        if (h_edge_offsets)
+            for (int32_t c = 0; c <= n_clouds; ++c) h_edge_offsets[c] = 0;
+        memset(&ctx->stats, 0, sizeof(ctx->stats));
+        ctx->stats.n = n;
+        return EMST_OK;
+    }
+    int64_t m = 0;
+    for (int32_t c = 0; c < n_clouds; ++c) m += std::max<int64_t>(h_offsets[c + 1] - h_offsets[c] - 1, 0);
+    if (!d_points || !d_workspace || (m > 0 && (!d_edges || !d_weights)))
+        return fail(ctx, EMST_EINVAL, "null pointer");
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(ctx, EMST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < emst_workspace_bytes_batched(n, n_clouds)) return fail(ctx, EMST_ENOMEM, "workspace too small");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+    return batched_impl(ctx, d_points, h_offsets, h_dims, n_clouds, d_edges, d_weights, d_d2, h_edge_offsets,
+                        (char*)d_workspace, reinterpret_cast<hipStream_t>(stream));
 }
 
 // ===========================================================================

@@ -47,7 +47,17 @@ struct TraverseArgs {
     bool first;  // first round: every point is its own component
     const uint32_t* leaf_parent;
     const Up* up;
+    // batches: cloud of every sorted position and subtree root of every
+    // cloud (kNone for a cloud of one point); null for one cloud
+    const uint32_t* cloud_of;
+    const uint32_t* cloud_root;
 };
+
+// Where a top-down search of query i starts.
+template <int DIM>
+__device__ __forceinline__ uint32_t start_node(const TraverseArgs<DIM>& a, int64_t i) {
+    return a.cloud_root ? a.cloud_root[a.cloud_of[i]] : a.root;
+}
 
 // Candidate order of Algorithm 2's leaf update, made strict: (D, j).
 __device__ __forceinline__ bool better(float d, uint32_t j, float best_d, uint32_t best_j) {
@@ -178,7 +188,8 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
         for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
         c = a.labels[i];
         float radius = bitsf(a.ub[c]);
-        descend<DIM, STACK, COUNT>(a, a.root, p, c, radius, best_d, best_j, n_int, n_leaf, n_eval);
+        const uint32_t root = start_node<DIM>(a, i);
+        if (root != kNone) descend<DIM, STACK, COUNT>(a, root, p, c, radius, best_d, best_j, n_int, n_leaf, n_eval);
     }
     finish_query<DIM>(a, i, c, best_d, best_j);
     flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
@@ -613,10 +624,10 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             mask = 2u >> (link & 1u);
             u = a.up[anc];
         } else {
-            node = a.root;
-            mask = 3u;
+            node = start_node<DIM>(a, i);
+            mask = node == kNone ? 0u : 3u;
         }
-        for (int64_t guard = 0;; ++guard) {
+        for (int64_t guard = 0; mask; ++guard) {
             if (guard > 2 * a.n + 256) {
                 atomicOr(&a.ctrl->error, kErrStack);
                 break;

@@ -1,0 +1,174 @@
+"""Continuous-batching EMST server on one GPU.
+
+Requests (point clouds) arrive over time.  Each of `workers` threads owns
+one EMST context, one HIP stream and a fixed share of the HBM budget.  A
+free worker immediately admits every queued request that fits its budget
+(oldest first, at least one) and solves them together with
+``emst_build_batched``; requests that arrive meanwhile wait for the next free
+worker.  Several batches are therefore in flight on the device at once,
+and a worker whose batch ends takes new requests right away (admission by
+memory footprint, at batch granularity).  Every request's result is exactly
+the EMST of its cloud alone: a batch only groups independent clouds.
+
+Latency of a request = completion on the host - arrival.  The server
+reports p50/p99 latency and Mpoints/s over the run.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import Context, workspace_bytes_batched
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    points: np.ndarray          # [n, dim] float32 (host)
+    arrival: float = 0.0        # seconds on the server clock
+    start: float = 0.0
+    done: float = 0.0
+    edges: Optional[np.ndarray] = None
+    weights: Optional[np.ndarray] = None
+    d2: Optional[np.ndarray] = None
+    error: Optional[str] = None
+    batch: int = -1
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Server:
+    """`budget_bytes` is the device memory all workers together may use for
+    inputs, outputs and workspaces; each worker gets an equal share."""
+
+    def __init__(self, workers: int = 2, budget_bytes: int = 8 << 30, max_batch: int = 256,
+                 device: int = 0):
+        import torch
+        self.device = device
+        self.workers = workers
+        self.share = budget_bytes // workers
+        self.max_batch = max_batch
+        self._queue: collections.deque = collections.deque()
+        self._cv = threading.Condition()
+        self._closed = False
+        self._threads: List[threading.Thread] = []
+        self._ctx = [Context(device) for _ in range(workers)]
+        self._streams = [torch.cuda.Stream(device=device) for _ in range(workers)]
+        self._batches = 0
+        self.t0 = time.perf_counter()
+
+    # ---- footprint of one request inside a batch
+    @staticmethod
+    def footprint(n: int, dim: int) -> int:
+        # points + outputs + this request's share of the batched workspace
+        return n * dim * 4 + max(n - 1, 0) * 16 + workspace_bytes_batched(max(n, 2), 1)
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request) -> None:
+        n, dim = req.points.shape
+        if self.footprint(n, dim) > self.share:
+            req.error = "EMST_ENOMEM: request larger than a worker's memory share"
+            req.done = self.now()
+            return
+        with self._cv:
+            req.arrival = self.now() if req.arrival == 0.0 else req.arrival
+            self._queue.append(req)
+            self._cv.notify()
+
+    def start(self) -> None:
+        for w in range(self.workers):
+            t = threading.Thread(target=self._run, args=(w,), daemon=True)
+            t.start()
+            self._threads.append(t)
+
+    def close(self) -> None:
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        for t in self._threads:
+            t.join()
+
+    def _admit(self) -> List[Request]:
+        batch, used = [], 0
+        while self._queue and len(batch) < self.max_batch:
+            r = self._queue[0]
+            f = self.footprint(*r.points.shape)
+            if batch and used + f > self.share:
+                break
+            batch.append(self._queue.popleft())
+            used += f
+        return batch
+
+    def _run(self, w: int) -> None:
+        import torch
+        ctx, stream = self._ctx[w], self._streams[w]
+        while True:
+            with self._cv:
+                while not self._queue and not self._closed:
+                    self._cv.wait()
+                if not self._queue and self._closed:
+                    return
+                batch = self._admit()
+                bid = self._batches
+                self._batches += 1
+            t = self.now()
+            for r in batch:
+                r.start, r.batch = t, bid
+            try:
+                with torch.cuda.stream(stream):
+                    dev = [torch.from_numpy(r.points).to(f"cuda:{self.device}", non_blocking=False)
+                           for r in batch]
+                    out = ctx.build_batched(dev, stream=stream)
+                    res = [(e.cpu().numpy(), wt.cpu().numpy(), d.cpu().numpy()) for e, wt, d in out]
+                stream.synchronize()
+                t_done = self.now()
+                for r, (e, wt, d) in zip(batch, res):
+                    r.edges, r.weights, r.d2 = e, wt, d
+                    r.done = t_done
+            except Exception as exc:  # a failing batch fails its own requests only
+                t_done = self.now()
+                for r in batch:
+                    r.error = str(exc)
+                    r.done = t_done
+
+
+def replay(server: Server, requests: List[Request], arrivals: List[float],
+           on_submit: Optional[Callable[[Request], None]] = None) -> float:
+    """Submit `requests` at the given arrival times (seconds from now) and
+    wait for all of them; returns the makespan in seconds."""
+    server.start()
+    t_begin = server.now()
+    for r, a in zip(requests, arrivals):
+        target = t_begin + a
+        while True:
+            dt = target - server.now()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.002))
+        r.arrival = server.now()
+        server.submit(r)
+        if on_submit:
+            on_submit(r)
+    server.close()
+    return max(r.done for r in requests) - t_begin
+
+
+def summary(requests: List[Request], makespan: float) -> dict:
+    ok = [r for r in requests if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    pts = sum(r.points.shape[0] for r in ok)
+    return {
+        "requests": len(requests), "failed": len(requests) - len(ok),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3), "mpoints_per_s": pts / makespan / 1e6 if makespan > 0 else 0.0,
+        "makespan_s": makespan, "batches": len({r.batch for r in ok}),
+    }

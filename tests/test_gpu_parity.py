@@ -266,3 +266,62 @@ def test_clustered3d_2m(ctx):
     for variant in (0, 1, 2, 3, 4, 5, 6):
         print(f"clustered3d_2m variant={variant}", flush=True)
         assert_same(run(ctx, pts, variant), ref, f"clustered3d_2m v{variant}")
+
+
+# ---------------------------------------------------------------------------
+# batches
+
+
+def run_batched(ctx, clouds):
+    ts = [torch.from_numpy(np.ascontiguousarray(c, np.float32)).cuda() for c in clouds]
+    out = ctx.build_batched(ts)
+    torch.cuda.synchronize()
+    return [(e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()) for e, w, d in out]
+
+
+def test_batched_small_mixed(ctx):
+    rng = np.random.default_rng(11)
+    clouds = []
+    for c in range(40):
+        n = int(rng.choice([0, 1, 2, 3, 17, 64, 300, 1500]))
+        dim = int(rng.choice([2, 3]))
+        kind = ("uniform", "int", "dup", "outlier")[c % 4]
+        clouds.append(W.small_random(n, dim, 1000 + c, kind))
+    res = run_batched(ctx, clouds)
+    for c, (pts, got) in enumerate(zip(clouds, res)):
+        assert_same(got, oracle.prim(pts), f"cloud {c} n={len(pts)} d={pts.shape[1]}")
+
+
+def test_batched_equals_solo(ctx):
+    clouds = W.batched_clouds(n_clouds=24, seed=21, lo=500, hi=20_000)
+    res = run_batched(ctx, clouds)
+    for c, (pts, got) in enumerate(zip(clouds, res)):
+        solo = run(ctx, pts)
+        for a, b in zip(got, solo):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), f"cloud {c}"
+
+
+def test_batched_errors(ctx):
+    import paper_2207_00514_amd as emst
+    clouds = [W.small_random(100, 3, 1), W.small_random(50, 2, 2)]
+    clouds[1][7, 0] = np.nan
+    with pytest.raises(emst.EmstError) as ei:
+        run_batched(ctx, clouds)
+    assert ei.value.name == "EMST_ENONFINITE" and "cloud 1" in str(ei.value)
+    # two single points: no edges at all
+    res = run_batched(ctx, [np.zeros((1, 3), np.float32), np.ones((1, 2), np.float32)])
+    assert all(r[0].shape == (0, 2) for r in res)
+    # the context still works
+    pts = W.small_random(300, 3, 1)
+    assert_same(run(ctx, pts), oracle.prim(pts), "after batch errors")
+
+
+def test_batched_512_clouds_sampled(ctx):
+    clouds = W.batched_clouds()  # 512 clouds, ~19M points
+    res = run_batched(ctx, clouds)
+    rng = np.random.default_rng(0)
+    for c in sorted(rng.choice(len(clouds), 12, replace=False).tolist()):
+        print(f"batched cloud {c} n={len(clouds[c])} dim={clouds[c].shape[1]}", flush=True)
+        assert_same(res[c], oracle.emst(clouds[c], threads=16), f"cloud {c}")
+    for c, r in enumerate(res):
+        assert r[0].shape[0] == max(len(clouds[c]) - 1, 0)
