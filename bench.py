@@ -43,7 +43,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="clustered3d_2m",
-                    choices=["uniform2d_10k", "clustered3d_2m", "cosmology3d_37m"])
+                    choices=["uniform2d_10k", "clustered3d_2m", "cosmology3d_37m", "batched512", "serving"])
+    ap.add_argument("--requests", type=int, default=300, help="serving: requests per measured run")
     ap.add_argument("--n", type=int, default=None, help="resize the workload (same recipe)")
     ap.add_argument("--variant", type=int, default=None, help="traversal variant (default: library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -63,6 +64,10 @@ def main() -> int:
     import paper_2207_00514_amd as emst
     from paper_2207_00514_amd import workloads as W
 
+    if args.workload == "batched512":
+        return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     spec = W.WORKLOADS[args.workload]
     pts_np = W.make(args.workload, args.n)
     n, dim = pts_np.shape
@@ -175,6 +180,127 @@ def main() -> int:
 
     print(json.dumps(line), flush=True)
     return 0 if line.get("parity", "bit-exact") == "bit-exact" else 1
+
+
+def bench_batched(args) -> int:
+    """512 clouds (log-uniform 1e3..2e5 points, half 2D uniform, half 3D
+    mixtures): one batched pass vs one emst_build per cloud, same GPU and
+    resident inputs."""
+    import numpy as np
+    import torch
+
+    import paper_2207_00514_amd as emst
+    from paper_2207_00514_amd import workloads as W
+
+    clouds = W.batched_clouds()
+    sizes = [len(c) for c in clouds]
+    dims = [c.shape[1] for c in clouds]
+    total = sum(sizes)
+    dev = torch.device("cuda:0")
+    flat = torch.from_numpy(np.concatenate([c.reshape(-1) for c in clouds])).to(dev)
+    per = [torch.from_numpy(c).to(dev) for c in clouds]
+    ctx = emst.Context(0)
+    ctx.workspace(max(sizes), 3)
+    ctx.build_batched_flat(flat, sizes, dims)  # sizes the batched workspace
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        ctx.build_batched_flat(flat, sizes, dims)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.build_batched_flat(flat, sizes, dims)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    ctx1 = emst.Context(0)
+    ctx1.workspace(max(sizes), 3)
+    for c in per[:8]:
+        ctx1.build(c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solo = [ctx1.build(c) for c in per]
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    # parity of every cloud, batched vs alone
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(out, solo))
+    line = {
+        "metric": METRIC, "value": round(total / t_batched / 1e6, 3), "unit": "Mpoints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_batched * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched512", "clouds": len(clouds), "points": int(total), "seed": 4},
+        "one_cloud_per_launch": {"value": round(total / t_solo / 1e6, 3), "unit": "Mpoints/s",
+                                 "ms": round(t_solo * 1e3, 3)},
+        "batched_speedup": round(t_solo / t_batched, 2),
+        "batched_equals_solo": bool(same),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        rng = np.random.default_rng(0)
+        pick = rng.choice(len(clouds), 16, replace=False)
+        c0 = time.perf_counter()
+        npts = 0
+        for c in pick:
+            ref = oracle.emst(clouds[c], threads=threads)
+            npts += len(clouds[c])
+            e = out[c][0].cpu().numpy()
+            if not np.array_equal(e, ref.edges):
+                same = False
+        c1 = time.perf_counter()
+        line["cpu_baseline"] = {"value": round(npts / (c1 - c0) / 1e6, 4), "unit": "Mpoints/s", "cores": threads,
+                                "kind": "oracle", "sample": f"16 of the 512 clouds ({npts} points), "
+                                f"Prim below 4000 points else kd-tree Boruvka, {c1 - c0:.2f} s"}
+        line["parity"] = "bit-exact" if same else "MISMATCH"
+    print(json.dumps(line), flush=True)
+    return 0 if same else 1
+
+
+def bench_serving(args) -> int:
+    """Poisson stream of 3D requests (lognormal sizes, median 5e4, sigma 1.2,
+    clipped to [5e3, 4e6]; uniform or clustered).  The continuous-batching
+    server is compared with a one-request-per-launch FIFO server on the same
+    arrival trace at 0.5 and 0.9 of the batched saturation rate."""
+    import numpy as np
+    import torch
+
+    from paper_2207_00514_amd import serve
+    from paper_2207_00514_amd import workloads as W
+
+    count = args.requests
+    sizes = W.request_sizes(count + 64, seed=5)
+    clouds = [W.request_cloud(int(n), seed=5000 + i) for i, n in enumerate(sizes)]
+    warm, clouds = clouds[:64], clouds[64:]
+
+    def run(workers, max_batch, rate, reqs):
+        srv = serve.Server(workers=workers, max_batch=max_batch, budget_bytes=16 << 30)
+        rq = [serve.Request(i, c) for i, c in enumerate(reqs)]
+        if rate is None:
+            arr = [0.0] * len(rq)
+        else:
+            gaps = np.random.default_rng(7).exponential(1.0 / rate, len(rq))
+            arr = list(np.cumsum(gaps) - gaps[0])
+        span = serve.replay(srv, rq, arr)
+        return serve.summary(rq, span), rq
+
+    run(2, 64, None, warm)                       # warm-up (kernels, allocator)
+    burst, _ = run(2, 64, None, clouds[:min(count, 150)])
+    mu = burst["requests"] / burst["makespan_s"]  # saturated requests/s
+    res = {}
+    for frac in (0.5, 0.9):
+        lam = frac * mu
+        b, rq = run(2, 64, lam, clouds)
+        f, rq1 = run(1, 1, lam, clouds)
+        same = all(np.array_equal(a.edges, c.edges) for a, c in zip(rq, rq1) if a.error is None)
+        res[f"{frac}"] = {"qps": round(lam, 1), "batched": b, "fifo_one_per_launch": f, "results_equal": same}
+    b9 = res["0.9"]["batched"]
+    line = {
+        "metric": METRIC, "value": round(b9["mpoints_per_s"], 3), "unit": "Mpoints/s", "n_gpus": 1,
+        "steps": count, "warmup": 64, "ms_per_step": round(b9["mean_ms"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving", "requests": count, "seed": 5, "saturation_qps": round(mu, 1)},
+        "p50_ms": round(b9["p50_ms"], 3), "p99_ms": round(b9["p99_ms"], 3), "runs": res,
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if all(v["results_equal"] for v in res.values()) else 1
 
 
 if __name__ == "__main__":
