@@ -406,19 +406,18 @@ __global__ __launch_bounds__(256) void k_runs_down(const uint32_t* __restrict__ 
     }
 }
 
-// Record k holds the children [lo_k, k] and [k+1, hi_k].
-template <int DIM>
+// Record k holds the children [lo_k, k] and [k+1, hi_k]; their labels go to
+// lab2[k], one 8-byte entry per record.
 __global__ __launch_bounds__(256) void k_record_labels(const uint32_t* __restrict__ labels,
                                                        const uint32_t* __restrict__ run_start,
                                                        const uint32_t* __restrict__ rlo,
-                                                       const uint32_t* __restrict__ rhi, Rec<DIM>* recs,
+                                                       const uint32_t* __restrict__ rhi, uint2* __restrict__ lab2,
                                                        int64_t m) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     const uint32_t lo = rlo[k], hi = rhi[k];
     const uint32_t a = labels[k], b = labels[k + 1];
-    *label_slot<DIM>(&recs[k], 0) = (run_start[k] <= lo) ? a : kInvalid;
-    *label_slot<DIM>(&recs[k], 1) = (run_start[hi] <= (uint32_t)(k + 1)) ? b : kInvalid;
+    lab2[k] = make_uint2((run_start[k] <= lo) ? a : kInvalid, (run_start[hi] <= (uint32_t)(k + 1)) ? b : kInvalid);
 }
 
 // Optimization 2 (Section 3): a Morton-adjacent pair with different labels
@@ -797,7 +796,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint32_t* __rest
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -828,6 +827,7 @@ static Layout make_layout(int64_t n, int dim) {
     L.orig = take(4 * N);
     L.pos = take(4 * N);
     L.recs = take(M * (dim == 3 ? sizeof(Rec<3>) : sizeof(Rec<2>)));
+    L.lab2 = take(8 * M);
     L.node_parent = take(4 * M);
     L.leaf_parent = take(4 * N);
     L.up = take(sizeof(Up) * M);
@@ -884,7 +884,7 @@ struct emst_ctx {
     std::string err;
     bool profiling = false;
     bool counting = false;
-    int traversal = 5;
+    int traversal = 7;
     emst_stats stats;
     Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
     hipEvent_t ev[2 * 64 + 8];
@@ -971,7 +971,7 @@ extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
     return EMST_OK;
 }
 extern "C" int emst_set_traversal(emst_ctx* ctx, int variant) {
-    if (!ctx || variant < 0 || variant > 6) return EMST_EINVAL;
+    if (!ctx || variant < 0 || variant > 9) return EMST_EINVAL;
     ctx->traversal = variant;
     return EMST_OK;
 }
@@ -1012,14 +1012,13 @@ MortonParams morton_params(const float* lo, const float* hi, int dim, int bits) 
     return mp;
 }
 
-template <int DIM>
 hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_start, uint32_t* run_part, const uint32_t* rlo,
-                            const uint32_t* rhi, Rec<DIM>* recs, int64_t n, hipStream_t st) {
+                            const uint32_t* rhi, uint2* lab2, int64_t n, hipStream_t st) {
     const int nb = (int)((n + kRunTile - 1) / kRunTile);
     k_runs_reduce<<<nb, 256, 0, st>>>(labels, n, run_part);
     k_runs_scan<<<1, 1024, 0, st>>>(run_part, nb);
     k_runs_down<<<nb, 256, 0, st>>>(labels, n, run_part, run_start);
-    k_record_labels<DIM><<<grid_for(n - 1), 256, 0, st>>>(labels, run_start, rlo, rhi, recs, n - 1);
+    k_record_labels<<<grid_for(n - 1), 256, 0, st>>>(labels, run_start, rlo, rhi, lab2, n - 1);
     return hipGetLastError();
 }
 
@@ -1032,6 +1031,7 @@ struct Bufs {
     float* spts;
     uint32_t *orig, *pos;
     Rec<DIM>* recs;
+    uint2* lab2;
     uint32_t *node_parent, *leaf_parent;
     Up* up;
     uint64_t* exch;
@@ -1053,6 +1053,7 @@ Bufs<DIM> carve(char* ws, const Layout& L) {
     b.orig = reinterpret_cast<uint32_t*>(ws + L.orig);
     b.pos = reinterpret_cast<uint32_t*>(ws + L.pos);
     b.recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
+    b.lab2 = reinterpret_cast<uint2*>(ws + L.lab2);
     b.node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
     b.leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
     b.up = reinterpret_cast<Up*>(ws + L.up);
@@ -1081,7 +1082,7 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     ta.spts = b.spts; ta.labels = b.labels; ta.orig = b.orig; ta.ub = b.ub; ta.recs = b.recs; ta.root = root;
     ta.n = n; ta.cand_d = b.cand_d; ta.cand_j = b.cand_j; ta.compkey = b.compkey; ta.compmax = b.compmax;
     ta.ctrl = b.ctrl; ta.first = true; ta.leaf_parent = b.leaf_parent; ta.up = b.up;
-    ta.cloud_of = nullptr; ta.cloud_root = nullptr;
+    ta.cloud_of = nullptr; ta.cloud_root = nullptr; ta.lab2 = b.lab2;
     return ta;
 }
 
@@ -1106,7 +1107,7 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
     while (ncomp > target) {
         if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
         S.components[round] = ncomp;
-        HIP_TRY(propagate_labels<DIM>(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.recs, n, st));
+        HIP_TRY(propagate_labels(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.lab2, n, st));
         if (round == 0) k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, n, b.ub, b.ctrl);
         else k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, n, b.ub, b.ctrl);
         if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
@@ -1375,7 +1376,7 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     TraverseArgs<3> ta = traverse_args<3>(b, n, ctx->h_ctrl->root);
     ta.cloud_of = cloud_sorted;
     ta.cloud_root = d_croot;
-    const int variant = (ctx->traversal == 0) ? 0 : 5;
+    const int variant = (ctx->traversal == 0 || ctx->traversal == 5 || ctx->traversal == 8) ? ctx->traversal : 7;
     if (int rc = run_rounds<3>(ctx, b, ta, n, nonempty, S.tree_height, variant, cloud_sorted, S, st)) return rc;
     if ((int64_t)ctx->h_ctrl->edge_count != eoff) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
@@ -1469,7 +1470,7 @@ __global__ __launch_bounds__(256) void k_test_prep(const uint32_t* __restrict__ 
     if (i + 1 < n) exch[i] = ~0ull;
 }
 
-__global__ __launch_bounds__(256) void k_test_extract(const Rec<3>* __restrict__ recs,
+__global__ __launch_bounds__(256) void k_test_extract(const Rec<3>* __restrict__ recs, const uint2* __restrict__ lab2,
                                                       const uint32_t* __restrict__ node_parent, int64_t m,
                                                       int32_t* __restrict__ left, int32_t* __restrict__ right,
                                                       uint32_t* __restrict__ label) {
@@ -1481,10 +1482,11 @@ __global__ __launch_bounds__(256) void k_test_extract(const Rec<3>* __restrict__
     right[k] = (c1.ref & kLeafFlag) ? -(int32_t)(c1.ref & ~kLeafFlag) - 1 : (int32_t)c1.ref;
     const uint32_t link = node_parent[k];
     if (link == kNone) {
-        label[k] = (c0.lab == c1.lab) ? c0.lab : kInvalid;
+        const uint2 L = lab2[k];
+        label[k] = (L.x == L.y) ? L.x : kInvalid;
     } else {
-        Rec<3> pr = recs[link >> 1];
-        label[k] = *label_slot<3>(&pr, (int)(link & 1u));
+        const uint2 L = lab2[link >> 1];
+        label[k] = (link & 1u) ? L.y : L.x;
     }
 }
 
@@ -1515,14 +1517,15 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint32_t* run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
     uint32_t* run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
     Rec<3>* recs = reinterpret_cast<Rec<3>*>(ws + L.recs);
+    uint2* lab2 = reinterpret_cast<uint2*>(ws + L.lab2);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
     uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
     k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
     k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch);
     k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, leaf_parent, node_parent, exch, rlo, rhi,
                                             ctrl);
-    HIP_TRY(propagate_labels<3>(labels, run_start, run_part, rlo, rhi, recs, n, st));
-    k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, node_parent, n - 1, d_left, d_right, d_label);
+    HIP_TRY(propagate_labels(labels, run_start, run_part, rlo, rhi, lab2, n, st));
+    k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, lab2, node_parent, n - 1, d_left, d_right, d_label);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

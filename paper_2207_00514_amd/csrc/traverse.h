@@ -51,6 +51,7 @@ struct TraverseArgs {
     // cloud (kNone for a cloud of one point); null for one cloud
     const uint32_t* cloud_of;
     const uint32_t* cloud_root;
+    const uint2* lab2;  // per record: component labels of its two children (rewritten every round)
 };
 
 // Where a top-down search of query i starts.
@@ -129,6 +130,11 @@ __device__ __forceinline__ void descend(const TraverseArgs<DIM>& a, uint32_t nod
         const Rec<DIM> r = a.recs[node];
         Child<DIM> ch[2];
         unpack<DIM>(r, ch[0], ch[1]);
+        {
+            const uint2 L = a.lab2[node];
+            ch[0].lab = L.x;
+            ch[1].lab = L.y;
+        }
         bool go[2] = {false, false};
         float dd[2] = {0.f, 0.f};
 #pragma unroll
@@ -229,6 +235,11 @@ __global__ __launch_bounds__(256) void k_traverse_up(TraverseArgs<DIM> a) {
             const Rec<DIM> r = a.recs[node];
             Child<DIM> ch[2];
             unpack<DIM>(r, ch[0], ch[1]);
+            {
+                const uint2 L = a.lab2[node];
+                ch[0].lab = L.x;
+                ch[1].lab = L.y;
+            }
             bool go[2] = {false, false};
             float dd[2] = {0.f, 0.f};
 #pragma unroll
@@ -337,6 +348,11 @@ __global__ __launch_bounds__(256) void k_traverse_wave(TraverseArgs<DIM> a) {
         const Rec<DIM> r = a.recs[node];
         Child<DIM> ch[2];
         unpack<DIM>(r, ch[0], ch[1]);
+        {
+            const uint2 L = a.lab2[node];
+            ch[0].lab = L.x;
+            ch[1].lab = L.y;
+        }
         const bool in = (mask & me) != 0ull;
         bool go[2] = {false, false};
         float dd[2] = {0.f, 0.f};
@@ -514,6 +530,11 @@ __global__ __launch_bounds__(256) void k_traverse_pool(TraverseArgs<DIM> a) {
         const Rec<DIM> r = a.recs[node];
         Child<DIM> ch[2];
         unpack<DIM>(r, ch[0], ch[1]);
+        {
+            const uint2 L = a.lab2[node];
+            ch[0].lab = L.x;
+            ch[1].lab = L.y;
+        }
         bool go[2] = {false, false};
         float dd[2] = {0.f, 0.f};
 #pragma unroll
@@ -597,9 +618,7 @@ __global__ __launch_bounds__(256) void k_traverse_pool(TraverseArgs<DIM> a) {
 // so a wave's accesses fall in distinct banks) with the deeper entries
 // spilled to a private array only when a search nests deeper than that.
 
-constexpr int kLdsDepth = 16;
-
-template <int DIM, int STACK, bool COUNT, bool UPWARD>
+template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16>
 __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
     __shared__ uint2 lds[kLdsDepth][256];
     const int t = threadIdx.x;
@@ -635,6 +654,11 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             const Rec<DIM> r = a.recs[node];
             Child<DIM> c0, c1;
             unpack<DIM>(r, c0, c1);
+            {
+                const uint2 L = a.lab2[node];
+                c0.lab = L.x;
+                c1.lab = L.y;
+            }
             const float d0 = boxdist<DIM>(p, c0.lo, c0.hi);
             const float d1 = boxdist<DIM>(p, c1.lo, c1.hi);
             const bool in0 = (mask & 1u) && c0.lab != c;
@@ -734,6 +758,15 @@ hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count
     } else if (variant == 6) {
         if (count) k_traverse_fast<DIM, STACK, true, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_fast<DIM, STACK, false, true><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 7) {
+        if (count) k_traverse_fast<DIM, STACK, true, false, 8><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false, 8><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 8) {
+        if (count) k_traverse_fast<DIM, STACK, true, false, 4><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false, 4><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 9) {
+        if (count) k_traverse_fast<DIM, STACK, true, true, 8><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, true, 8><<<grid, 256, 0, st>>>(a);
     } else if (variant == 3 || variant == 4) {
         // persistent: enough waves to fill every CU several times over
         const unsigned pgrid = std::min<unsigned>(grid, 2048u);
