@@ -431,37 +431,63 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, 
                                                 const uint32_t* __restrict__ cloud_of, int64_t n, uint32_t* ub,
                                                 Ctrl* ctrl) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
     if (k == 0) {
         ctrl->ncomp_next = 0u;
         ctrl->trav_next = 0ull;
     }
-    uint32_t lab = kNone, v = kInfBits;
-    if (k < n) {
+    // every position loads itself once; the right neighbour comes from the
+    // next lane (the last lane of a wave loads it)
+    const bool valid = k < n;
+    uint32_t lab = kNone, cl = 0u;
+    float p[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) p[c] = 0.f;
+    if (valid) {
         lab = labels[k];
-        float p[DIM];
+        if (cloud_of) cl = cloud_of[k];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) p[c] = spts[k * DIM + c];
-        const uint32_t cl = cloud_of ? cloud_of[k] : 0u;
-        if (k > 0 && labels[k - 1] != lab && (!cloud_of || cloud_of[k - 1] == cl)) {
-            float q[DIM];
+    }
+    uint32_t rlab = __shfl_down(lab, 1), rcl = __shfl_down(cl, 1);
+    float q[DIM];
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) q[c] = spts[(k - 1) * DIM + c];
-            v = min(v, fbits(sqdist<DIM>(q, p)));
-        }
-        if (k + 1 < n && labels[k + 1] != lab && (!cloud_of || cloud_of[k + 1] == cl)) {
-            float q[DIM];
+    for (int c = 0; c < DIM; ++c) q[c] = __shfl_down(p[c], 1);
+    if (lane == 63) {
+        rlab = kNone;
+        if (k + 1 < n) {
+            rlab = labels[k + 1];
+            rcl = cloud_of ? cloud_of[k + 1] : 0u;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) q[c] = spts[(k + 1) * DIM + c];
-            v = min(v, fbits(sqdist<DIM>(p, q)));
         }
     }
+    // D of the pair (k, k+1) if it joins two components of one cloud
+    const bool right = valid && k + 1 < n && rlab != lab && rcl == cl;
+    const uint32_t dr = right ? fbits(sqdist<DIM>(p, q)) : kInfBits;
+    // the pair (k-1, k) was computed by the previous lane
+    uint32_t dl = __shfl_up(dr, 1);
+    if (lane == 0) {
+        dl = kInfBits;
+        if (valid && k > 0) {
+            const uint32_t llab = labels[k - 1];
+            const uint32_t lcl = cloud_of ? cloud_of[k - 1] : 0u;
+            if (llab != lab && lcl == cl) {
+                float o[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) o[c] = spts[(k - 1) * DIM + c];
+                dl = fbits(sqdist<DIM>(o, p));
+            }
+        }
+    }
+    uint32_t v = min(dl, dr);
     if (FIRST) {
-        if (k < n) ub[k] = v;
+        if (valid) ub[k] = v;
         return;
     }
     bool run_end;
     v = wave_seg_min<uint32_t>(lab, v, &run_end);
-    if (k < n && run_end && v != kInfBits) atomicMin(&ub[lab], v);
+    if (valid && run_end && v != kInfBits) atomicMin(&ub[lab], v);
 }
 
 // Stage B of the component minimum: among the points whose candidate matches

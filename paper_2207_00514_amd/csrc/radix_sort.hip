@@ -10,9 +10,10 @@
 //              stable rank of each item among equal digits comes from 8
 //              wave ballots (lanes with the same digit), per-(slot, wave)
 //              digit counts are staged in LDS and prefix-summed per digit,
-//              and the items are scattered to their global positions
-//              (every block first turns the 256 digit totals into digit
-//              start offsets itself).
+//              and the tile is staged in LDS in digit order, so every run of
+//              equal digits is written by consecutive threads to
+//              consecutive addresses (every block first turns the 256
+//              digit totals into digit start offsets itself).
 // Items are loaded striped (item s of thread t is tile element s*256 + t),
 // so the (slot, wave, lane) order equals the input order and the sort is
 // stable.
@@ -83,9 +84,15 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
                                                            int64_t tiles_per_block,
                                                            const uint32_t* __restrict__ hist, int nb,
                                                            const uint32_t* __restrict__ row_total) {
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t gbase[256];   // running global start of every digit for this block
+    __shared__ uint32_t lstart[256];  // tile-local start of every digit
     __shared__ uint32_t wsum[kRsWaves];
-    __shared__ uint32_t cnt[kRsItems][kRsWaves][256];
+    // per-(slot, wave, digit) counts, then offsets; afterwards the same
+    // storage stages the tile's keys and values in digit order
+    __shared__ __attribute__((aligned(16))) uint32_t cnt[kRsItems][kRsWaves][256];
+    static_assert(sizeof(cnt) >= kRsTile * (sizeof(uint64_t) + sizeof(uint32_t)), "staging fits");
+    uint64_t* skey = reinterpret_cast<uint64_t*>(&cnt[0][0][0]);
+    uint32_t* sval = reinterpret_cast<uint32_t*>(skey + kRsTile);
     const int t = threadIdx.x, w = t / 64, lane = t & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     {
@@ -101,7 +108,7 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
         __syncthreads();
         uint32_t before = 0;
         for (int k = 0; k < w; ++k) before += wsum[k];
-        base[t] = (x - v) + before + hist[(int64_t)t * nb + blockIdx.x];
+        gbase[t] = (x - v) + before + hist[(int64_t)t * nb + blockIdx.x];
     }
     const int64_t first_tile = (int64_t)blockIdx.x * tiles_per_block;
     const int64_t num_tiles = (n + kRsTile - 1) / kRsTile;
@@ -110,6 +117,7 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
         for (int k = t; k < kRsItems * kRsWaves * 256; k += kRsThreads) (&cnt[0][0][0])[k] = 0;
         __syncthreads();
         const int64_t tb = tile * kRsTile;
+        const int valid = (int)min((int64_t)kRsTile, n - tb);
         uint64_t key[kRsItems];
         uint32_t val[kRsItems], dig[kRsItems], rank[kRsItems];
         bool ok[kRsItems];
@@ -134,8 +142,11 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
             if (ok[s] && rank[s] == 0) cnt[s][w][dig[s]] = (uint32_t)__popcll(peers);
         }
         __syncthreads();
+        // per digit: offsets of every (slot, wave) group inside the digit,
+        // and the digit's tile total
+        uint32_t total;
         {
-            uint32_t off = base[t];
+            uint32_t off = 0;
 #pragma unroll
             for (int s = 0; s < kRsItems; ++s)
 #pragma unroll
@@ -144,17 +155,48 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
                     cnt[s][ww][t] = off;
                     off += c;
                 }
-            base[t] = off;
+            total = off;
+            // tile-local start of digit t: exclusive scan of the totals
+            uint32_t x = total;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) wsum[w] = x;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int k = 0; k < w; ++k) before += wsum[k];
+            lstart[t] = x - total + before;
         }
         __syncthreads();
+        uint32_t lpos[kRsItems];
+#pragma unroll
+        for (int s = 0; s < kRsItems; ++s)
+            lpos[s] = ok[s] ? lstart[dig[s]] + cnt[s][w][dig[s]] + rank[s] : 0u;
+        __syncthreads();  // cnt is reused for staging from here on
 #pragma unroll
         for (int s = 0; s < kRsItems; ++s) {
             if (ok[s]) {
-                const uint32_t dst = cnt[s][w][dig[s]] + rank[s];
-                kout[dst] = key[s];
-                vout[dst] = val[s];
+                skey[lpos[s]] = key[s];
+                sval[lpos[s]] = val[s];
             }
         }
+        __syncthreads();
+        // consecutive threads write consecutive positions of each digit run
+#pragma unroll
+        for (int s = 0; s < kRsItems; ++s) {
+            const int lp = s * kRsThreads + t;
+            if (lp < valid) {
+                const uint64_t k = skey[lp];
+                const uint32_t d = (uint32_t)(k >> shift) & 255u;
+                const uint32_t dst = gbase[d] + (uint32_t)lp - lstart[d];
+                kout[dst] = k;
+                vout[dst] = sval[lp];
+            }
+        }
+        __syncthreads();
+        gbase[t] += total;
         __syncthreads();
     }
 }
