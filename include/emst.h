@@ -71,7 +71,7 @@ const char *emst_last_error(const emst_ctx *ctx);
 
 /* Exact number of workspace bytes emst_build needs for n points of
  * dimension dim (0 for invalid arguments).  Grows linearly in n, about
- * 150 bytes per point in 3D. */
+ * 225 bytes per point in 3D. */
 size_t emst_workspace_bytes(int64_t n, int dim);
 
 /*

@@ -36,6 +36,19 @@ int emst_test_tree_from_codes(emst_ctx *ctx, const uint64_t *d_codes, int64_t n,
                               size_t ws_bytes, void *stream);
 
 /*
+ * The tree construction of emst_build on given 3D points (Morton codes,
+ * sort, hierarchy, box fit).  For every internal node k in [0, n-2]:
+ *   d_left[k], d_right[k]   child: internal node index >= 0, or -(j+1) for
+ *                           the leaf of ORIGINAL point index j
+ *   d_lo[3k..3k+2], d_hi[3k..3k+2]   the node's bounding box
+ * (the union of its two child boxes as the traversal sees them).
+ * *root_out (host) receives the root.  2 <= n <= 2^31-1, d_points [n][3].
+ */
+int emst_test_tree_boxes(emst_ctx *ctx, const float *d_points, int64_t n, int32_t *d_left,
+                         int32_t *d_right, float *d_lo, float *d_hi, int32_t *root_out,
+                         void *d_workspace, size_t ws_bytes, void *stream);
+
+/*
  * The radix sort of the tree construction: sorts the n pairs
  * (d_keys[i], d_vals[i]) in place, stably, by key bits [0, 64).
  */

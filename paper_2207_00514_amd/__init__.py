@@ -31,7 +31,7 @@ EXPORTS = [
     "emst_create", "emst_destroy", "emst_last_error", "emst_workspace_bytes", "emst_build",
     "emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_get_stats",
     "emst_test_tree_from_codes", "emst_test_radix_sort",
-    "emst_workspace_bytes_batched", "emst_build_batched",
+    "emst_workspace_bytes_batched", "emst_build_batched", "emst_test_tree_boxes",
 ]
 
 
@@ -102,6 +102,8 @@ def lib():
         L.emst_test_tree_from_codes.argtypes = [vp, vp, i64, vp, vp, vp, vp,
                                                 ctypes.POINTER(ctypes.c_int32), vp, sz, vp]
         L.emst_test_tree_from_codes.restype = i32
+        L.emst_test_tree_boxes.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp, sz, vp]
+        L.emst_test_tree_boxes.restype = i32
         L.emst_test_radix_sort.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         L.emst_test_radix_sort.restype = i32
         _lib = L
@@ -194,6 +196,23 @@ class Context:
             ctypes.c_void_p(left.data_ptr()), ctypes.c_void_p(right.data_ptr()),
             ctypes.c_void_p(label.data_ptr()), ctypes.byref(root), ws, wsb, _stream_handle(stream)))
         return left, right, label, root.value
+
+    def test_tree_boxes(self, points, stream=None):
+        """Tree of emst_build on points [n, 3]; returns (left, right, lo, hi,
+        root) -- see include/emst_test.h."""
+        import torch
+        n = points.shape[0]
+        left = torch.empty(n - 1, dtype=torch.int32, device=points.device)
+        right = torch.empty_like(left)
+        lo = torch.empty((n - 1, 3), dtype=torch.float32, device=points.device)
+        hi = torch.empty_like(lo)
+        root = ctypes.c_int32()
+        ws, wsb = self._ws_ptr(n, 3)
+        self._check(lib().emst_test_tree_boxes(
+            self._h, ctypes.c_void_p(points.data_ptr()), int(n), ctypes.c_void_p(left.data_ptr()),
+            ctypes.c_void_p(right.data_ptr()), ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+            ctypes.byref(root), ws, wsb, _stream_handle(stream)))
+        return left, right, lo, hi, root.value
 
     def test_radix_sort(self, keys, vals, stream=None):
         """Sort (keys int64 bit patterns as uint64, vals int32) in place."""

@@ -183,33 +183,26 @@ __device__ __forceinline__ int split_bit(const uint64_t* __restrict__ codes, int
 }
 
 // Bottom-up construction of the binary radix tree over the sorted codes
-// together with the bounding boxes (the agglomerative scheme of Apetrei 2014,
-// one of the two constructions the paper's BVH follows).  Internal node k
-// is the node that splits between leaves k and k+1.  A node spanning leaves
-// [l, r] becomes the left child of node r if its right neighbour pair
-// (r, r+1) shares a longer prefix than its left neighbour pair (l-1, l),
-// else the right child of node l-1.  The first of the two children to reach
-// a parent parks its range end and height there and stops; the second
-// combines both and continues upwards.
-//
-// Data crosses between the two children only through device-scope atomic
-// operations: the range end and height travel in the exchanged 64-bit word;
-// each child writes its box into the parent's record with device-scope
-// stores and waits for them to complete before the exchange, and the second
-// arrival reads its sibling's box with device-scope loads issued after its
-// exchange returned.  (Agent-scope acquire/release would write back and
-// invalidate the per-XCD L2 caches at every step.)
+// (the agglomerative scheme of Apetrei 2014, one of the two constructions
+// the paper's BVH follows).  Internal node k is the node that splits
+// between leaves k and k+1.  A node spanning leaves [l, r] becomes the left
+// child of node r if its right neighbour pair (r, r+1) shares a longer
+// prefix than its left neighbour pair (l-1, l), else the right child of
+// node l-1.  The first of the two children to reach a parent parks its range
+// end and its height there and stops; the second learns both from that
+// exchange and continues upwards.  Only the 64-bit atomic exchange crosses
+// between threads (agent-scope acquire/release would write back and
+// invalidate the per-XCD L2 caches at every step); every other store is read
+// by later kernels only.  The boxes are fitted afterwards, level by level.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ codes,
-                                               const uint32_t* __restrict__ orig, const float* __restrict__ spts,
-                                               int64_t n, Rec<DIM>* recs, uint32_t* __restrict__ leaf_parent,
+                                               const uint32_t* __restrict__ orig, int64_t n, Rec<DIM>* recs,
+                                               uint32_t* __restrict__ leaf_parent,
                                                uint32_t* __restrict__ node_parent, uint64_t* exch,
-                                               uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi, Ctrl* ctrl) {
+                                               uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi,
+                                               uint8_t* __restrict__ height, Ctrl* ctrl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float lo[DIM], hi[DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) lo[k] = hi[k] = spts[i * DIM + k];
     int64_t l = i, r = i;
     uint32_t h = 0;
     uint32_t self = (uint32_t)i, self_ref = orig[i] | kLeafFlag;
@@ -227,21 +220,12 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         else left_child = split_bit(codes, r) < split_bit(codes, l - 1);
         const uint32_t parent = (uint32_t)(left_child ? r : l - 1);
         const int side = left_child ? 0 : 1;
-        store_child_box_coherent<DIM>(&recs[parent], side, lo, hi, self_ref);
+        set_child_ref<DIM>(&recs[parent], side, self_ref);
         if (leaf) leaf_parent[i] = (parent << 1) | (uint32_t)side;
         else node_parent[self] = (parent << 1) | (uint32_t)side;
-        // the box is stored before the exchange is issued
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
         const uint64_t other = atomicExch((unsigned long long*)&exch[parent], (unsigned long long)mine);
         if (other == ~0ull) return;
-        float slo[DIM], shi[DIM];
-        load_child_box_coherent<DIM>(&recs[parent], 1 - side, slo, shi);
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            lo[k] = fminf(lo[k], slo[k]);
-            hi[k] = fmaxf(hi[k], shi[k]);
-        }
         const int64_t oend = (int64_t)(other >> 32);
         if (left_child) r = oend;
         else l = oend;
@@ -251,6 +235,7 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         leaf = false;
         rlo[parent] = (uint32_t)l;
         rhi[parent] = (uint32_t)r;
+        height[parent] = (uint8_t)h;
         if (l == 0 && r == n - 1) {
             ctrl->root = parent;
             ctrl->height = h;
@@ -258,6 +243,42 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
             return;
         }
     }
+}
+
+// A leaf's box is its point, stored in its parent's record.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ spts,
+                                                    const uint32_t* __restrict__ leaf_parent, int64_t n,
+                                                    Rec<DIM>* recs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float p[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) p[k] = spts[i * DIM + k];
+    const uint32_t link = leaf_parent[i];
+    set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), p, p);
+}
+
+// Nodes of height h: box = union of the two child boxes in the own record,
+// stored in the parent's record.  Children have smaller heights, so the
+// launch of the previous level has written them.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_fit_level(const uint8_t* __restrict__ height,
+                                                   const uint32_t* __restrict__ node_parent, int64_t m, uint32_t h,
+                                                   Rec<DIM>* recs) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m || height[k] != h) return;
+    const uint32_t link = node_parent[k];
+    if (link == kNone) return;
+    Child<DIM> c0, c1;
+    unpack<DIM>(recs[k], c0, c1);
+    float lo[DIM], hi[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        lo[d] = fminf(c0.lo[d], c1.lo[d]);
+        hi[d] = fmaxf(c0.hi[d], c1.hi[d]);
+    }
+    set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), lo, hi);
 }
 
 __device__ __forceinline__ uint32_t compact3(uint64_t x) {
@@ -487,7 +508,7 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, 
     }
     bool run_end;
     v = wave_seg_min<uint32_t>(lab, v, &run_end);
-    if (valid && run_end && v != kInfBits) atomicMin(&ub[lab], v);
+    if (valid && run_end && v != kInfBits && v < load_relaxed(&ub[lab])) atomicMin(&ub[lab], v);
 }
 
 // Stage B of the component minimum: among the points whose candidate matches
@@ -822,7 +843,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint32_t* __rest
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -854,6 +875,7 @@ static Layout make_layout(int64_t n, int dim) {
     L.pos = take(4 * N);
     L.recs = take(M * (dim == 3 ? sizeof(Rec<3>) : sizeof(Rec<2>)));
     L.lab2 = take(8 * M);
+    L.height = take(M);
     L.node_parent = take(4 * M);
     L.leaf_parent = take(4 * N);
     L.up = take(sizeof(Up) * M);
@@ -1058,6 +1080,7 @@ struct Bufs {
     uint32_t *orig, *pos;
     Rec<DIM>* recs;
     uint2* lab2;
+    uint8_t* height;
     uint32_t *node_parent, *leaf_parent;
     Up* up;
     uint64_t* exch;
@@ -1080,6 +1103,7 @@ Bufs<DIM> carve(char* ws, const Layout& L) {
     b.pos = reinterpret_cast<uint32_t*>(ws + L.pos);
     b.recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
     b.lab2 = reinterpret_cast<uint2*>(ws + L.lab2);
+    b.height = reinterpret_cast<uint8_t*>(ws + L.height);
     b.node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
     b.leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
     b.up = reinterpret_cast<Up*>(ws + L.up);
@@ -1209,6 +1233,24 @@ int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_clou
     return EMST_OK;
 }
 
+// Hierarchy (bottom-up, exchange only), then the boxes: leaves, then one
+// launch per height.  Reads the control block back for the root and height.
+template <int DIM>
+int build_tree(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hipStream_t st) {
+    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, b.orig, n, b.recs, b.leaf_parent, b.node_parent, b.exch, b.rlo,
+                                              b.rhi, b.height, b.ctrl);
+    k_fit_leaves<DIM><<<grid_for(n), 256, 0, st>>>(b.spts, b.leaf_parent, n, b.recs);
+    HIP_TRY(hipGetLastError());
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+    const uint32_t root = ctx->h_ctrl->root, H = ctx->h_ctrl->height;
+    if (root == kNone || root >= (uint32_t)(n - 1) || ctx->h_ctrl->error || H > 128)
+        return fail(ctx, EMST_EINTERNAL, "tree construction failed");
+    for (uint32_t h = 1; h < H; ++h)  // the root (height H) has no parent record
+        k_fit_level<DIM><<<grid_for(n - 1), 256, 0, st>>>(b.height, b.node_parent, n - 1, h, b.recs);
+    HIP_TRY(hipGetLastError());
+    return EMST_OK;
+}
+
 void finish_stats(emst_ctx* ctx, emst_stats& S) {
     if (ctx->profiling && ctx->ev_ok) {
         hipEvent_t* E = ctx->ev;
@@ -1267,14 +1309,9 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     // ---- hierarchy + boxes
     k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
                                                b.compmax, b.exch, b.eu, b.ev, b.ed);
-    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, b.orig, b.spts, n, b.recs, b.leaf_parent, b.node_parent,
-                                              b.exch, b.rlo, b.rhi, b.ctrl);
-    HIP_TRY(hipGetLastError());
-    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+    if (int rc = build_tree<DIM>(ctx, b, codes, n, st)) return rc;
     const uint32_t root = ctx->h_ctrl->root;
     S.tree_height = (int32_t)ctx->h_ctrl->height;
-    if (root == kNone || root >= (uint32_t)(n - 1) || ctx->h_ctrl->error)
-        return fail(ctx, EMST_EINTERNAL, "tree construction failed");
     k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, mp, b.up);
     HIP_TRY(hipGetLastError());
     if (prof) HIP_TRY(hipEventRecord(E[1], st));
@@ -1388,14 +1425,11 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     k_gather<3><<<grid_for(n), 256, 0, st>>>(pts3, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
                                              b.compmax, b.exch, b.eu, b.ev, b.ed);
     k_batch_sorted_cloud<<<grid_for(n), 256, 0, st>>>(cloud_of, perm, n, cloud_sorted);
-    k_build<3><<<grid_for(n), 256, 0, st>>>(codes, b.orig, b.spts, n, b.recs, b.leaf_parent, b.node_parent, b.exch,
-                                            b.rlo, b.rhi, b.ctrl);
+    if (int rc = build_tree<3>(ctx, b, codes, n, st)) return rc;
     k_fill_u32<<<grid_for(B), 256, 0, st>>>(d_croot, B, kNone);
     k_cloud_roots<<<grid_for(n - 1), 256, 0, st>>>(b.rlo, b.rhi, cloud_sorted, d_cin, n - 1, d_croot);
     HIP_TRY(hipGetLastError());
-    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
     S.tree_height = (int32_t)ctx->h_ctrl->height;
-    if (ctx->h_ctrl->root == kNone || ctx->h_ctrl->error) return fail(ctx, EMST_EINTERNAL, "tree construction failed");
     if (prof) HIP_TRY(hipEventRecord(E[1], st));
 
     // ---- rounds, every query inside its own cloud's subtree (top-down)
@@ -1516,6 +1550,21 @@ __global__ __launch_bounds__(256) void k_test_extract(const Rec<3>* __restrict__
     }
 }
 
+__global__ __launch_bounds__(256) void k_test_boxes(const Rec<3>* __restrict__ recs, int64_t m,
+                                                    int32_t* __restrict__ left, int32_t* __restrict__ right,
+                                                    float* __restrict__ lo, float* __restrict__ hi) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    Child<3> c0, c1;
+    unpack<3>(recs[k], c0, c1);
+    left[k] = (c0.ref & kLeafFlag) ? -(int32_t)(c0.ref & ~kLeafFlag) - 1 : (int32_t)c0.ref;
+    right[k] = (c1.ref & kLeafFlag) ? -(int32_t)(c1.ref & ~kLeafFlag) - 1 : (int32_t)c1.ref;
+    for (int d = 0; d < 3; ++d) {
+        lo[3 * k + d] = fminf(c0.lo[d], c1.lo[d]);
+        hi[3 * k + d] = fmaxf(c0.hi[d], c1.hi[d]);
+    }
+}
+
 }  // namespace emst
 
 extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes, int64_t n,
@@ -1548,7 +1597,8 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint32_t* leaf_parent = reinterpret_cast<uint32_t*>(ws + L.leaf_parent);
     k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
     k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch);
-    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, spts, n, recs, leaf_parent, node_parent, exch, rlo, rhi,
+    uint8_t* height = reinterpret_cast<uint8_t*>(ws + L.height);
+    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, n, recs, leaf_parent, node_parent, exch, rlo, rhi, height,
                                             ctrl);
     HIP_TRY(propagate_labels(labels, run_start, run_part, rlo, rhi, lab2, n, st));
     k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, lab2, node_parent, n - 1, d_left, d_right, d_label);
@@ -1585,5 +1635,45 @@ extern "C" int emst_test_radix_sort(emst_ctx* ctx, uint64_t* d_keys, uint32_t* d
         HIP_TRY(hipMemcpyAsync(d_vals, v1, 4 * (size_t)n, hipMemcpyDeviceToDevice, st));
     }
     HIP_TRY(hipStreamSynchronize(st));
+    return EMST_OK;
+}
+
+extern "C" int emst_test_tree_boxes(emst_ctx* ctx, const float* d_points, int64_t n, int32_t* d_left,
+                                    int32_t* d_right, float* d_lo, float* d_hi, int32_t* root_out, void* d_workspace,
+                                    size_t ws_bytes, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 2 || n > 0x7FFFFFFFll || !d_points || !d_left || !d_right || !d_lo || !d_hi || !root_out ||
+        !d_workspace)
+        return fail(ctx, EMST_EINVAL, "bad argument");
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(ctx, EMST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < emst_workspace_bytes(n, 3)) return fail(ctx, EMST_ENOMEM, "workspace too small");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* ws = (char*)d_workspace;
+    const Layout L = make_layout(n, 3);
+    Bufs<3> b = carve<3>(ws, L);
+    k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
+    k_bbox<3><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(d_points, n, b.ctrl);
+    HIP_TRY(hipGetLastError());
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+    if (ctx->h_ctrl->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) { lo[k] = ord_dec(ctx->h_ctrl->bb_min[k]); hi[k] = ord_dec(ctx->h_ctrl->bb_max[k]); }
+    const MortonParams mp = morton_params(lo, hi, 3, 21);
+    k_morton<3><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(d_points, n, mp, b.k0, b.v0, b.ctrl);
+    int shifts[8];
+    for (int q = 0; q < 8; ++q) shifts[q] = 8 * q;
+    int in1 = 0;
+    HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, 8, &in1));
+    const uint64_t* codes = in1 ? b.k1 : b.k0;
+    const uint32_t* perm = in1 ? b.v1 : b.v0;
+    k_gather<3><<<grid_for(n), 256, 0, st>>>(d_points, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
+                                             b.compmax, b.exch, b.eu, b.ev, b.ed);
+    if (int rc = build_tree<3>(ctx, b, codes, n, st)) return rc;
+    k_test_boxes<<<grid_for(n - 1), 256, 0, st>>>(b.recs, n - 1, d_left, d_right, d_lo, d_hi);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    *root_out = (int32_t)ctx->h_ctrl->root;
     return EMST_OK;
 }

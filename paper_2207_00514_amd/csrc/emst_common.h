@@ -96,87 +96,21 @@ __device__ __forceinline__ void load_child<2>(const Rec<2>* r, int side, Child<2
     c.lab = m.x; c.ref = m.y;
 }
 
+// Write the reference / the box of child `side` of record r.
 template <int DIM>
-__device__ __forceinline__ void store_child_box(Rec<DIM>* r, int side, const float* lo, const float* hi,
-                                                uint32_t ref);
-
-template <>
-__device__ __forceinline__ void store_child_box<3>(Rec<3>* r, int side, const float* lo, const float* hi,
-                                                   uint32_t ref) {
-    float* f = reinterpret_cast<float*>(r) + 8 * side;
-    f[0] = lo[0]; f[1] = lo[1]; f[2] = lo[2];
-    f[4] = hi[0]; f[5] = hi[1]; f[6] = hi[2];
-    f[7] = bitsf(ref);
-}
-
-template <>
-__device__ __forceinline__ void store_child_box<2>(Rec<2>* r, int side, const float* lo, const float* hi,
-                                                   uint32_t ref) {
-    float* f = reinterpret_cast<float*>(r) + 4 * side;
-    f[0] = lo[0]; f[1] = lo[1]; f[2] = hi[0]; f[3] = hi[1];
-    reinterpret_cast<uint32_t*>(r)[8 + 2 * side + 1] = ref;
-}
-
-// The same two operations with device-scope (agent) relaxed atomic stores
-// and loads, which are coherent across the XCDs' L2 caches without any
-// cache-wide writeback or invalidation.
-__device__ __forceinline__ void store_coherent(float* p, float v) {
-    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float load_coherent(const float* p) {
-    return __uint_as_float(__hip_atomic_load(reinterpret_cast<uint32_t*>(const_cast<float*>(p)), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
-}
-
-template <int DIM>
-__device__ __forceinline__ void store_child_box_coherent(Rec<DIM>* r, int side, const float* lo, const float* hi,
-                                                         uint32_t ref) {
-    float* f = reinterpret_cast<float*>(r) + (DIM == 3 ? 8 : 4) * side;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        store_coherent(f + k, lo[k]);
-        store_coherent(f + (DIM == 3 ? 4 : 2) + k, hi[k]);
-    }
-    if (DIM == 3) f[7] = __uint_as_float(ref);
+__device__ __forceinline__ void set_child_ref(Rec<DIM>* r, int side, uint32_t ref) {
+    if (DIM == 3) reinterpret_cast<uint32_t*>(r)[8 * side + 7] = ref;
     else reinterpret_cast<uint32_t*>(r)[8 + 2 * side + 1] = ref;
 }
 
 template <int DIM>
-__device__ __forceinline__ void load_child_box_coherent(const Rec<DIM>* r, int side, float* lo, float* hi) {
-    const float* f = reinterpret_cast<const float*>(r) + (DIM == 3 ? 8 : 4) * side;
+__device__ __forceinline__ void set_child_box(Rec<DIM>* r, int side, const float* lo, const float* hi) {
+    float* f = reinterpret_cast<float*>(r) + (DIM == 3 ? 8 : 4) * side;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        lo[k] = load_coherent(f + k);
-        hi[k] = load_coherent(f + (DIM == 3 ? 4 : 2) + k);
+        f[k] = lo[k];
+        f[(DIM == 3 ? 4 : 2) + k] = hi[k];
     }
-}
-
-template <int DIM>
-__device__ __forceinline__ uint32_t* label_slot(Rec<DIM>* r, int side);
-
-template <>
-__device__ __forceinline__ uint32_t* label_slot<3>(Rec<3>* r, int side) {
-    return reinterpret_cast<uint32_t*>(r) + 8 * side + 3;
-}
-template <>
-__device__ __forceinline__ uint32_t* label_slot<2>(Rec<2>* r, int side) {
-    return reinterpret_cast<uint32_t*>(r) + 8 + 2 * side;
-}
-
-template <int DIM>
-__device__ __forceinline__ void load_child_box(const Rec<DIM>* r, int side, float* lo, float* hi);
-
-template <>
-__device__ __forceinline__ void load_child_box<3>(const Rec<3>* r, int side, float* lo, float* hi) {
-    const float* f = reinterpret_cast<const float*>(r) + 8 * side;
-    lo[0] = f[0]; lo[1] = f[1]; lo[2] = f[2];
-    hi[0] = f[4]; hi[1] = f[5]; hi[2] = f[6];
-}
-template <>
-__device__ __forceinline__ void load_child_box<2>(const Rec<2>* r, int side, float* lo, float* hi) {
-    const float* f = reinterpret_cast<const float*>(r) + 4 * side;
-    lo[0] = f[0]; lo[1] = f[1]; hi[0] = f[2]; hi[1] = f[3];
 }
 
 // ---------------------------------------------------------------------------

@@ -325,3 +325,38 @@ def test_batched_512_clouds_sampled(ctx):
         assert_same(res[c], oracle.emst(clouds[c], threads=16), f"cloud {c}")
     for c, r in enumerate(res):
         assert r[0].shape[0] == max(len(clouds[c]) - 1, 0)
+
+
+def test_tree_boxes_are_exact(ctx):
+    """Every internal node's box is exactly the min/max of its leaves."""
+    import sys
+    sys.setrecursionlimit(100000)
+    for seed, n in ((1, 2), (2, 3), (3, 777), (4, 5000), (5, 40000)):
+        pts = W.small_random(n, 3, seed, ("uniform", "dup", "int", "outlier")[seed % 4])
+        left, right, lo, hi, root = ctx.test_tree_boxes(torch.from_numpy(pts).cuda())
+        left, right = left.cpu().numpy(), right.cpu().numpy()
+        lo, hi = lo.cpu().numpy(), hi.cpu().numpy()
+        mn = np.zeros((n - 1, 3), np.float32)
+        mx = np.zeros((n - 1, 3), np.float32)
+        seen = np.zeros(n, bool)
+        # post-order without recursion
+        order, stack = [], [root]
+        while stack:
+            k = stack.pop()
+            order.append(k)
+            for c in (left[k], right[k]):
+                if c >= 0:
+                    stack.append(c)
+        for k in reversed(order):
+            boxes = []
+            for c in (left[k], right[k]):
+                if c < 0:
+                    seen[-c - 1] = True
+                    boxes.append((pts[-c - 1], pts[-c - 1]))
+                else:
+                    boxes.append((mn[c], mx[c]))
+            mn[k] = np.minimum(boxes[0][0], boxes[1][0])
+            mx[k] = np.maximum(boxes[0][1], boxes[1][1])
+        assert seen.all() and len(order) == n - 1
+        np.testing.assert_array_equal(lo, mn)
+        np.testing.assert_array_equal(hi, mx)
