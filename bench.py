@@ -32,6 +32,28 @@ if ROOT not in sys.path:
 METRIC = "EMST Mpoints/sec at 1 GPU + HBM roofline fraction; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 
+# Measured HBM traffic of the traversal kernel: rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs (KiB per dispatch, averaged over the uninstrumented
+# traversal launches of one build), scaled by what the same counters read for
+# a plain 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the bytes the
+# copy moves, so factors 2.0 and 1.0).  Keyed by workload, traversal variant
+# and a hash of the traversal sources: once the kernel changes there is no
+# entry and `traffic` is null until the counters are taken again.
+TRAFFIC_SOURCES = ("traverse.h", "emst_common.h", "emst_kernels.h")
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+MEASURED_TRAFFIC = {
+    # (workload, variant, source hash): (FETCH_SIZE KiB, WRITE_SIZE KiB, TCC hit fraction, profile)
+}
+
+
+def traversal_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2207_00514_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def algorithmic_bytes(dim: int, n: int, internal: int, leaf: int) -> int:
     return internal * (8 * dim + 8) + leaf * (4 * dim + 8) + n * (4 * dim + 16)
@@ -125,6 +147,15 @@ def main() -> int:
     avg_launch_ms = trav_ms / max(launches, 1)
     bytes_per_launch = bytes_per_step / max(rounds, 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
+    # compulsory bytes of one launch: every node record and its label entry
+    # once, plus the per-query fixed bytes
+    rec_bytes = (64 if dim == 3 else 48) + 8
+    b_min = (n - 1) * rec_bytes + n * (4 * dim + 16)
+    variant_ran = int(st["traversal_variant"])
+    src_hash = traversal_source_hash()
+    meas = MEASURED_TRAFFIC.get((args.workload, variant_ran, src_hash))
+    traffic = (None if meas is None or args.n is not None
+               else int(meas[0] * 1024 * FETCH_FACTOR + meas[1] * 1024 * WRITE_FACTOR))
 
     edges, w, d2 = (t.cpu().numpy() for t in out)
     line = {
@@ -151,10 +182,17 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": "k_traverse",
+            "traffic": traffic,
+            "kernel": {0: "k_traverse_lane", 1: "k_traverse_wave", 2: "k_traverse_up", 3: "k_traverse_pool",
+                       4: "k_traverse_pool"}.get(variant_ran, "k_traverse_fast"),
+            "variant": variant_ran,
+            "source_hash": src_hash,
             "avg_launch_ms": round(avg_launch_ms, 4),
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "compulsory_bytes_per_launch": int(b_min),
+            "compulsory_frac": round(b_min / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if avg_launch_ms > 0 else 0.0,
+            "l2_hit": None if meas is None else meas[2],
+            "traffic_profile": None if meas is None else meas[3],
             "children_examined_per_query_round": round((cst["child_tests"] + cst["leaf_tests"]) / (n * rounds), 2),
             "dist_evals_per_query_round": round(cst["dist_evals"] / (n * rounds), 2),
         },

@@ -154,6 +154,8 @@ typedef struct emst_stats {
     int64_t leaf_tests_round[64];
     int64_t dist_evals;             /* leaf children outside the query's
                                        component: point distances computed */
+    int32_t traversal_variant;      /* the traversal variant that ran */
+    int32_t reserved;
 } emst_stats;
 
 /* Time every phase with HIP events (adds synchronisation; off by default). */
@@ -170,8 +172,17 @@ int emst_set_counting(emst_ctx *ctx, int on);
  *   2  one lane per query, walking up from the query's own leaf and stopping
  *      at the first ancestor whose Morton cell holds the search ball
  *   3, 4  as 0 and 2 on persistent waves that refill finished lanes
- *   5  as 0 with a branch-free inner loop and an LDS stack (default)
- *   6  as 2 with the loop of 5 */
+ *   5  as 0 with a branch-free inner loop and a 16-deep LDS stack
+ *   6  as 2 with the loop of 5
+ *   7  as 5 with an 8-deep LDS stack
+ *   8  as 5 with a 4-deep LDS stack
+ *   9  as 6 with an 8-deep LDS stack
+ *  10  as 7, but each wave of 64 queries starts below the root, at the
+ *      lowest ancestor of its leaves whose Morton cell holds every lane's
+ *      search ball (default)
+ * Batches (emst_build_batched) run 0, 5, 7 or 8 as chosen and 7 for any
+ * other value.
+ * Returns EMST_EINVAL outside [0, 10]. */
 int emst_set_traversal(emst_ctx *ctx, int variant);
 
 int emst_get_stats(const emst_ctx *ctx, emst_stats *out);

@@ -343,6 +343,28 @@ __global__ __launch_bounds__(256) void k_cells(const uint64_t* __restrict__ code
     up[k] = u;
 }
 
+// For every wave of 64 Morton-consecutive queries [64w, 64w + 63]: the
+// lowest node whose leaf range covers them, found by climbing from the first
+// leaf.  Written over the exchange words of the build, which are dead once
+// the hierarchy exists.
+__global__ __launch_bounds__(256) void k_wave_lca(const uint32_t* __restrict__ rlo, const uint32_t* __restrict__ rhi,
+                                                  const uint32_t* __restrict__ leaf_parent,
+                                                  const uint32_t* __restrict__ node_parent, int64_t n,
+                                                  uint32_t* __restrict__ wave_lca) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = 64 * w;
+    if (i0 >= n) return;
+    const uint32_t i1 = (uint32_t)min<int64_t>(i0 + 63, n - 1);
+    uint32_t s = leaf_parent[i0] >> 1;
+    for (int h = 0; h < 160; ++h) {
+        if (rlo[s] <= (uint32_t)i0 && rhi[s] >= i1) break;
+        const uint32_t link = node_parent[s];
+        if (link == kNone) break;
+        s = link >> 1;
+    }
+    wave_lca[w] = s;
+}
+
 // ===========================================================================
 // one Boruvka round
 
@@ -932,7 +954,7 @@ struct emst_ctx {
     std::string err;
     bool profiling = false;
     bool counting = false;
-    int traversal = 7;
+    int traversal = 10;
     emst_stats stats;
     Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
     hipEvent_t ev[2 * 64 + 8];
@@ -1019,7 +1041,7 @@ extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
     return EMST_OK;
 }
 extern "C" int emst_set_traversal(emst_ctx* ctx, int variant) {
-    if (!ctx || variant < 0 || variant > 9) return EMST_EINVAL;
+    if (!ctx || variant < 0 || variant > 10) return EMST_EINVAL;
     ctx->traversal = variant;
     return EMST_OK;
 }
@@ -1133,6 +1155,7 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     ta.n = n; ta.cand_d = b.cand_d; ta.cand_j = b.cand_j; ta.compkey = b.compkey; ta.compmax = b.compmax;
     ta.ctrl = b.ctrl; ta.first = true; ta.leaf_parent = b.leaf_parent; ta.up = b.up;
     ta.cloud_of = nullptr; ta.cloud_root = nullptr; ta.lab2 = b.lab2;
+    ta.wave_lca = reinterpret_cast<const uint32_t*>(b.exch);  // the build's exchange words are free by now
     return ta;
 }
 
@@ -1194,6 +1217,7 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
     }
     S.rounds = round;
     S.traversal_launches = round;
+    S.traversal_variant = variant;
     return EMST_OK;
 }
 
@@ -1313,6 +1337,8 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     const uint32_t root = ctx->h_ctrl->root;
     S.tree_height = (int32_t)ctx->h_ctrl->height;
     k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, mp, b.up);
+    k_wave_lca<<<grid_for((n + 63) / 64), 256, 0, st>>>(b.rlo, b.rhi, b.leaf_parent, b.node_parent, n,
+                                                        reinterpret_cast<uint32_t*>(b.exch));
     HIP_TRY(hipGetLastError());
     if (prof) HIP_TRY(hipEventRecord(E[1], st));
 
@@ -1436,7 +1462,10 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     TraverseArgs<3> ta = traverse_args<3>(b, n, ctx->h_ctrl->root);
     ta.cloud_of = cloud_sorted;
     ta.cloud_root = d_croot;
-    const int variant = (ctx->traversal == 0 || ctx->traversal == 5 || ctx->traversal == 8) ? ctx->traversal : 7;
+    // variants 1-4 start every lane at one root and 6, 9, 10 need the Morton
+    // cells of one cloud: a batch runs them as 7
+    const int t = ctx->traversal;
+    const int variant = (t == 0 || t == 5 || t == 8) ? t : 7;
     if (int rc = run_rounds<3>(ctx, b, ta, n, nonempty, S.tree_height, variant, cloud_sorted, S, st)) return rc;
     if ((int64_t)ctx->h_ctrl->edge_count != eoff) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));

@@ -16,16 +16,17 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------------------
 // Node record of the binary LBVH.  One record per internal node holds
 // everything a traversal needs about BOTH children, so testing the two
-// children of a node is one contiguous read: per child its bounding box, its
-// reference (internal node index, or kLeafFlag | original point index) and
-// its component label (kInvalid if its leaves span several components).
-// With one point per leaf a leaf child's box is the point itself.
+// children of a node is one contiguous read: per child its bounding box and
+// its reference (internal node index, or kLeafFlag | original point index).
+// With one point per leaf a leaf child's box is the point itself.  The
+// component labels of the children change every round and live in a
+// separate 8-byte entry per record; the record's label slots stay unused.
 //
-//   3D, 64 B:  child c at [32c, 32c+32): float4(lo.x, lo.y, lo.z, label)
+//   3D, 64 B:  child c at [32c, 32c+32): float4(lo.x, lo.y, lo.z, unused)
 //                                        float4(hi.x, hi.y, hi.z, ref)
 //   2D, 48 B:  float4(lo0.x, lo0.y, hi0.x, hi0.y)
 //              float4(lo1.x, lo1.y, hi1.x, hi1.y)
-//              uint4 (label0, ref0, label1, ref1)
+//              uint4 (unused, ref0, unused, ref1)
 template <int DIM> struct Rec;
 
 template <> struct alignas(64) Rec<3> {
@@ -51,7 +52,7 @@ struct alignas(16) Up {
 
 template <int DIM> struct Child {
     float lo[DIM], hi[DIM];
-    uint32_t lab, ref;
+    uint32_t lab, ref;  // label (from the per-round entry), reference
 };
 
 __device__ __forceinline__ uint32_t fbits(float f) { return __float_as_uint(f); }
@@ -62,9 +63,9 @@ __device__ __forceinline__ void unpack(const Rec<DIM>& r, Child<DIM>& c0, Child<
 
 template <>
 __device__ __forceinline__ void unpack<3>(const Rec<3>& r, Child<3>& c0, Child<3>& c1) {
-    c0.lo[0] = r.a0.x; c0.lo[1] = r.a0.y; c0.lo[2] = r.a0.z; c0.lab = fbits(r.a0.w);
+    c0.lo[0] = r.a0.x; c0.lo[1] = r.a0.y; c0.lo[2] = r.a0.z; c0.lab = kInvalid;
     c0.hi[0] = r.b0.x; c0.hi[1] = r.b0.y; c0.hi[2] = r.b0.z; c0.ref = fbits(r.b0.w);
-    c1.lo[0] = r.a1.x; c1.lo[1] = r.a1.y; c1.lo[2] = r.a1.z; c1.lab = fbits(r.a1.w);
+    c1.lo[0] = r.a1.x; c1.lo[1] = r.a1.y; c1.lo[2] = r.a1.z; c1.lab = kInvalid;
     c1.hi[0] = r.b1.x; c1.hi[1] = r.b1.y; c1.hi[2] = r.b1.z; c1.ref = fbits(r.b1.w);
 }
 
@@ -72,28 +73,7 @@ template <>
 __device__ __forceinline__ void unpack<2>(const Rec<2>& r, Child<2>& c0, Child<2>& c1) {
     c0.lo[0] = r.box0.x; c0.lo[1] = r.box0.y; c0.hi[0] = r.box0.z; c0.hi[1] = r.box0.w;
     c1.lo[0] = r.box1.x; c1.lo[1] = r.box1.y; c1.hi[0] = r.box1.z; c1.hi[1] = r.box1.w;
-    c0.lab = r.meta.x; c0.ref = r.meta.y; c1.lab = r.meta.z; c1.ref = r.meta.w;
-}
-
-// Write the box and reference of child `side` of record r (labels are
-// written separately, every round).
-template <int DIM>
-__device__ __forceinline__ void load_child(const Rec<DIM>* r, int side, Child<DIM>& c);
-
-template <>
-__device__ __forceinline__ void load_child<3>(const Rec<3>* r, int side, Child<3>& c) {
-    const float4* f = reinterpret_cast<const float4*>(r) + 2 * side;
-    const float4 u = f[0], v = f[1];
-    c.lo[0] = u.x; c.lo[1] = u.y; c.lo[2] = u.z; c.lab = fbits(u.w);
-    c.hi[0] = v.x; c.hi[1] = v.y; c.hi[2] = v.z; c.ref = fbits(v.w);
-}
-
-template <>
-__device__ __forceinline__ void load_child<2>(const Rec<2>* r, int side, Child<2>& c) {
-    const float4 u = reinterpret_cast<const float4*>(r)[side];
-    const uint2 m = reinterpret_cast<const uint2*>(r)[4 + side];
-    c.lo[0] = u.x; c.lo[1] = u.y; c.hi[0] = u.z; c.hi[1] = u.w;
-    c.lab = m.x; c.ref = m.y;
+    c0.lab = kInvalid; c0.ref = r.meta.y; c1.lab = kInvalid; c1.ref = r.meta.w;
 }
 
 // Write the reference / the box of child `side` of record r.

@@ -52,6 +52,9 @@ struct TraverseArgs {
     const uint32_t* cloud_of;
     const uint32_t* cloud_root;
     const uint2* lab2;  // per record: component labels of its two children (rewritten every round)
+    // per wave of 64 Morton-consecutive queries: the lowest common ancestor
+    // of their leaves (one cloud only)
+    const uint32_t* wave_lca;
 };
 
 // Where a top-down search of query i starts.
@@ -617,8 +620,30 @@ __global__ __launch_bounds__(256) void k_traverse_pool(TraverseArgs<DIM> a) {
 // the stack lives in LDS (kLdsDepth entries per lane, laid out [depth][lane]
 // so a wave's accesses fall in distinct banks) with the deeper entries
 // spilled to a private array only when a search nests deeper than that.
+//
+// With WSTART (variant 10) the whole wave starts its top-down searches below
+// the root, at one node S: from the lowest common ancestor of the wave's 64
+// leaves it climbs until the Morton cell of S contains the ball of every
+// lane's starting radius.  Every point a lane can admit lies in its ball,
+// hence in that cell, hence among the leaves of S (a code-split node holds
+// every point of its cell), so each search below S finds the candidate the
+// search from the root finds.  The climb reads one uniform cell per step;
+// the lanes stay in lockstep and skip the shared descent from the root.
 
-template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16>
+// The ball of radius sqrt(radius) around p lies inside the (shrunk) Morton
+// cell u; the radius is widened by more than the rounding of D and of the
+// square root, so no point with D <= radius lies outside.
+template <int DIM>
+__device__ __forceinline__ bool ball_in_cell(const float* p, float rr, const Up& u) {
+    bool inside = (p[0] - rr >= u.a.x) && (p[0] + rr <= u.b.x);
+    if (DIM > 1) inside = inside && (p[1 % DIM] - rr >= u.a.y) && (p[1 % DIM] + rr <= u.b.y);
+    if (DIM > 2) inside = inside && (p[2 % DIM] - rr >= u.a.z) && (p[2 % DIM] + rr <= u.b.z);
+    return inside;
+}
+
+__device__ __forceinline__ float widen(float radius) { return sqrtf(radius) * 1.000001f + 1e-22f; }
+
+template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16, bool WSTART = false>
 __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
     __shared__ uint2 lds[kLdsDepth][256];
     const int t = threadIdx.x;
@@ -645,6 +670,18 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
         } else {
             node = start_node<DIM>(a, i);
             mask = node == kNone ? 0u : 3u;
+            if (WSTART && mask) {
+                // wave-uniform climb; lanes past the end take no part
+                const float rr = widen(radius);
+                uint32_t s = a.wave_lca[i >> 6];
+                for (int h = 0; h < 160 && s != node; ++h) {
+                    const Up cu = a.up[s];
+                    if (__all(ball_in_cell<DIM>(p, rr, cu))) break;
+                    const uint32_t link = fbits(cu.a.w);
+                    s = link == kNone ? node : link >> 1;
+                }
+                node = s;
+            }
         }
         for (int64_t guard = 0; mask; ++guard) {
             if (guard > 2 * a.n + 256) {
@@ -669,16 +706,18 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 n_int += ((mask & 1u) && !l0) + ((mask & 2u) && !l1);
                 n_eval += (in0 && l0) + (in1 && l1);
             }
-            // leaf candidates: (D, j) order, radius follows the best
+            // leaf candidates: (D, j) order, radius follows the best.  D >= 0,
+            // so (D bits, j) as one 64-bit integer has the same order.
             {
-                const uint32_t j0 = c0.ref & ~kLeafFlag;
-                const bool b0 = in0 && l0 && d0 <= radius && better(d0, j0, best_d, best_j);
-                best_d = b0 ? d0 : best_d;
-                best_j = b0 ? j0 : best_j;
-                const uint32_t j1 = c1.ref & ~kLeafFlag;
-                const bool b1 = in1 && l1 && d1 <= radius && better(d1, j1, best_d, best_j);
-                best_d = b1 ? d1 : best_d;
-                best_j = b1 ? j1 : best_j;
+                const uint64_t k0 = ((uint64_t)fbits(d0) << 32) | (c0.ref & ~kLeafFlag);
+                const uint64_t k1 = ((uint64_t)fbits(d1) << 32) | (c1.ref & ~kLeafFlag);
+                const bool b0 = in0 & l0 & (d0 <= radius);
+                const bool b1 = in1 & l1 & (d1 <= radius);
+                uint64_t bk = ((uint64_t)fbits(best_d) << 32) | best_j;
+                bk = (b0 & (k0 < bk)) ? k0 : bk;
+                bk = (b1 & (k1 < bk)) ? k1 : bk;
+                best_d = bitsf((uint32_t)(bk >> 32));
+                best_j = (uint32_t)bk;
                 radius = fminf(radius, best_d);
             }
             const bool go0 = in0 && !l0 && d0 <= radius;
@@ -724,10 +763,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             if (!UPWARD) break;
             // every leaf of `anc` has been searched: stop if the ball of the
             // radius lies in its Morton cell (see variant 2)
-            const float rr = sqrtf(radius) * 1.000001f + 1e-22f;
-            bool inside = (p[0] - rr >= u.a.x) && (p[0] + rr <= u.b.x);
-            if (DIM > 1) inside = inside && (p[1 % DIM] - rr >= u.a.y) && (p[1 % DIM] + rr <= u.b.y);
-            if (DIM > 2) inside = inside && (p[2 % DIM] - rr >= u.a.z) && (p[2 % DIM] + rr <= u.b.z);
+            const bool inside = ball_in_cell<DIM>(p, widen(radius), u);
             const uint32_t link = fbits(u.a.w);
             if (inside || link == kNone) break;
             anc = link >> 1;
@@ -767,6 +803,9 @@ hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count
     } else if (variant == 9) {
         if (count) k_traverse_fast<DIM, STACK, true, true, 8><<<grid, 256, 0, st>>>(a);
         else k_traverse_fast<DIM, STACK, false, true, 8><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 10) {
+        if (count) k_traverse_fast<DIM, STACK, true, false, 8, true><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false, 8, true><<<grid, 256, 0, st>>>(a);
     } else if (variant == 3 || variant == 4) {
         // persistent: enough waves to fill every CU several times over
         const unsigned pgrid = std::min<unsigned>(grid, 2048u);

@@ -64,3 +64,24 @@ def test_oracle_is_not_imported_by_the_product_path():
     assert "oracle" not in src.replace("no CPU fallback", "")
     for f in os.listdir(os.path.join(ROOT, "paper_2207_00514_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_2207_00514_amd", "csrc", f)).read().lower()
+
+
+def test_stats_struct_matches_the_header(tmp_path):
+    """The binding's emst_stats mirror has the C struct's size and offsets."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in emst.Stats._fields_]
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "emst.h"\nint main(void){\n'
+        '  printf("%zu\\n", sizeof(emst_stats));\n'
+        + "".join(f'  printf("%zu\\n", offsetof(emst_stats, {f}));\n' for f in fields)
+        + "  return 0;\n}\n")
+    exe = tmp_path / "sz"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == ctypes.sizeof(emst.Stats)
+    assert out[1:] == [getattr(emst.Stats, f).offset for f in fields]
