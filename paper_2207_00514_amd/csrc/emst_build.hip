@@ -157,8 +157,7 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, c
                                                 uint32_t* __restrict__ pos, uint32_t* __restrict__ labels,
                                                 uint32_t* __restrict__ ub, uint64_t* __restrict__ compkey,
                                                 uint32_t* __restrict__ compmax, uint64_t* __restrict__ exch,
-                                                uint32_t* __restrict__ eu,
-                                                uint32_t* __restrict__ ev, uint32_t* __restrict__ ed) {
+                                                uint4* __restrict__ eud) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t o = perm[i];
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, c
     ub[i] = kInfBits;
     compkey[i] = kKeyMax;
     compmax[i] = kNone;
-    eu[i] = ev[i] = ed[i] = kNone;   // the final root's slot keeps these and sorts last
+    eud[i] = make_uint4(kNone, kNone, kNone, 0u);   // the final root's slot keeps these and sorts last
     if (i + 1 < n) exch[i] = ~0ull;
 }
 
@@ -582,8 +581,7 @@ __global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__
 __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict__ labels,
                                                       const uint32_t* __restrict__ succ, uint32_t* par,
                                                       uint64_t* compkey, uint32_t* compmax, uint32_t* ub,
-                                                      uint32_t* __restrict__ eu, uint32_t* __restrict__ ev,
-                                                      uint32_t* __restrict__ ed, Ctrl* ctrl, int64_t n) {
+                                                      uint4* __restrict__ eud, Ctrl* ctrl, int64_t n) {
     __shared__ uint32_t s_cnt[2];
     if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -603,9 +601,7 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
             // emits at most once over the whole run: its slot is its own
             ++emitted;
             const uint64_t key = compkey[c];
-            eu[c] = (uint32_t)(key & 0xFFFFFFFFu);
-            ev[c] = compmax[c];
-            ed[c] = (uint32_t)(key >> 32);
+            eud[c] = make_uint4((uint32_t)(key & 0xFFFFFFFFu), compmax[c], (uint32_t)(key >> 32), 0u);
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -659,35 +655,94 @@ __global__ __launch_bounds__(256) void k_relabel(uint32_t* labels, const uint32_
 // ===========================================================================
 // finalize
 
-__global__ __launch_bounds__(256) void k_edge_keys(const uint32_t* __restrict__ eu, const uint32_t* __restrict__ ev,
-                                                   int64_t m, uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals) {
+// Canonical edge order (the key K = (D, min, max) of every emitted edge).
+// Component slot e holds (u, v, D bits) with u < v; the empty slots (the
+// final root of each cloud) hold D = kNone and sort last.
+//
+// Fast path: sort the slots by the 64-bit key (D bits, u), then put every
+// run of equal keys -- edges of exactly equal length at one endpoint u, at
+// most a point's MST degree unless points coincide -- in v order in place.
+// A run longer than kMaxTieRun raises long_ties and the caller redoes the
+// order by the full path: by (u, v), then stably by D.  A batch finally
+// sorts stably by cloud (a run never spans two clouds: u fixes the cloud).
+constexpr int kMaxTieRun = 32;
+
+__global__ __launch_bounds__(256) void k_edge_du_keys(const uint4* __restrict__ eud, int64_t m,
+                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
-    keys[e] = ((uint64_t)eu[e] << 32) | (uint64_t)ev[e];
+    const uint4 s = eud[e];
+    keys[e] = ((uint64_t)s.z << 32) | (uint64_t)s.x;
     vals[e] = (uint32_t)e;
 }
 
-__global__ __launch_bounds__(256) void k_edge_dkeys(const uint32_t* __restrict__ ed,
-                                                    const uint32_t* __restrict__ perm, int64_t m,
-                                                    uint64_t* __restrict__ keys) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    keys[i] = (uint64_t)ed[perm[i]];
+__global__ __launch_bounds__(256) void k_tie_fix(const uint64_t* __restrict__ keys, uint32_t* __restrict__ order,
+                                                 const uint4* __restrict__ eud, int64_t m, Ctrl* ctrl) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r + 1 >= m) return;
+    const uint64_t k = keys[r];
+    // one thread per run of two or more equal keys: its first position
+    if (keys[r + 1] != k || (r > 0 && keys[r - 1] == k) || (uint32_t)(k >> 32) == kNone) return;
+    int64_t e = r + 2;
+    while (e < m && e - r <= kMaxTieRun && keys[e] == k) ++e;
+    if (e - r > kMaxTieRun) {
+        atomicOr(&ctrl->long_ties, 1u);
+        return;
+    }
+    const int len = (int)(e - r);
+    uint32_t id[kMaxTieRun];
+    uint64_t uv[kMaxTieRun];
+    for (int t = 0; t < len; ++t) {  // insertion sort by (u, v)
+        const uint32_t x = order[r + t];
+        const uint4 s = eud[x];
+        const uint64_t y = ((uint64_t)s.x << 32) | s.y;
+        int q = t;
+        while (q > 0 && uv[q - 1] > y) {
+            uv[q] = uv[q - 1];
+            id[q] = id[q - 1];
+            --q;
+        }
+        uv[q] = y;
+        id[q] = x;
+    }
+    for (int t = 0; t < len; ++t) order[r + t] = id[t];
 }
 
-__global__ __launch_bounds__(256) void k_edge_write(const uint32_t* __restrict__ eu,
-                                                    const uint32_t* __restrict__ ev,
-                                                    const uint32_t* __restrict__ ed,
-                                                    const uint32_t* __restrict__ perm, int64_t m,
-                                                    int32_t* __restrict__ edges, float* __restrict__ w,
+// Full path, first pass: (u, v) keys of every slot.
+__global__ __launch_bounds__(256) void k_edge_keys(const uint4* __restrict__ eud, int64_t m,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint4 s = eud[e];
+    keys[e] = ((uint64_t)s.x << 32) | (uint64_t)s.y;
+    vals[e] = (uint32_t)e;
+}
+
+// keys[i] = D bits of slot perm[i]
+__global__ __launch_bounds__(256) void k_edge_dkeys(const uint4* __restrict__ eud, const uint32_t* __restrict__ perm,
+                                                    int64_t m, uint64_t* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    keys[i] = (uint64_t)eud[perm[i]].z;
+}
+
+// keys[i] = src[perm[i]]
+__global__ __launch_bounds__(256) void k_perm_keys(const uint32_t* __restrict__ src,
+                                                   const uint32_t* __restrict__ perm, int64_t m,
+                                                   uint64_t* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    keys[i] = (uint64_t)src[perm[i]];
+}
+
+__global__ __launch_bounds__(256) void k_edge_write(const uint4* __restrict__ eud, const uint32_t* __restrict__ perm,
+                                                    int64_t m, int32_t* __restrict__ edges, float* __restrict__ w,
                                                     float* __restrict__ d2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    const uint32_t e = perm[i];
-    const float d = bitsf(ed[e]);
-    edges[2 * i] = (int32_t)eu[e];
-    edges[2 * i + 1] = (int32_t)ev[e];
+    const uint4 s = eud[perm[i]];
+    const float d = bitsf(s.z);
+    reinterpret_cast<int2*>(edges)[i] = make_int2((int32_t)s.x, (int32_t)s.y);
     w[i] = sqrtf(d);
     if (d2) d2[i] = d;
 }
@@ -840,9 +895,7 @@ __global__ __launch_bounds__(256) void k_cloud_roots(const uint32_t* __restrict_
 }
 
 // Sorted slot i -> output edge of its cloud, with cloud-local indices.
-__global__ __launch_bounds__(256) void k_batch_edge_write(const uint32_t* __restrict__ eu,
-                                                          const uint32_t* __restrict__ ev,
-                                                          const uint32_t* __restrict__ ed,
+__global__ __launch_bounds__(256) void k_batch_edge_write(const uint4* __restrict__ eud,
                                                           const uint32_t* __restrict__ order,
                                                           const uint32_t* __restrict__ cloud_sorted,
                                                           const CloudIn* __restrict__ cin, int64_t n,
@@ -851,12 +904,13 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint32_t* __rest
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t e = order[i];
-    if (ed[e] == kNone) return;
+    const uint4 s = eud[e];
+    if (s.z == kNone) return;
     const CloudIn ci = cin[cloud_sorted[e]];
     const int64_t o = ci.eoff + (i - ci.off);
-    const float d = bitsf(ed[e]);
-    edges[2 * o] = (int32_t)((int64_t)eu[e] - ci.off);
-    edges[2 * o + 1] = (int32_t)((int64_t)ev[e] - ci.off);
+    const float d = bitsf(s.z);
+    edges[2 * o] = (int32_t)((int64_t)s.x - ci.off);
+    edges[2 * o + 1] = (int32_t)((int64_t)s.y - ci.off);
     w[o] = sqrtf(d);
     if (d2) d2[o] = d;
 }
@@ -865,7 +919,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint32_t* __rest
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eu, ev, ed, total;
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -914,9 +968,7 @@ static Layout make_layout(int64_t n, int dim) {
     L.par = take(4 * N);
     L.cand_d = take(4 * N);
     L.cand_j = take(4 * N);
-    L.eu = take(4 * N);
-    L.ev = take(4 * N);
-    L.ed = take(4 * N);
+    L.eud = take(16 * N);
     L.total = o;
     return L;
 }
@@ -1108,7 +1160,8 @@ struct Bufs {
     uint64_t* exch;
     uint32_t *rlo, *rhi, *run_start, *run_part, *labels, *ub;
     uint64_t* compkey;
-    uint32_t *compmax, *succ, *par, *cand_d, *cand_j, *eu, *ev, *ed;
+    uint32_t *compmax, *succ, *par, *cand_d, *cand_j;
+    uint4* eud;
 };
 
 template <int DIM>
@@ -1142,9 +1195,7 @@ Bufs<DIM> carve(char* ws, const Layout& L) {
     b.par = reinterpret_cast<uint32_t*>(ws + L.par);
     b.cand_d = reinterpret_cast<uint32_t*>(ws + L.cand_d);
     b.cand_j = reinterpret_cast<uint32_t*>(ws + L.cand_j);
-    b.eu = reinterpret_cast<uint32_t*>(ws + L.eu);
-    b.ev = reinterpret_cast<uint32_t*>(ws + L.ev);
-    b.ed = reinterpret_cast<uint32_t*>(ws + L.ed);
+    b.eud = reinterpret_cast<uint4*>(ws + L.eud);
     return b;
 }
 
@@ -1192,7 +1243,7 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
         k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.succ, b.ctrl, n,
                                                   cloud_of != nullptr);
         k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(
-            b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eu, b.ev, b.ed, b.ctrl, n);
+            b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud, b.ctrl, n);
         HIP_TRY(hipGetLastError());
         k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024);
         k_relabel<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 4096, b.ctrl);
@@ -1222,31 +1273,49 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
 }
 
 // Canonical edge order over the n component slots (the slots of the final
-// roots are empty and sort last): by (u, v), then stably by D bits, then --
-// for a batch -- stably by cloud.  Writes sorted slot ids to *order.
+// roots are empty and sort last).  Writes sorted slot ids to *order.
+//   full = false: by (D bits, u), runs of equal keys put in v order in place
+//                 (see k_tie_fix; may raise long_ties);
+//   full = true:  by (u, v), then stably by D bits;
+// then, for a batch, stably by cloud.
 template <int DIM>
-int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_cloud, int cloud_bits,
+int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_cloud, int cloud_bits, bool full,
                const uint32_t** order, hipStream_t st) {
     int in1 = 0;
-    k_edge_keys<<<grid_for(n), 256, 0, st>>>(b.eu, b.ev, n, b.k0, b.v0);
-    int sh[16], q = 0;
     const int ib = 32 - __builtin_clz((unsigned)(n - 1));  // bits of the largest index
-    for (int s = 0; s < ib; s += 8) sh[q++] = s;
-    for (int s = 0; s < ib; s += 8) sh[q++] = 32 + s;
-    HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, sh, q, &in1));
-    uint32_t* p = in1 ? b.v1 : b.v0;
-    uint64_t* kd = in1 ? b.k1 : b.k0;
-    uint64_t* kd_alt = in1 ? b.k0 : b.k1;
-    uint32_t* p_alt = in1 ? b.v0 : b.v1;
-    k_edge_dkeys<<<grid_for(n), 256, 0, st>>>(b.ed, p, n, kd);
-    const int dsh[4] = {0, 8, 16, 24};
-    HIP_TRY(radix_sort_pairs(st, kd, p, kd_alt, p_alt, b.hist, n, dsh, 4, &in1));
-    if (in1) {
-        std::swap(p, p_alt);
-        std::swap(kd, kd_alt);
+    uint32_t *p, *p_alt;
+    uint64_t *kd, *kd_alt;
+    if (!full) {
+        k_edge_du_keys<<<grid_for(n), 256, 0, st>>>(b.eud, n, b.k0, b.v0);
+        int sh[8], q = 0;
+        for (int s = 0; s < ib; s += 8) sh[q++] = s;
+        for (int s = 32; s < 64; s += 8) sh[q++] = s;
+        HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, sh, q, &in1));
+        p = in1 ? b.v1 : b.v0;
+        kd = in1 ? b.k1 : b.k0;
+        kd_alt = in1 ? b.k0 : b.k1;
+        p_alt = in1 ? b.v0 : b.v1;
+        k_tie_fix<<<grid_for(n), 256, 0, st>>>(kd, p, b.eud, n, b.ctrl);
+    } else {
+        k_edge_keys<<<grid_for(n), 256, 0, st>>>(b.eud, n, b.k0, b.v0);
+        int sh[8], q = 0;
+        for (int s = 0; s < ib; s += 8) sh[q++] = s;
+        for (int s = 0; s < ib; s += 8) sh[q++] = 32 + s;
+        HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, sh, q, &in1));
+        p = in1 ? b.v1 : b.v0;
+        kd = in1 ? b.k1 : b.k0;
+        kd_alt = in1 ? b.k0 : b.k1;
+        p_alt = in1 ? b.v0 : b.v1;
+        k_edge_dkeys<<<grid_for(n), 256, 0, st>>>(b.eud, p, n, kd);
+        const int dsh[4] = {0, 8, 16, 24};
+        HIP_TRY(radix_sort_pairs(st, kd, p, kd_alt, p_alt, b.hist, n, dsh, 4, &in1));
+        if (in1) {
+            std::swap(p, p_alt);
+            std::swap(kd, kd_alt);
+        }
     }
     if (slot_cloud && cloud_bits > 0) {
-        k_edge_dkeys<<<grid_for(n), 256, 0, st>>>(slot_cloud, p, n, kd);
+        k_perm_keys<<<grid_for(n), 256, 0, st>>>(slot_cloud, p, n, kd);
         int csh[4], cq = 0;
         for (int s = 0; s < cloud_bits; s += 8) csh[cq++] = s;
         HIP_TRY(radix_sort_pairs(st, kd, p, kd_alt, p_alt, b.hist, n, csh, cq, &in1));
@@ -1332,7 +1401,7 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     const uint32_t* perm = in1 ? b.v1 : b.v0;
     // ---- hierarchy + boxes
     k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
-                                               b.compmax, b.exch, b.eu, b.ev, b.ed);
+                                               b.compmax, b.exch, b.eud);
     if (int rc = build_tree<DIM>(ctx, b, codes, n, st)) return rc;
     const uint32_t root = ctx->h_ctrl->root;
     S.tree_height = (int32_t)ctx->h_ctrl->height;
@@ -1348,13 +1417,16 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     if (ctx->h_ctrl->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
 
-    // ---- canonical order
+    // ---- canonical order (the full sort only after a long run of ties)
     const uint32_t* order = nullptr;
-    if (int rc = sort_edges<DIM>(ctx, b, n, nullptr, 0, &order, st)) return rc;
-    k_edge_write<<<grid_for(n - 1), 256, 0, st>>>(b.eu, b.ev, b.ed, order, n - 1, edges, weights, d2);
-    HIP_TRY(hipGetLastError());
-    if (prof) HIP_TRY(hipEventRecord(E[3], st));
-    HIP_TRY(hipStreamSynchronize(st));
+    for (int full = 0; full < 2; ++full) {
+        if (int rc = sort_edges<DIM>(ctx, b, n, nullptr, 0, full != 0, &order, st)) return rc;
+        k_edge_write<<<grid_for(n - 1), 256, 0, st>>>(b.eud, order, n - 1, edges, weights, d2);
+        HIP_TRY(hipGetLastError());
+        if (prof) HIP_TRY(hipEventRecord(E[3], st));
+        if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+        if (!ctx->h_ctrl->long_ties) break;
+    }
     finish_stats(ctx, S);
     return EMST_OK;
 }
@@ -1449,7 +1521,7 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     const uint32_t* perm = in1 ? b.v1 : b.v0;
     // ---- one tree over all clouds
     k_gather<3><<<grid_for(n), 256, 0, st>>>(pts3, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
-                                             b.compmax, b.exch, b.eu, b.ev, b.ed);
+                                             b.compmax, b.exch, b.eud);
     k_batch_sorted_cloud<<<grid_for(n), 256, 0, st>>>(cloud_of, perm, n, cloud_sorted);
     if (int rc = build_tree<3>(ctx, b, codes, n, st)) return rc;
     k_fill_u32<<<grid_for(B), 256, 0, st>>>(d_croot, B, kNone);
@@ -1470,14 +1542,16 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     if ((int64_t)ctx->h_ctrl->edge_count != eoff) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
 
-    // ---- per-cloud canonical order
+    // ---- per-cloud canonical order (the full sort only after a long run of ties)
     const uint32_t* order = nullptr;
-    if (int rc = sort_edges<3>(ctx, b, n, cloud_sorted, cloud_bits, &order, st)) return rc;
-    k_batch_edge_write<<<grid_for(n), 256, 0, st>>>(b.eu, b.ev, b.ed, order, cloud_sorted, d_cin, n, edges, weights,
-                                                    d2);
-    HIP_TRY(hipGetLastError());
-    if (prof) HIP_TRY(hipEventRecord(E[3], st));
-    HIP_TRY(hipStreamSynchronize(st));
+    for (int full = 0; full < 2; ++full) {
+        if (int rc = sort_edges<3>(ctx, b, n, cloud_sorted, cloud_bits, full != 0, &order, st)) return rc;
+        k_batch_edge_write<<<grid_for(n), 256, 0, st>>>(b.eud, order, cloud_sorted, d_cin, n, edges, weights, d2);
+        HIP_TRY(hipGetLastError());
+        if (prof) HIP_TRY(hipEventRecord(E[3], st));
+        if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+        if (!ctx->h_ctrl->long_ties) break;
+    }
     finish_stats(ctx, S);
     return EMST_OK;
 }
@@ -1698,7 +1772,7 @@ extern "C" int emst_test_tree_boxes(emst_ctx* ctx, const float* d_points, int64_
     const uint64_t* codes = in1 ? b.k1 : b.k0;
     const uint32_t* perm = in1 ? b.v1 : b.v0;
     k_gather<3><<<grid_for(n), 256, 0, st>>>(d_points, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
-                                             b.compmax, b.exch, b.eu, b.ev, b.ed);
+                                             b.compmax, b.exch, b.eud);
     if (int rc = build_tree<3>(ctx, b, codes, n, st)) return rc;
     k_test_boxes<<<grid_for(n - 1), 256, 0, st>>>(b.recs, n - 1, d_left, d_right, d_lo, d_hi);
     HIP_TRY(hipGetLastError());

@@ -22,7 +22,8 @@ struct Ctrl {
     unsigned long long leaf_tests;
     unsigned long long dist_evals;
     unsigned long long trav_next;   // next query handed out by the persistent traversal
-    uint32_t pad[6];
+    uint32_t long_ties;      // the edge order met a run of equal keys too long to fix in place
+    uint32_t pad[5];
 };
 
 constexpr uint32_t kErrStack = 1u;

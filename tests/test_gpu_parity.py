@@ -60,6 +60,25 @@ def test_small_clouds(ctx, n, dim, seed, kind, variant):
     assert_same(run(ctx, pts, variant), oracle.prim(pts), f"{kind} n={n} d={dim}")
 
 
+@pytest.mark.parametrize("dim,span", [(2, 6000), (3, 600)])
+def test_short_runs_of_equal_edge_lengths(ctx, dim, span):
+    """Integer coordinates over a wide range: a few pairs of MST edges share
+    their smaller endpoint u and have exactly equal D, so the (D, u)-sorted
+    edge order needs its in-place v fix-up; heavy-tie inputs (grids,
+    duplicates) take the full sort instead."""
+    ties_seen = 0
+    for seed in range(6):
+        rng = np.random.default_rng(500 + seed)
+        pts = rng.integers(0, span, (3000, dim)).astype(np.float32)
+        ref = oracle.prim(pts)
+        print(f"case dim={dim} seed={500 + seed}", flush=True)
+        assert_same(run(ctx, pts), ref, f"int-wide dim={dim} seed={seed}")
+        k = (ref.d2.view(np.uint32).astype(np.uint64) << np.uint64(32)) | ref.edges[:, 0].astype(np.uint64)
+        k = np.sort(k)
+        ties_seen += int((k[1:] == k[:-1]).sum())
+    assert ties_seen > 0
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_closed_forms(ctx, variant):
     cases = {
