@@ -258,26 +258,50 @@ __global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ sp
     set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), p, p);
 }
 
-// Nodes of height h: box = union of the two child boxes in the own record,
-// stored in the parent's record.  Children have smaller heights, so the
-// launch of the previous level has written them.
-template <int DIM>
-__global__ __launch_bounds__(256) void k_fit_level(const uint8_t* __restrict__ height,
-                                                   const uint32_t* __restrict__ node_parent, int64_t m, uint32_t h,
-                                                   Rec<DIM>* recs) {
+// Nodes grouped by height: keys = height, values = node id, for one stable
+// radix pass; then the first sorted position of every height.  Heights of
+// internal nodes run without gaps from 1 to the root's.
+__global__ __launch_bounds__(256) void k_height_keys(const uint8_t* __restrict__ height, int64_t m,
+                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m || height[k] != h) return;
-    const uint32_t link = node_parent[k];
-    if (link == kNone) return;
-    Child<DIM> c0, c1;
-    unpack<DIM>(recs[k], c0, c1);
-    float lo[DIM], hi[DIM];
+    if (k >= m) return;
+    keys[k] = height[k];
+    vals[k] = (uint32_t)k;
+}
+
+__global__ __launch_bounds__(256) void k_level_starts(const uint64_t* __restrict__ keys, int64_t m,
+                                                      uint32_t* __restrict__ starts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t h = (uint32_t)keys[i];
+    if (i == 0 || keys[i - 1] != h) starts[h] = (uint32_t)i;
+    if (i == m - 1) starts[h + 1] = (uint32_t)m;
+}
+
+// Nodes of height h (sorted positions [starts[h], starts[h+1])): box = union
+// of the two child boxes in the own record, stored in the parent's record.
+// Children have smaller heights, so the launch of the previous level has
+// written them.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_fit_level(const uint32_t* __restrict__ ids,
+                                                   const uint32_t* __restrict__ starts, uint32_t h,
+                                                   const uint32_t* __restrict__ node_parent, Rec<DIM>* recs) {
+    const int64_t end = starts[h + 1];
+    for (int64_t j = starts[h] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < end;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = ids[j];
+        const uint32_t link = node_parent[k];
+        if (link == kNone) continue;
+        Child<DIM> c0, c1;
+        unpack<DIM>(recs[k], c0, c1);
+        float lo[DIM], hi[DIM];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        lo[d] = fminf(c0.lo[d], c1.lo[d]);
-        hi[d] = fmaxf(c0.hi[d], c1.hi[d]);
+        for (int d = 0; d < DIM; ++d) {
+            lo[d] = fminf(c0.lo[d], c1.lo[d]);
+            hi[d] = fmaxf(c0.hi[d], c1.hi[d]);
+        }
+        set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), lo, hi);
     }
-    set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), lo, hi);
 }
 
 __device__ __forceinline__ uint32_t compact3(uint64_t x) {
@@ -473,56 +497,36 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, 
                                                 const uint32_t* __restrict__ cloud_of, int64_t n, uint32_t* ub,
                                                 Ctrl* ctrl) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = lane_id();
     if (k == 0) {
         ctrl->ncomp_next = 0u;
         ctrl->trav_next = 0ull;
     }
-    // every position loads itself once; the right neighbour comes from the
-    // next lane (the last lane of a wave loads it)
+    // every position reads itself and both neighbours directly (cached
+    // re-reads), so the wave waits for memory once
     const bool valid = k < n;
-    uint32_t lab = kNone, cl = 0u;
-    float p[DIM];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) p[c] = 0.f;
+    uint32_t v = kInfBits, lab = kNone;
     if (valid) {
+        const int64_t kl = k > 0 ? k - 1 : k, kr = k + 1 < n ? k + 1 : k;
         lab = labels[k];
-        if (cloud_of) cl = cloud_of[k];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) p[c] = spts[k * DIM + c];
-    }
-    uint32_t rlab = __shfl_down(lab, 1), rcl = __shfl_down(cl, 1);
-    float q[DIM];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) q[c] = __shfl_down(p[c], 1);
-    if (lane == 63) {
-        rlab = kNone;
-        if (k + 1 < n) {
-            rlab = labels[k + 1];
-            rcl = cloud_of ? cloud_of[k + 1] : 0u;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) q[c] = spts[(k + 1) * DIM + c];
+        const uint32_t llab = labels[kl], rlab = labels[kr];
+        uint32_t cl = 0u, lcl = 0u, rcl = 0u;
+        if (cloud_of) {
+            cl = cloud_of[k];
+            lcl = cloud_of[kl];
+            rcl = cloud_of[kr];
         }
-    }
-    // D of the pair (k, k+1) if it joins two components of one cloud
-    const bool right = valid && k + 1 < n && rlab != lab && rcl == cl;
-    const uint32_t dr = right ? fbits(sqdist<DIM>(p, q)) : kInfBits;
-    // the pair (k-1, k) was computed by the previous lane
-    uint32_t dl = __shfl_up(dr, 1);
-    if (lane == 0) {
-        dl = kInfBits;
-        if (valid && k > 0) {
-            const uint32_t llab = labels[k - 1];
-            const uint32_t lcl = cloud_of ? cloud_of[k - 1] : 0u;
-            if (llab != lab && lcl == cl) {
-                float o[DIM];
+        float p[DIM], o[DIM], q[DIM];
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) o[c] = spts[(k - 1) * DIM + c];
-                dl = fbits(sqdist<DIM>(o, p));
-            }
+        for (int c = 0; c < DIM; ++c) {
+            p[c] = spts[k * DIM + c];
+            o[c] = spts[kl * DIM + c];
+            q[c] = spts[kr * DIM + c];
         }
+        // D of the pairs (k-1, k) and (k, k+1) when they join two components
+        // of one cloud (D(k-1, k) evaluated as the previous position does)
+        if (llab != lab && lcl == cl) v = min(v, fbits(sqdist<DIM>(o, p)));
+        if (rlab != lab && rcl == cl) v = min(v, fbits(sqdist<DIM>(p, q)));
     }
-    uint32_t v = min(dl, dr);
     if (FIRST) {
         if (valid) ub[k] = v;
         return;
@@ -1338,8 +1342,23 @@ int build_tree(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hi
     const uint32_t root = ctx->h_ctrl->root, H = ctx->h_ctrl->height;
     if (root == kNone || root >= (uint32_t)(n - 1) || ctx->h_ctrl->error || H > 128)
         return fail(ctx, EMST_EINTERNAL, "tree construction failed");
-    for (uint32_t h = 1; h < H; ++h)  // the root (height H) has no parent record
-        k_fit_level<DIM><<<grid_for(n - 1), 256, 0, st>>>(b.height, b.node_parent, n - 1, h, b.recs);
+    // node ids grouped by height (the exchange words, the free key buffer and
+    // the index buffers are dead by now), then one launch per height below
+    // the root (the root, height H, has no parent record)
+    const int64_t m = n - 1;
+    uint64_t* hkeys = b.exch;
+    uint64_t* kfree = (codes == b.k0) ? b.k1 : b.k0;
+    k_height_keys<<<grid_for(m), 256, 0, st>>>(b.height, m, hkeys, b.v0);
+    const int hshift = 0;
+    int in1 = 0;
+    HIP_TRY(radix_sort_pairs(st, hkeys, b.v0, kfree, b.v1, b.hist, m, &hshift, 1, &in1));
+    const uint64_t* skeys = in1 ? kfree : hkeys;
+    const uint32_t* ids = in1 ? b.v1 : b.v0;
+    uint32_t* starts = b.hist;  // the sort's histogram is free again
+    k_level_starts<<<grid_for(m), 256, 0, st>>>(skeys, m, starts);
+    const unsigned fgrid = std::min<unsigned>(grid_for(m), 1024);
+    for (uint32_t h = 1; h < H; ++h)
+        k_fit_level<DIM><<<fgrid, 256, 0, st>>>(ids, starts, h, b.node_parent, b.recs);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
 }
