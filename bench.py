@@ -43,6 +43,8 @@ TRAFFIC_SOURCES = ("traverse.h", "emst_common.h", "emst_kernels.h")
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 MEASURED_TRAFFIC = {
     # (workload, variant, source hash): (FETCH_SIZE KiB, WRITE_SIZE KiB, TCC hit fraction, profile)
+    ("clustered3d_2m", 10, "e873c24fee91cffd"):
+        (72378.0, 22329.6, 0.929, "profiles/k_traverse_fast_clustered3d_2m.md"),
 }
 
 
