@@ -17,6 +17,11 @@ Contents
                     and the bottom-up label propagation of Section 3,
                     Optimization 1 (pure Python; small inputs)
 * invariant checkers: spanning tree, cycle property, round structure.
+* mutual reachability (Section 4, "Mutual reachability distance"):
+  ``core_distances`` (brute force by sorting, or a kd-tree k-nearest
+  search), ``prim_mreach`` / ``kdboruvka_mreach`` / ``mreach_mst`` (the MST
+  under M(u, v) = max(core2(u), core2(v), D(u, v)) and the same tie-break),
+  and the numpy checks ``core_bruteforce`` / ``kruskal_bruteforce(core2=)``.
 
 The key K(u, v) = (bits(D(u, v)), min(u, v), max(u, v)) is the paper's
 tie-break (Section 2, Boruvka's algorithm) applied to the float32 squared
@@ -71,6 +76,14 @@ def lib():
         L.oracle_canonicalize.restype = ctypes.c_int
         L.oracle_total_weight.argtypes = [ctypes.c_int64, f32p]
         L.oracle_total_weight.restype = ctypes.c_double
+        L.oracle_prim_mreach.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, f32p, i32p, f32p]
+        L.oracle_prim_mreach.restype = ctypes.c_int
+        L.oracle_kdboruvka_mreach.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, f32p, i32p, f32p,
+                                              ctypes.c_int, i64p, i64p]
+        L.oracle_kdboruvka_mreach.restype = ctypes.c_int
+        for f in ("oracle_core_brute", "oracle_core_kd"):
+            getattr(L, f).argtypes = [f32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, f32p, ctypes.c_int]
+            getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -157,6 +170,74 @@ def emst(points, threads: int = 1) -> MST:
 
 
 # ----------------------------------------------------------------------------
+# mutual reachability (Section 4, "Mutual reachability distance")
+
+
+def core_distances(points, k_pts: int, method: str = "kd", threads: int = 1) -> np.ndarray:
+    """Squared core distance of every point: the k_pts-th smallest of the
+    values D(u, v) over all v, the point itself (D = 0) included."""
+    pts = _points(points)
+    n, dim = pts.shape
+    out = np.zeros(n, np.float32)
+    if n == 0:
+        return out
+    fn = lib().oracle_core_kd if method == "kd" else lib().oracle_core_brute
+    rc = fn(_p(pts, ctypes.c_float), n, dim, int(k_pts), _p(out, ctypes.c_float), int(threads))
+    if rc != 0:
+        raise RuntimeError(f"core distances failed: {rc}")
+    return out
+
+
+def prim_mreach(points, core2) -> MST:
+    pts = _points(points)
+    c = np.ascontiguousarray(np.asarray(core2, dtype=np.float32))
+    n, dim = pts.shape
+    m = max(n - 1, 0)
+    e = np.zeros((m, 2), np.int32)
+    d = np.zeros(m, np.float32)
+    rc = lib().oracle_prim_mreach(_p(pts, ctypes.c_float), n, dim, _p(c, ctypes.c_float),
+                                  _p(e, ctypes.c_int32), _p(d, ctypes.c_float))
+    if rc != 0:
+        raise RuntimeError(f"oracle_prim_mreach failed: {rc}")
+    return canonicalize(e, d)
+
+
+def kdboruvka_mreach(points, core2, threads: int = 1) -> MST:
+    pts = _points(points)
+    c = np.ascontiguousarray(np.asarray(core2, dtype=np.float32))
+    n, dim = pts.shape
+    m = max(n - 1, 0)
+    e = np.zeros((m, 2), np.int32)
+    d = np.zeros(m, np.float32)
+    rounds = np.zeros(1, np.int64)
+    comps = np.zeros(64, np.int64)
+    rc = lib().oracle_kdboruvka_mreach(_p(pts, ctypes.c_float), n, dim, _p(c, ctypes.c_float),
+                                       _p(e, ctypes.c_int32), _p(d, ctypes.c_float), int(threads),
+                                       _p(rounds, ctypes.c_int64), _p(comps, ctypes.c_int64))
+    if rc != 0:
+        raise RuntimeError(f"oracle_kdboruvka_mreach failed: {rc}")
+    out = canonicalize(e, d)
+    out.rounds = int(rounds[0])
+    out.comps = comps[:out.rounds].copy()
+    return out
+
+
+def mreach_mst(points, k_pts: int, threads: int = 1):
+    """(MST under M, squared core distances) for any size."""
+    pts = _points(points)
+    core2 = core_distances(pts, k_pts, "kd", threads)
+    if pts.shape[0] <= 4000:
+        return prim_mreach(pts, core2), core2
+    return kdboruvka_mreach(pts, core2, threads), core2
+
+
+def core_bruteforce(points, k_pts: int) -> np.ndarray:
+    """numpy: the k_pts-th smallest entry of every row of the D matrix."""
+    D = pair_d2_matrix(points)
+    return np.sort(D, axis=1)[:, k_pts - 1].astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
 # numpy brute force (small n)
 
 
@@ -174,14 +255,18 @@ def pair_d2_matrix(points) -> np.ndarray:
     return s.astype(np.float32)
 
 
-def kruskal_bruteforce(points) -> MST:
+def kruskal_bruteforce(points, core2=None) -> MST:
     """Kruskal (Section 2): sort all pairs by K, add every pair that joins
-    two different components (union-find)."""
+    two different components (union-find).  With core2, the weight of a
+    pair is M = max(core2[u], core2[v], D)."""
     pts = _points(points)
     n = pts.shape[0]
     if n < 2:
         return canonicalize(np.zeros((0, 2), np.int32), np.zeros(0, np.float32))
     D = pair_d2_matrix(pts)
+    if core2 is not None:
+        c = np.asarray(core2, dtype=np.float32)
+        D = np.maximum(np.maximum(D, c[:, None]), c[None, :]).astype(np.float32)
     iu, ju = np.triu_indices(n, k=1)
     w = D[iu, ju].view(np.uint32)
     order = np.lexsort((ju, iu, w))  # primary w, then min (=iu), then max (=ju)
@@ -250,14 +335,19 @@ def check_spanning_tree(n: int, edges) -> None:
         par[max(ra, rb)] = min(ra, rb)
 
 
-def check_cycle_property(points, mst: MST) -> None:
+def check_cycle_property(points, mst: MST, core2=None) -> None:
     """Every non-tree pair's key exceeds the largest key on its tree path
-    (the cycle property that characterises the unique MST under K)."""
+    (the cycle property that characterises the unique MST under K; with
+    core2, under the key of M)."""
     pts = _points(points)
     n = pts.shape[0]
     if n < 3:
         return
-    D = pair_d2_matrix(pts).view(np.uint32).astype(np.int64)
+    W = pair_d2_matrix(pts)
+    if core2 is not None:
+        c = np.asarray(core2, dtype=np.float32)
+        W = np.maximum(np.maximum(W, c[:, None]), c[None, :]).astype(np.float32)
+    D = W.view(np.uint32).astype(np.int64)
     adj = [[] for _ in range(n)]
     for (u, v), d in zip(mst.edges.tolist(), mst.d2.view(np.uint32).tolist()):
         adj[u].append((v, d))

@@ -34,6 +34,23 @@
  *                       "extreme case" of Section 3, Optimization 2)
  *   oracle_canonicalize sort edges by K, weights = sqrtf(D)
  *
+ * Mutual reachability (Section 4, "Mutual reachability distance"; Section 3,
+ * "Non-Euclidean metrics"): the core distance of u is the distance to its
+ * k_pts-th nearest neighbour counting u itself, and the mutual reachability
+ * of u and v is the largest of core(u), core(v) and |u - v|.  Squaring is
+ * monotone on non-negative values, so in squared terms
+ *
+ *       M(u, v) = max(core2(u), core2(v), D(u, v)),   core2 = squared core,
+ *
+ * and the tree is the MST under (bits(M), min, max).  With k_pts = 1 every
+ * core distance is 0 (the point itself) and M = D.
+ *   oracle_core_brute   core2 by sorting all n values D(u, .) per point
+ *   oracle_core_kd      core2 by a kd-tree k-nearest search
+ *   oracle_prim_mreach, oracle_kdboruvka_mreach
+ *                       the two MST routines above under M (core2 given);
+ *                       the kd-tree search still prunes by the Euclidean
+ *                       box distance, a lower bound of M
+ *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -fPIC -shared
  */
 #include <math.h>
@@ -89,9 +106,16 @@ static inline int key_lt(okey a, okey b) {
     return a.v < b.v;
 }
 
-static inline okey make_key(const float *pts, int dim, int64_t i, int64_t j) {
+/* core2 == NULL: the key of D; else the key of M (all values are
+ * non-negative, so comparing them as floats is comparing their bits). */
+static inline okey make_key(const float *pts, int dim, const float *core2, int64_t i, int64_t j) {
     okey k;
-    k.w = fbits(sqdist(pts + i * dim, pts + j * dim, dim));
+    float w = sqdist(pts + i * dim, pts + j * dim, dim);
+    if (core2) {
+        if (core2[i] > w) w = core2[i];
+        if (core2[j] > w) w = core2[j];
+    }
+    k.w = fbits(w);
     k.u = (uint32_t)(i < j ? i : j);
     k.v = (uint32_t)(i < j ? j : i);
     return k;
@@ -101,7 +125,7 @@ static inline okey make_key(const float *pts, int dim, int64_t i, int64_t j) {
 /* dense Prim: the tree grows from vertex 0; every step adds the outside
  * vertex whose cheapest connection to the tree is smallest under K.        */
 
-int oracle_prim(const float *pts, int64_t n, int dim, int32_t *edges, float *d2) {
+static int prim_impl(const float *pts, int64_t n, int dim, const float *core2, int32_t *edges, float *d2) {
     if (n < 2) return 0;
     if (dim < 1) return -1;
     unsigned int csr = fp_enter();
@@ -109,7 +133,7 @@ int oracle_prim(const float *pts, int64_t n, int dim, int32_t *edges, float *d2)
     unsigned char *in_tree = (unsigned char *)calloc((size_t)n, 1);
     if (!best || !in_tree) { free(best); free(in_tree); fp_leave(csr); return -4; }
     in_tree[0] = 1;
-    for (int64_t v = 1; v < n; ++v) best[v] = make_key(pts, dim, 0, v);
+    for (int64_t v = 1; v < n; ++v) best[v] = make_key(pts, dim, core2, 0, v);
     for (int64_t step = 0; step + 1 < n; ++step) {
         int64_t pick = -1;
         for (int64_t v = 0; v < n; ++v)
@@ -121,7 +145,7 @@ int oracle_prim(const float *pts, int64_t n, int dim, int32_t *edges, float *d2)
         in_tree[pick] = 1;
         for (int64_t w = 0; w < n; ++w) {
             if (in_tree[w]) continue;
-            okey k = make_key(pts, dim, pick, w);
+            okey k = make_key(pts, dim, core2, pick, w);
             if (key_lt(k, best[w])) best[w] = k;
         }
     }
@@ -129,6 +153,14 @@ int oracle_prim(const float *pts, int64_t n, int dim, int32_t *edges, float *d2)
     free(in_tree);
     fp_leave(csr);
     return 0;
+}
+
+int oracle_prim(const float *pts, int64_t n, int dim, int32_t *edges, float *d2) {
+    return prim_impl(pts, n, dim, NULL, edges, d2);
+}
+
+int oracle_prim_mreach(const float *pts, int64_t n, int dim, const float *core2, int32_t *edges, float *d2) {
+    return prim_impl(pts, n, dim, core2, edges, d2);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -265,7 +297,7 @@ static int64_t uf_find(int64_t *par, int64_t x) {
 /* nearest other-component search for one point, sharing the component's
  * running best key (Algorithm 2 with the bound updated at every leaf).     */
 
-static void query_point(const kdtree *t, const uint32_t *lab, const uint32_t *node_comp,
+static void query_point(const kdtree *t, const float *core2, const uint32_t *lab, const uint32_t *node_comp,
                         int64_t i, okey *best, int32_t *stack) {
     const int dim = t->dim;
     const float *p = t->pts + i * dim;
@@ -281,7 +313,7 @@ static void query_point(const kdtree *t, const uint32_t *lab, const uint32_t *no
             for (int64_t q = nd->begin; q < nd->end; ++q) {
                 int32_t j = t->idx[q];
                 if (lab[j] == c) continue;
-                okey k = make_key(t->pts, dim, i, j);
+                okey k = make_key(t->pts, dim, core2, i, j);
                 if (key_lt(k, *best)) *best = k;
             }
         } else {
@@ -297,8 +329,8 @@ static void query_point(const kdtree *t, const uint32_t *lab, const uint32_t *no
 /* Boruvka over the kd-tree.  rounds_out (nullable) gets the number of
  * rounds; comps_out (nullable, capacity >= 64) gets the component count at
  * the start of every round.  nthreads <= 0 uses the OpenMP default. */
-int oracle_kdboruvka(const float *pts, int64_t n, int dim, int32_t *edges, float *d2,
-                     int nthreads, int64_t *rounds_out, int64_t *comps_out) {
+static int kdboruvka_impl(const float *pts, int64_t n, int dim, const float *core2, int32_t *edges, float *d2,
+                          int nthreads, int64_t *rounds_out, int64_t *comps_out) {
     if (rounds_out) *rounds_out = 0;
     if (n < 2) return 0;
     if (dim < 1 || dim > 3) return -1;
@@ -365,7 +397,7 @@ int oracle_kdboruvka(const float *pts, int64_t n, int dim, int32_t *edges, float
 #pragma omp for schedule(dynamic, 64)
             for (int64_t c = 0; c < n; ++c) {
                 for (int64_t q = cstart[c]; q < cstart[c + 1]; ++q)
-                    query_point(&t, lab, node_comp, members[q], &best[c], stk);
+                    query_point(&t, core2, lab, node_comp, members[q], &best[c], stk);
             }
         }
         /* (v) add every component's shortest outgoing edge; a mutual pair
@@ -390,6 +422,132 @@ int oracle_kdboruvka(const float *pts, int64_t n, int dim, int32_t *edges, float
 done:
     free(t.idx); free(t.nodes); free(par); free(lab); free(best);
     free(cstart); free(members); free(fill); free(node_comp);
+    fp_leave(csr);
+    return rc;
+}
+
+int oracle_kdboruvka(const float *pts, int64_t n, int dim, int32_t *edges, float *d2,
+                     int nthreads, int64_t *rounds_out, int64_t *comps_out) {
+    return kdboruvka_impl(pts, n, dim, NULL, edges, d2, nthreads, rounds_out, comps_out);
+}
+
+int oracle_kdboruvka_mreach(const float *pts, int64_t n, int dim, const float *core2, int32_t *edges, float *d2,
+                            int nthreads, int64_t *rounds_out, int64_t *comps_out) {
+    return kdboruvka_impl(pts, n, dim, core2, edges, d2, nthreads, rounds_out, comps_out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* core distances (Section 4, "Mutual reachability distance")               */
+
+static int cmp_float(const void *a, const void *b) {
+    float x = *(const float *)a, y = *(const float *)b;
+    return (x < y) ? -1 : (x > y) ? 1 : 0;
+}
+
+/* core2[u] = the k-th smallest of the n values D(u, v), v = 0..n-1 (v = u
+ * gives 0: the point itself counts).  1 <= k <= n. */
+int oracle_core_brute(const float *pts, int64_t n, int dim, int k, float *core2, int nthreads) {
+    if (n < 1) return 0;
+    if (dim < 1 || k < 1 || k > n) return -1;
+    unsigned int csr = fp_enter();
+    int rc = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        fp_enter();
+        float *row = (float *)malloc((size_t)n * sizeof(float));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t u = 0; u < n; ++u) {
+            if (!row) { rc = -4; continue; }
+            for (int64_t v = 0; v < n; ++v) row[v] = sqdist(pts + u * dim, pts + v * dim, dim);
+            qsort(row, (size_t)n, sizeof(float), cmp_float);
+            core2[u] = row[k - 1];
+        }
+        free(row);
+    }
+    fp_leave(csr);
+    return rc;
+}
+
+/* The same by a k-nearest search over the kd-tree: a max-heap keeps the k
+ * smallest values seen (the point itself is among the candidates); a box is
+ * skipped when the heap is full and its box distance exceeds the heap top. */
+static void heap_push(float *h, int *len, int k, float x) {
+    if (*len < k) {
+        int i = (*len)++;
+        h[i] = x;
+        while (i > 0 && h[(i - 1) / 2] < h[i]) {
+            float tmp = h[i]; h[i] = h[(i - 1) / 2]; h[(i - 1) / 2] = tmp;
+            i = (i - 1) / 2;
+        }
+    } else if (x < h[0]) {
+        h[0] = x;
+        int i = 0;
+        for (;;) {
+            int l = 2 * i + 1, r = l + 1, m = i;
+            if (l < k && h[l] > h[m]) m = l;
+            if (r < k && h[r] > h[m]) m = r;
+            if (m == i) break;
+            float tmp = h[i]; h[i] = h[m]; h[m] = tmp;
+            i = m;
+        }
+    }
+}
+
+int oracle_core_kd(const float *pts, int64_t n, int dim, int k, float *core2, int nthreads) {
+    if (n < 1) return 0;
+    if (dim < 1 || dim > 3 || k < 1 || k > n) return -1;
+    unsigned int csr = fp_enter();
+    int rc = 0;
+    kdtree t;
+    memset(&t, 0, sizeof(t));
+    t.pts = pts;
+    t.dim = dim;
+    t.idx = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!t.idx) { fp_leave(csr); return -4; }
+    for (int64_t i = 0; i < n; ++i) t.idx[i] = (int32_t)i;
+    rc = kd_build(&t, n);
+    if (rc) { free(t.idx); free(t.nodes); fp_leave(csr); return rc; }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        fp_enter();
+        float *heap = (float *)malloc((size_t)k * sizeof(float));
+        int32_t stk[KD_STACK];
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t u = 0; u < n; ++u) {
+            if (!heap) { rc = -4; continue; }
+            const float *p = pts + u * dim;
+            int len = 0;
+            int64_t sp = 0;
+            stk[sp++] = 0;
+            while (sp > 0) {
+                const kdnode *nd = &t.nodes[stk[--sp]];
+                if (len == k && boxdist(p, nd, dim) > heap[0]) continue;
+                if (nd->left < 0) {
+                    for (int64_t q = nd->begin; q < nd->end; ++q)
+                        heap_push(heap, &len, k, sqdist(p, pts + (int64_t)t.idx[q] * dim, dim));
+                } else {
+                    float dl = boxdist(p, &t.nodes[nd->left], dim);
+                    float dr = boxdist(p, &t.nodes[nd->right], dim);
+                    if (dl <= dr) { stk[sp++] = nd->right; stk[sp++] = nd->left; }
+                    else { stk[sp++] = nd->left; stk[sp++] = nd->right; }
+                }
+            }
+            core2[u] = heap[0];
+        }
+        free(heap);
+    }
+    free(t.idx);
+    free(t.nodes);
     fp_leave(csr);
     return rc;
 }
