@@ -69,9 +69,9 @@ void emst_destroy(emst_ctx *ctx);
 /* Message of the last failing call on this context ("" if none). */
 const char *emst_last_error(const emst_ctx *ctx);
 
-/* Exact number of workspace bytes emst_build needs for n points of
- * dimension dim (0 for invalid arguments).  Grows linearly in n, about
- * 225 bytes per point in 3D. */
+/* Exact number of workspace bytes emst_build, emst_core_distances and
+ * emst_build_mreach need for n points of dimension dim (0 for invalid
+ * arguments).  Grows linearly in n, 237 bytes per point in 3D. */
 size_t emst_workspace_bytes(int64_t n, int dim);
 
 /*
@@ -127,6 +127,49 @@ int emst_build_batched(emst_ctx *ctx, const float *d_points, const int64_t *h_of
                        const int32_t *h_dims, int32_t n_clouds, int32_t *d_edges,
                        float *d_weights, float *d_d2, int64_t *h_edge_offsets,
                        void *d_workspace, size_t ws_bytes, void *stream);
+
+/*
+ * emst_core_distances -- squared core distances of the mutual reachability
+ * metric (Section 4, "Mutual reachability distance"): the core distance of
+ * point i is its distance to the k_pts-th nearest point, i itself counted
+ * (so k_pts = 1 gives 0).
+ *
+ *  d_points, n, dim   as for emst_build.
+ *  k_pts      1 <= k_pts <= min(n, 64).
+ *  d_core2    [n] float32 out, input order: the k_pts-th smallest D(i, j)
+ *             over all j (float32 D as for emst_build, so bit-exact).
+ *  d_workspace, ws_bytes   >= emst_workspace_bytes(n, dim).
+ *
+ * Errors: EMST_EINVAL (also for k_pts out of range), EMST_ENONFINITE,
+ * EMST_ERANGE, EMST_ENOMEM, EMST_EHIP, EMST_EINTERNAL.  Returns when the
+ * result is complete on `stream`.
+ */
+int emst_core_distances(emst_ctx *ctx, const float *d_points, int64_t n, int dim, int32_t k_pts,
+                        float *d_core2, void *d_workspace, size_t ws_bytes, void *stream);
+
+/*
+ * emst_build_mreach -- minimum spanning tree under the mutual reachability
+ * of HDBSCAN* (Section 4, "Mutual reachability distance"; Section 3,
+ * "Non-Euclidean metrics"):
+ *
+ *   M(u, v) = max(core2(u), core2(v), D(u, v))      (squared terms)
+ *
+ * with core2 as emst_core_distances computes it; the tree is the unique
+ * MST under (bits(M), min(u, v), max(u, v)).  k_pts = 1 gives the EMST.
+ *
+ *  d_points, n, dim, d_edges   as for emst_build (edges sorted by that key).
+ *  k_pts      1 <= k_pts <= min(n, 64).
+ *  d_weights  [n-1] float32 out: sqrtf(M) of each edge.
+ *  d_d2       [n-1] float32 out, or NULL: M of each edge.
+ *  d_core2    [n] float32 out, or NULL: the squared core distances.
+ *  d_workspace, ws_bytes   >= emst_workspace_bytes(n, dim).
+ *
+ * n = 0 or 1 writes no edges and returns EMST_OK.  Errors as for
+ * emst_core_distances.
+ */
+int emst_build_mreach(emst_ctx *ctx, const float *d_points, int64_t n, int dim, int32_t k_pts,
+                      int32_t *d_edges, float *d_weights, float *d_d2, float *d_core2,
+                      void *d_workspace, size_t ws_bytes, void *stream);
 
 /* Per-call statistics of the last successful emst_build or
  * emst_build_batched on this context.

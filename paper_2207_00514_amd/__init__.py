@@ -32,6 +32,7 @@ EXPORTS = [
     "emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_get_stats",
     "emst_test_tree_from_codes", "emst_test_radix_sort",
     "emst_workspace_bytes_batched", "emst_build_batched", "emst_test_tree_boxes",
+    "emst_core_distances", "emst_build_mreach",
 ]
 
 
@@ -90,6 +91,10 @@ def lib():
         L.emst_workspace_bytes.argtypes = [i64, i32]
         L.emst_workspace_bytes.restype = sz
         L.emst_build.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]
+        L.emst_core_distances.argtypes = [vp, vp, i64, i32, i32, vp, vp, sz, vp]
+        L.emst_core_distances.restype = i32
+        L.emst_build_mreach.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.emst_build_mreach.restype = i32
         L.emst_build.restype = i32
         for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal"):
             getattr(L, f).argtypes = [vp, i32]
@@ -254,6 +259,50 @@ class Context:
         self._check(rc)
         return edges, weights, d2
 
+
+    @staticmethod
+    def _check_points(points):
+        import torch
+        if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
+            raise TypeError("points must be a CUDA (HIP) torch tensor")
+        if points.dtype != torch.float32 or points.dim() != 2:
+            raise TypeError("points must be float32 [n, dim]")
+        return points.contiguous()
+
+    def core_distances(self, points, k_pts: int, stream=None):
+        """Squared core distances [n] (float32, input order) of the mutual
+        reachability metric: the k_pts-th smallest D from each point, the
+        point itself counted."""
+        import torch
+        points = self._check_points(points)
+        n, dim = points.shape
+        core2 = torch.empty(n, dtype=torch.float32, device=points.device)
+        ws, wsb = self._ws_ptr(n, dim if dim in (2, 3) else 3)
+        self._check(lib().emst_core_distances(self._h, ctypes.c_void_p(points.data_ptr()), int(n), int(dim),
+                                              int(k_pts), ctypes.c_void_p(core2.data_ptr()), ws, wsb,
+                                              _stream_handle(stream)))
+        return core2
+
+    def build_mreach(self, points, k_pts: int, want_d2: bool = True, stream=None):
+        """MST under the mutual reachability M = max(core2(u), core2(v), D).
+        Returns (edges [n-1, 2], weights sqrtf(M) [n-1], M [n-1] or None,
+        core2 [n]) sorted by (M, min index, max index)."""
+        import torch
+        points = self._check_points(points)
+        n, dim = points.shape
+        m = max(n - 1, 0)
+        dev = points.device
+        edges = torch.empty((m, 2), dtype=torch.int32, device=dev)
+        weights = torch.empty(m, dtype=torch.float32, device=dev)
+        d2 = torch.empty(m, dtype=torch.float32, device=dev) if want_d2 else None
+        core2 = torch.empty(n, dtype=torch.float32, device=dev)
+        ws, wsb = self._ws_ptr(n, dim if dim in (2, 3) else 3)
+        self._check(lib().emst_build_mreach(
+            self._h, ctypes.c_void_p(points.data_ptr()), int(n), int(dim), int(k_pts),
+            ctypes.c_void_p(edges.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
+            ctypes.c_void_p(d2.data_ptr() if d2 is not None else 0), ctypes.c_void_p(core2.data_ptr()),
+            ws, wsb, _stream_handle(stream)))
+        return edges, weights, d2, core2
 
     def build_batched(self, clouds, want_d2: bool = True, stream=None):
         """EMSTs of a list of clouds ([n_c, dim_c] float32 tensors on this

@@ -491,10 +491,12 @@ __global__ __launch_bounds__(256) void k_record_labels(const uint32_t* __restric
 // position takes the smaller D to its neighbours outside its component; in
 // the first round every point is its own component and writes its bound
 // directly, later the positions of a run of equal labels within a wave
-// combine first and one lane per run updates the component.
+// combine first and one lane per run updates the component.  Under mutual
+// reachability (core_s set) the pair's value is its M.
 template <int DIM, bool FIRST>
 __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, const uint32_t* __restrict__ labels,
-                                                const uint32_t* __restrict__ cloud_of, int64_t n, uint32_t* ub,
+                                                const uint32_t* __restrict__ cloud_of,
+                                                const float* __restrict__ core_s, int64_t n, uint32_t* ub,
                                                 Ctrl* ctrl) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) {
@@ -524,8 +526,11 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, 
         }
         // D of the pairs (k-1, k) and (k, k+1) when they join two components
         // of one cloud (D(k-1, k) evaluated as the previous position does)
-        if (llab != lab && lcl == cl) v = min(v, fbits(sqdist<DIM>(o, p)));
-        if (rlab != lab && rcl == cl) v = min(v, fbits(sqdist<DIM>(p, q)));
+        // mutual reachability: M = max(core2 of both ends, D)
+        const float ck = core_s ? core_s[k] : 0.f;
+        const float cll = core_s ? core_s[kl] : 0.f, crr = core_s ? core_s[kr] : 0.f;
+        if (llab != lab && lcl == cl) v = min(v, fbits(fmaxf(fmaxf(cll, ck), sqdist<DIM>(o, p))));
+        if (rlab != lab && rcl == cl) v = min(v, fbits(fmaxf(fmaxf(ck, crr), sqdist<DIM>(p, q))));
     }
     if (FIRST) {
         if (valid) ub[k] = v;
@@ -923,7 +928,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint4* __restric
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, total;
+    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, core_s, core_o, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -973,6 +978,8 @@ static Layout make_layout(int64_t n, int dim) {
     L.cand_d = take(4 * N);
     L.cand_j = take(4 * N);
     L.eud = take(16 * N);
+    L.core_s = take(4 * N);
+    L.core_o = take(4 * N);
     L.total = o;
     return L;
 }
@@ -1166,6 +1173,7 @@ struct Bufs {
     uint64_t* compkey;
     uint32_t *compmax, *succ, *par, *cand_d, *cand_j;
     uint4* eud;
+    float *core_s, *core_o;
 };
 
 template <int DIM>
@@ -1200,6 +1208,8 @@ Bufs<DIM> carve(char* ws, const Layout& L) {
     b.cand_d = reinterpret_cast<uint32_t*>(ws + L.cand_d);
     b.cand_j = reinterpret_cast<uint32_t*>(ws + L.cand_j);
     b.eud = reinterpret_cast<uint4*>(ws + L.eud);
+    b.core_s = reinterpret_cast<float*>(ws + L.core_s);
+    b.core_o = reinterpret_cast<float*>(ws + L.core_o);
     return b;
 }
 
@@ -1211,6 +1221,8 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     ta.ctrl = b.ctrl; ta.first = true; ta.leaf_parent = b.leaf_parent; ta.up = b.up;
     ta.cloud_of = nullptr; ta.cloud_root = nullptr; ta.lab2 = b.lab2;
     ta.wave_lca = reinterpret_cast<const uint32_t*>(b.exch);  // the build's exchange words are free by now
+    ta.core_s = nullptr;
+    ta.core_o = nullptr;
     return ta;
 }
 
@@ -1236,8 +1248,10 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
         if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
         S.components[round] = ncomp;
         HIP_TRY(propagate_labels(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.lab2, n, st));
-        if (round == 0) k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, n, b.ub, b.ctrl);
-        else k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, n, b.ub, b.ctrl);
+        if (round == 0)
+            k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
+        else
+            k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
         if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
         ta.first = round == 0;
         HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
@@ -1379,8 +1393,12 @@ void finish_stats(emst_ctx* ctx, emst_stats& S) {
 }
 
 template <int DIM>
+// k_pts = 0: the EMST.  k_pts >= 1: the MST under mutual reachability with
+// core distances of k_pts (k_pts = 1 gives zero cores, hence the EMST);
+// core_out (nullable) receives the squared core distances in input order.
+// core_only stops after the core distances.
 int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float* weights, float* d2, char* ws,
-               hipStream_t st) {
+               hipStream_t st, int k_pts = 0, float* core_out = nullptr, bool core_only = false) {
     const Layout L = make_layout(n, DIM);
     Bufs<DIM> b = carve<DIM>(ws, L);
     emst_stats S;
@@ -1428,10 +1446,30 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     k_wave_lca<<<grid_for((n + 63) / 64), 256, 0, st>>>(b.rlo, b.rhi, b.leaf_parent, b.node_parent, n,
                                                         reinterpret_cast<uint32_t*>(b.exch));
     HIP_TRY(hipGetLastError());
+    TraverseArgs<DIM> ta = traverse_args<DIM>(b, n, root);
+    // ---- core distances (mutual reachability)
+    if (k_pts >= 2) {
+        HIP_TRY(launch_core<DIM>(ta, S.tree_height, k_pts, b.core_s, b.core_o, core_out, st));
+        ta.core_s = b.core_s;
+        ta.core_o = b.core_o;
+    } else if (k_pts == 1 && core_out) {
+        k_fill_u32<<<grid_for(n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(core_out), n, 0u);
+        HIP_TRY(hipGetLastError());
+    }
     if (prof) HIP_TRY(hipEventRecord(E[1], st));
+    if (core_only) {
+        if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+        if (ctx->h_ctrl->error) return fail(ctx, EMST_EINTERNAL, "core distance search failed");
+        if (prof) {
+            HIP_TRY(hipEventRecord(E[2], st));
+            HIP_TRY(hipEventRecord(E[3], st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        finish_stats(ctx, S);
+        return EMST_OK;
+    }
 
     // ---- Boruvka rounds
-    TraverseArgs<DIM> ta = traverse_args<DIM>(b, n, root);
     if (int rc = run_rounds<DIM>(ctx, b, ta, n, 1, S.tree_height, ctx->traversal, nullptr, S, st)) return rc;
     if (ctx->h_ctrl->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
@@ -1598,6 +1636,69 @@ extern "C" int emst_build(emst_ctx* ctx, const float* d_points, int64_t n, int d
     return build_impl<2>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st);
 }
 
+
+static int check_single(emst_ctx* ctx, const float* d_points, int64_t n, int dim, void* d_workspace,
+                        size_t ws_bytes) {
+    if (!d_points || !d_workspace) return fail(ctx, EMST_EINVAL, "null pointer");
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(ctx, EMST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < emst_workspace_bytes(n, dim)) return fail(ctx, EMST_ENOMEM, "workspace too small");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+    return EMST_OK;
+}
+
+extern "C" int emst_core_distances(emst_ctx* ctx, const float* d_points, int64_t n, int dim, int32_t k_pts,
+                                   float* d_core2, void* d_workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > 0x7FFFFFFFll) return fail(ctx, EMST_EINVAL, "n out of range");
+    if (dim != 2 && dim != 3) return fail(ctx, EMST_EINVAL, "dim must be 2 or 3");
+    if (k_pts < 1 || k_pts > 64 || k_pts > n) return fail(ctx, EMST_EINVAL, "k_pts must be in [1, min(n, 64)]");
+    if (!d_core2) return fail(ctx, EMST_EINVAL, "null pointer");
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->stats.n = n;
+    ctx->stats.dim = dim;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (n == 1 || k_pts == 1) {  // the point itself: 0
+        if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+        k_fill_u32<<<grid_for(n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(d_core2), n, 0u);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));
+        return EMST_OK;
+    }
+    if (int rc = check_single(ctx, d_points, n, dim, d_workspace, ws_bytes)) return rc;
+    if (dim == 3)
+        return build_impl<3>(ctx, d_points, n, nullptr, nullptr, nullptr, (char*)d_workspace, st, k_pts, d_core2, true);
+    return build_impl<2>(ctx, d_points, n, nullptr, nullptr, nullptr, (char*)d_workspace, st, k_pts, d_core2, true);
+}
+
+extern "C" int emst_build_mreach(emst_ctx* ctx, const float* d_points, int64_t n, int dim, int32_t k_pts,
+                                 int32_t* d_edges, float* d_weights, float* d_d2, float* d_core2, void* d_workspace,
+                                 size_t ws_bytes, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > 0x7FFFFFFFll) return fail(ctx, EMST_EINVAL, "n out of range");
+    if (dim != 2 && dim != 3) return fail(ctx, EMST_EINVAL, "dim must be 2 or 3");
+    if (k_pts < 1 || k_pts > 64 || (n > 0 && k_pts > n)) return fail(ctx, EMST_EINVAL, "k_pts must be in [1, min(n, 64)]");
+    if (n < 2) {
+        memset(&ctx->stats, 0, sizeof(ctx->stats));
+        ctx->stats.n = n;
+        ctx->stats.dim = dim;
+        if (n == 1 && d_core2) {
+            if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+            hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+            k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(d_core2), 1, 0u);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        return EMST_OK;
+    }
+    if (!d_edges || !d_weights) return fail(ctx, EMST_EINVAL, "null pointer");
+    if (int rc = check_single(ctx, d_points, n, dim, d_workspace, ws_bytes)) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (dim == 3)
+        return build_impl<3>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st, k_pts, d_core2);
+    return build_impl<2>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st, k_pts, d_core2);
+}
 
 extern "C" size_t emst_workspace_bytes_batched(int64_t total_points, int32_t n_clouds) {
     if (total_points < 0 || total_points > 0x7FFFFFFFll || n_clouds < 1) return 0;

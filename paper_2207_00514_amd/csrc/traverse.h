@@ -55,6 +55,10 @@ struct TraverseArgs {
     // per wave of 64 Morton-consecutive queries: the lowest common ancestor
     // of their leaves (one cloud only)
     const uint32_t* wave_lca;
+    // mutual reachability: squared core distances by sorted position and by
+    // original index (null for the Euclidean tree)
+    const float* core_s;
+    const float* core_o;
 };
 
 // Where a top-down search of query i starts.
@@ -643,7 +647,12 @@ __device__ __forceinline__ bool ball_in_cell(const float* p, float rr, const Up&
 
 __device__ __forceinline__ float widen(float radius) { return sqrtf(radius) * 1.000001f + 1e-22f; }
 
-template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16, bool WSTART = false>
+// With MREACH the leaf metric is the mutual reachability M = max(core2(p),
+// core2(q), D) (Section 3, "Non-Euclidean metrics"): candidates are
+// admitted and ordered by (M, j), the radius follows the best M, and boxes
+// are still pruned by their Euclidean distance, a lower bound of M.  A
+// query whose own core distance exceeds the radius has no candidate.
+template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16, bool WSTART = false, bool MREACH = false>
 __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
     __shared__ uint2 lds[kLdsDepth][256];
     const int t = threadIdx.x;
@@ -657,6 +666,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
         for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
         c = a.labels[i];
         float radius = bitsf(a.ub[c]);
+        const float core_p = MREACH ? a.core_s[i] : 0.f;
         uint2 spill[STACK];
         int sp = 0, base = 0;  // entries [0, base) spilled, [base, sp) in the LDS ring
         uint32_t node, mask, anc = 0;
@@ -669,7 +679,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             u = a.up[anc];
         } else {
             node = start_node<DIM>(a, i);
-            mask = node == kNone ? 0u : 3u;
+            mask = (node == kNone || (MREACH && core_p > radius)) ? 0u : 3u;
             if (WSTART && mask) {
                 // wave-uniform climb; lanes past the end take no part
                 const float rr = widen(radius);
@@ -709,10 +719,18 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             // leaf candidates: (D, j) order, radius follows the best.  D >= 0,
             // so (D bits, j) as one 64-bit integer has the same order.
             {
-                const uint64_t k0 = ((uint64_t)fbits(d0) << 32) | (c0.ref & ~kLeafFlag);
-                const uint64_t k1 = ((uint64_t)fbits(d1) << 32) | (c1.ref & ~kLeafFlag);
-                const bool b0 = in0 & l0 & (d0 <= radius);
-                const bool b1 = in1 & l1 & (d1 <= radius);
+                float m0 = d0, m1 = d1;
+                if (MREACH) {  // a leaf box is its point, so d0 / d1 are the exact D
+                    const uint32_t j0 = c0.ref & ~kLeafFlag, j1 = c1.ref & ~kLeafFlag;
+                    const float q0 = (in0 & l0 & (d0 <= radius)) ? a.core_o[j0] : 0.f;
+                    const float q1 = (in1 & l1 & (d1 <= radius)) ? a.core_o[j1] : 0.f;
+                    m0 = fmaxf(fmaxf(core_p, q0), d0);
+                    m1 = fmaxf(fmaxf(core_p, q1), d1);
+                }
+                const uint64_t k0 = ((uint64_t)fbits(m0) << 32) | (c0.ref & ~kLeafFlag);
+                const uint64_t k1 = ((uint64_t)fbits(m1) << 32) | (c1.ref & ~kLeafFlag);
+                const bool b0 = in0 & l0 & (m0 <= radius);
+                const bool b1 = in1 & l1 & (m1 <= radius);
                 uint64_t bk = ((uint64_t)fbits(best_d) << 32) | best_j;
                 bk = (b0 & (k0 < bk)) ? k0 : bk;
                 bk = (b1 & (k1 < bk)) ? k1 : bk;
@@ -777,11 +795,163 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Core distances (Section 4, "Mutual reachability distance"): for every
+// sorted position i the k-th smallest D(i, j) over all j, the point itself
+// (D = 0) included.  The k-th smallest D to the sorted positions within k-1
+// of i (at least k points) bounds it from above; the search then keeps the
+// K smallest D of every leaf it reaches in registers (K >= k, only the
+// first k matter), prunes boxes farther than the running k-th value, and
+// starts every wave below the root as variant 10 does.
+
+template <int K>
+__device__ __forceinline__ void knn_insert(float (&best)[K], float d) {
+    if (!(d < best[K - 1])) return;
+#pragma unroll
+    for (int q = K - 1; q > 0; --q) best[q] = (d < best[q - 1]) ? best[q - 1] : ((d < best[q]) ? d : best[q]);
+    best[0] = (d < best[0]) ? d : best[0];
+}
+
+template <int K>
+__device__ __forceinline__ float knn_kth(const float (&best)[K], int k) {
+    float r = best[0];
+#pragma unroll
+    for (int q = 1; q < K; ++q) r = (q == k - 1) ? best[q] : r;
+    return r;
+}
+
+template <int DIM, int STACK, int K>
+__global__ __launch_bounds__(256) void k_core_dist(TraverseArgs<DIM> a, int k, float* __restrict__ core_s,
+                                                   float* __restrict__ core_o, float* __restrict__ core_out) {
+    constexpr int kDepth = 8;
+    __shared__ uint2 lds[kDepth][256];
+    const int t = threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + t;
+    if (i >= a.n) return;
+    float p[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) p[c] = a.spts[i * DIM + c];
+    float best[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) best[q] = INFINITY;
+    {
+        const int64_t w0 = i - (k - 1) > 0 ? i - (k - 1) : 0;
+        const int64_t w1 = i + (k - 1) < a.n - 1 ? i + (k - 1) : a.n - 1;
+        for (int64_t q = w0; q <= w1; ++q) {
+            float o[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) o[c] = a.spts[q * DIM + c];
+            knn_insert<K>(best, sqdist<DIM>(p, o));
+        }
+    }
+    float radius = knn_kth<K>(best, k);
+#pragma unroll
+    for (int q = 0; q < K; ++q) best[q] = INFINITY;
+    uint32_t node = a.root;
+    {  // wave-uniform climb from the wave's leaf LCA (lanes past the end take no part)
+        const float rr = widen(radius);
+        uint32_t s = a.wave_lca[i >> 6];
+        for (int h = 0; h < 160 && s != node; ++h) {
+            const Up cu = a.up[s];
+            if (__all(ball_in_cell<DIM>(p, rr, cu))) break;
+            const uint32_t link = fbits(cu.a.w);
+            s = link == kNone ? node : link >> 1;
+        }
+        node = s;
+    }
+    uint2 spill[STACK];
+    int sp = 0, base = 0;
+    for (int64_t guard = 0;; ++guard) {
+        if (guard > 2 * a.n + 256) {
+            atomicOr(&a.ctrl->error, kErrStack);
+            break;
+        }
+        const Rec<DIM> r = a.recs[node];
+        Child<DIM> c0, c1;
+        unpack<DIM>(r, c0, c1);
+        const float d0 = boxdist<DIM>(p, c0.lo, c0.hi);
+        const float d1 = boxdist<DIM>(p, c1.lo, c1.hi);
+        const bool l0 = (c0.ref & kLeafFlag) != 0u, l1 = (c1.ref & kLeafFlag) != 0u;
+        if (l0 && d0 <= radius) knn_insert<K>(best, d0);
+        if (l1 && d1 <= radius) knn_insert<K>(best, d1);
+        radius = fminf(radius, knn_kth<K>(best, k));
+        const bool go0 = !l0 && d0 <= radius;
+        const bool go1 = !l1 && d1 <= radius;
+        if (go0 && go1) {
+            const bool near1 = d1 < d0;
+            const uint2 far = make_uint2(near1 ? c0.ref : c1.ref, fbits(near1 ? d0 : d1));
+            node = near1 ? c1.ref : c0.ref;
+            if (sp - base == kDepth) {
+                if (base >= STACK) {
+                    atomicOr(&a.ctrl->error, kErrStack);
+                    break;
+                }
+                spill[base] = lds[base % kDepth][t];
+                ++base;
+            }
+            lds[sp % kDepth][t] = far;
+            ++sp;
+            continue;
+        }
+        if (go0 || go1) {
+            node = go0 ? c0.ref : c1.ref;
+            continue;
+        }
+        bool found = false;
+        while (sp > 0) {
+            --sp;
+            uint2 e;
+            if (sp < base) {
+                base = sp;
+                e = spill[sp];
+            } else {
+                e = lds[sp % kDepth][t];
+            }
+            if (bitsf(e.y) <= radius) {
+                node = e.x;
+                found = true;
+                break;
+            }
+        }
+        if (!found) break;
+    }
+    const float core = knn_kth<K>(best, k);
+    const uint32_t oi = a.orig[i];
+    core_s[i] = core;
+    core_o[oi] = core;
+    if (core_out) core_out[oi] = core;
+}
+
+template <int DIM, int STACK>
+hipError_t launch_core_s(const TraverseArgs<DIM>& a, int k, float* core_s, float* core_o, float* core_out,
+                         hipStream_t st) {
+    const unsigned grid = (unsigned)(((a.n + 255) / 256 + kXcds - 1) / kXcds * kXcds);
+    if (k <= 4) k_core_dist<DIM, STACK, 4><<<grid, 256, 0, st>>>(a, k, core_s, core_o, core_out);
+    else if (k <= 8) k_core_dist<DIM, STACK, 8><<<grid, 256, 0, st>>>(a, k, core_s, core_o, core_out);
+    else if (k <= 16) k_core_dist<DIM, STACK, 16><<<grid, 256, 0, st>>>(a, k, core_s, core_o, core_out);
+    else if (k <= 32) k_core_dist<DIM, STACK, 32><<<grid, 256, 0, st>>>(a, k, core_s, core_o, core_out);
+    else k_core_dist<DIM, STACK, 64><<<grid, 256, 0, st>>>(a, k, core_s, core_o, core_out);
+    return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t launch_core(const TraverseArgs<DIM>& a, int height, int k, float* core_s, float* core_o, float* core_out,
+                       hipStream_t st) {
+    if (height <= 32) return launch_core_s<DIM, 32>(a, k, core_s, core_o, core_out, st);
+    if (height <= 64) return launch_core_s<DIM, 64>(a, k, core_s, core_o, core_out, st);
+    return launch_core_s<DIM, 96>(a, k, core_s, core_o, core_out, st);
+}
+
+// ---------------------------------------------------------------------------
 
 template <int DIM, int STACK>
 hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count, hipStream_t st) {
     // a multiple of the XCD count, for the XCD-contiguous block mapping
     const unsigned grid = (unsigned)(((a.n + 255) / 256 + kXcds - 1) / kXcds * kXcds);
+    if (a.core_s) {  // mutual reachability: the loop and start of variant 10
+        if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, true><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false, 8, true, true><<<grid, 256, 0, st>>>(a);
+        return hipGetLastError();
+    }
     if (variant == 1) {
         if (count) k_traverse_wave<DIM, STACK, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_wave<DIM, STACK, false><<<grid, 256, 0, st>>>(a);
