@@ -75,6 +75,12 @@ def main() -> int:
     ap.add_argument("--cpu-threads", type=int, default=None)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--sweep", type=str, default=None,
+                    help="comma-separated sizes: EMST throughput of the workload's recipe at every size "
+                         "(size scaling; no CPU baseline)")
+    ap.add_argument("--mreach", type=str, default=None,
+                    help="comma-separated k_pts: time core distances and the mutual-reachability MST "
+                         "(HDBSCAN*) on the workload instead of the EMST")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -88,6 +94,10 @@ def main() -> int:
     import paper_2207_00514_amd as emst
     from paper_2207_00514_amd import workloads as W
 
+    if args.mreach:
+        return bench_mreach(args)
+    if args.sweep:
+        return bench_sweep(args)
     if args.workload == "batched512":
         return bench_batched(args)
     if args.workload == "serving":
@@ -220,6 +230,107 @@ def main() -> int:
 
     print(json.dumps(line), flush=True)
     return 0 if line.get("parity", "bit-exact") == "bit-exact" else 1
+
+
+def bench_sweep(args) -> int:
+    """EMST time and Mpoints/s of one workload recipe over a range of sizes
+    (the saturation size and the linear regime of one GPU)."""
+    import torch
+    import paper_2207_00514_amd as emst
+    from paper_2207_00514_amd import workloads as W
+
+    if args.workload in ("batched512", "serving"):
+        print("bench.py: --sweep runs on a single-cloud workload", file=sys.stderr)
+        return 2
+    ctx = emst.Context(0)
+    ctx.set_profiling(True)
+    rows = []
+    for n in [int(float(x)) for x in args.sweep.split(",")]:
+        pts = torch.from_numpy(W.make(args.workload, n)).cuda()
+        out = None
+        for _ in range(args.warmup):
+            out = ctx.build(pts, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = ctx.build(pts, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        st = ctx.stats()
+        rows.append({"n": n, "ms": round(1e3 * dt, 3), "mpoints_per_s": round(n / dt / 1e6, 3),
+                     "rounds": st["rounds"], "tree_ms": round(st["tree_ms"], 3),
+                     "rounds_ms": round(st["rounds_ms"], 3), "finalize_ms": round(st["finalize_ms"], 3)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        del pts, out
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "EMST Mpoints/sec at 1 GPU over sizes", "value": max(r["mpoints_per_s"] for r in rows),
+        "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "sweep": [r["n"] for r in rows]}, "sizes": rows,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_mreach(args) -> int:
+    """Mutual-reachability MST (Section 4): per k_pts, the time of the core
+    distances alone (T_core) and of the whole MST including them (T_emst),
+    both from device-resident points, and parity with the oracle (core
+    distances by a kd-tree k-nearest search, tree by kd-Boruvka) unless
+    --no-cpu-baseline."""
+    import numpy as np
+    import torch
+    import paper_2207_00514_amd as emst
+    from paper_2207_00514_amd import workloads as W
+
+    if args.workload in ("batched512", "serving"):
+        print("bench.py: --mreach runs on a single-cloud workload", file=sys.stderr)
+        return 2
+    pts_np = W.make(args.workload, args.n) if args.n else W.make(args.workload)
+    n, dim = pts_np.shape
+    pts = torch.from_numpy(pts_np).cuda()
+    ctx = emst.Context(0)
+    rows = []
+    ok = True
+    for k in [int(x) for x in args.mreach.split(",")]:
+        def timed(fn):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / args.steps
+        t_core = timed(lambda: ctx.core_distances(pts, k))
+        t_mst = timed(lambda: ctx.build_mreach(pts, k))
+        e, w, d2, core2 = ctx.build_mreach(pts, k)
+        row = {"k_pts": k, "t_core_ms": round(1e3 * t_core, 3), "t_emst_ms": round(1e3 * t_mst, 3),
+               "mpoints_per_s": round(n / t_mst / 1e6, 3)}
+        if not args.no_cpu_baseline:
+            import oracle
+            threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+            c0 = time.perf_counter()
+            ref, rcore = oracle.mreach_mst(pts_np, k, threads=threads)
+            c1 = time.perf_counter()
+            par = (np.array_equal(core2.cpu().numpy().view(np.uint32), rcore.view(np.uint32))
+                   and np.array_equal(e.cpu().numpy(), ref.edges)
+                   and np.array_equal(d2.cpu().numpy().view(np.uint32), ref.d2.view(np.uint32)))
+            row["cpu_oracle_s"] = round(c1 - c0, 2)
+            row["parity"] = "bit-exact" if par else "MISMATCH"
+            ok = ok and par
+        rows.append(row)
+    line = {
+        "metric": "mutual-reachability MST Mpoints/sec at 1 GPU (T_core, T_emst per k_pts)",
+        "value": rows[0]["mpoints_per_s"], "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": int(n), "dim": int(dim), "metric": "mutual_reachability"},
+        "k_pts": rows,
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if ok else 1
 
 
 def bench_batched(args) -> int:
