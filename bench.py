@@ -67,7 +67,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="clustered3d_2m",
-                    choices=["uniform2d_10k", "clustered3d_2m", "cosmology3d_37m", "batched512", "serving"])
+                    choices=["uniform2d_10k", "clustered3d_2m", "cosmology3d_37m", "skewed3d_2m", "batched512", "serving"])
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per measured run")
     ap.add_argument("--n", type=int, default=None, help="resize the workload (same recipe)")
     ap.add_argument("--variant", type=int, default=None, help="traversal variant (default: library's)")

@@ -198,7 +198,9 @@ typedef struct emst_stats {
     int64_t dist_evals;             /* leaf children outside the query's
                                        component: point distances computed */
     int32_t traversal_variant;      /* the traversal variant that ran */
-    int32_t reserved;
+    int32_t rank_codes;             /* 1 if the tree was built on rank-space
+                                       codes (many points shared a Morton
+                                       code), else 0 */
 } emst_stats;
 
 /* Time every phase with HIP events (adds synchronisation; off by default). */

@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
         ("total_ms", ctypes.c_double), ("child_tests", ctypes.c_int64),
         ("leaf_tests", ctypes.c_int64), ("child_tests_round", ctypes.c_int64 * 64),
         ("leaf_tests_round", ctypes.c_int64 * 64), ("dist_evals", ctypes.c_int64),
-        ("traversal_variant", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("traversal_variant", ctypes.c_int32), ("rank_codes", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -66,7 +66,7 @@ class Stats(ctypes.Structure):
             child_tests=self.child_tests, leaf_tests=self.leaf_tests,
             child_tests_round=list(self.child_tests_round[:r]),
             leaf_tests_round=list(self.leaf_tests_round[:r]), dist_evals=self.dist_evals,
-            traversal_variant=self.traversal_variant,
+            traversal_variant=self.traversal_variant, rank_codes=self.rank_codes,
         )
 
 

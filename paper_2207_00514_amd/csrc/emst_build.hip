@@ -81,6 +81,7 @@ __global__ void k_init_ctrl(Ctrl* ctrl) {
         ctrl->ncomp_next = 0; ctrl->edge_count = 0; ctrl->error = 0;
         ctrl->key_or = 0ull; ctrl->key_and = ~0ull;
         ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0; ctrl->trav_next = 0;
+        ctrl->long_ties = 0; ctrl->dup_codes = 0;
     }
 }
 
@@ -146,6 +147,60 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, i
         atomicOr((unsigned long long*)&ctrl->key_or, (unsigned long long)kor);
         atomicAnd((unsigned long long*)&ctrl->key_and, (unsigned long long)kand);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Rank-space codes.  When many points share a Morton code (a density
+// contrast beyond the code's resolution: the scene box is set by a few far
+// points and the rest crowd into a handful of cells), equal codes are split
+// by index and the tree loses its spatial order.  The codes are then built
+// on per-axis ranks instead of coordinates: every axis is sorted once, and
+// a point's quantised coordinate on that axis is its rank scaled to the
+// code width.  Ranks are monotone in the coordinates, so the Z-curve of the
+// ranks is still a spatial order, with resolution where the points are.
+
+// Sorted positions whose code equals the previous one (one atomic per block).
+__global__ __launch_bounds__(256) void k_count_dups(const uint64_t* __restrict__ codes, int64_t n, Ctrl* ctrl) {
+    __shared__ uint32_t s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool dup = i > 0 && i < n && codes[i] == codes[i - 1];
+    const uint64_t b = __ballot(dup);
+    if (lane_id() == 0 && b) atomicAdd(&s_cnt, (uint32_t)__popcll(b));
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(&ctrl->dup_codes, s_cnt);
+}
+
+// keys = order-preserving bits of coordinate `axis`, values = point index
+template <int DIM>
+__global__ __launch_bounds__(256) void k_axis_keys(const float* __restrict__ pts, int64_t n, int axis,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = ord_enc(pts[i * DIM + axis]);
+    vals[i] = (uint32_t)i;
+}
+
+// The point at rank r on `axis` gets the quantised coordinate r * 2^bits / n,
+// spread into its Morton position; acc collects the axes.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_axis_rank(const uint32_t* __restrict__ order, int64_t n, int axis, int bits,
+                                                   uint64_t* __restrict__ acc) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t q = ((uint64_t)r << bits) / (uint64_t)n;  // r < 2^31, bits <= 32
+    const uint64_t part = (DIM == 3 ? spread3(q) : spread2(q)) << (DIM - 1 - axis);
+    const uint32_t i = order[r];
+    acc[i] = axis == 0 ? part : (acc[i] | part);
+}
+
+__global__ __launch_bounds__(256) void k_codes_from(const uint64_t* __restrict__ acc, int64_t n,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = acc[i];
+    vals[i] = (uint32_t)i;
 }
 
 // Gather the coordinates into Morton order and initialise the per-point and
@@ -331,15 +386,17 @@ __device__ __forceinline__ uint32_t compact2(uint64_t x) {
 // margin far above every rounding in the quantisation, so any point inside
 // the stored box has codes with the node's prefix.  Axes at the scene edge
 // stay open, nodes that split equal codes get an empty cell.
+// With rank-space codes (`ranks`) a cell is not a box of coordinates: every
+// cell is left empty, so the climbs run to the top.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_cells(const uint64_t* __restrict__ codes,
                                                const uint32_t* __restrict__ node_parent, int64_t m,
-                                               MortonParams mp, Up* __restrict__ up) {
+                                               MortonParams mp, bool ranks, Up* __restrict__ up) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
     const uint64_t x = codes[k] ^ codes[k + 1];
-    if (x) {
+    if (x && !ranks) {
         const int t = 63 - __clzll(x);  // highest differing code bit = the node's split bit
         const uint64_t code = codes[k];
 #pragma unroll
@@ -1436,13 +1493,37 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, ns, &in1));
     const uint64_t* codes = in1 ? b.k1 : b.k0;
     const uint32_t* perm = in1 ? b.v1 : b.v0;
+    k_count_dups<<<grid_for(n), 256, 0, st>>>(codes, n, b.ctrl);
     // ---- hierarchy + boxes
     k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
                                                b.compmax, b.exch, b.eud);
     if (int rc = build_tree<DIM>(ctx, b, codes, n, st)) return rc;
+    const bool ranks = (int64_t)ctx->h_ctrl->dup_codes * 64 > n;
+    if (ranks) {
+        // many equal codes: rebuild on rank-space codes (the node records
+        // are rebuilt below, so they hold the codes meanwhile)
+        uint64_t* acc = reinterpret_cast<uint64_t*>(b.recs);
+        const int bits = DIM == 3 ? 21 : 32;
+        const int ash[4] = {0, 8, 16, 24};
+        for (int axis = 0; axis < DIM; ++axis) {
+            k_axis_keys<DIM><<<grid_for(n), 256, 0, st>>>(pts, n, axis, b.k0, b.v0);
+            HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, ash, 4, &in1));
+            k_axis_rank<DIM><<<grid_for(n), 256, 0, st>>>(in1 ? b.v1 : b.v0, n, axis, bits, acc);
+        }
+        k_codes_from<<<grid_for(n), 256, 0, st>>>(acc, n, b.k0, b.v0);
+        int csh[8], cq = 0;
+        for (int s = 0; s < DIM * bits; s += 8) csh[cq++] = s;
+        HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, csh, cq, &in1));
+        codes = in1 ? b.k1 : b.k0;
+        perm = in1 ? b.v1 : b.v0;
+        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
+                                                   b.compmax, b.exch, b.eud);
+        if (int rc = build_tree<DIM>(ctx, b, codes, n, st)) return rc;
+    }
+    S.rank_codes = ranks ? 1 : 0;
     const uint32_t root = ctx->h_ctrl->root;
     S.tree_height = (int32_t)ctx->h_ctrl->height;
-    k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, mp, b.up);
+    k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, mp, ranks, b.up);
     k_wave_lca<<<grid_for((n + 63) / 64), 256, 0, st>>>(b.rlo, b.rhi, b.leaf_parent, b.node_parent, n,
                                                         reinterpret_cast<uint32_t*>(b.exch));
     HIP_TRY(hipGetLastError());

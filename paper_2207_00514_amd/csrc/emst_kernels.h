@@ -23,7 +23,8 @@ struct Ctrl {
     unsigned long long dist_evals;
     unsigned long long trav_next;   // next query handed out by the persistent traversal
     uint32_t long_ties;      // the edge order met a run of equal keys too long to fix in place
-    uint32_t pad[5];
+    uint32_t dup_codes;      // sorted positions whose Morton code equals the previous one
+    uint32_t pad[4];
 };
 
 constexpr uint32_t kErrStack = 1u;

@@ -29,7 +29,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "rng_for", "uniform2d", "clustered3d", "cosmology3d", "batched_clouds",
+    "rng_for", "uniform2d", "clustered3d", "cosmology3d", "skewed3d", "batched_clouds",
     "request_sizes", "request_cloud", "integer_grid", "duplicates", "collinear",
     "identical", "two_clusters", "small_random", "WORKLOADS", "make",
 ]
@@ -66,6 +66,28 @@ def clustered3d(n: int = 2_000_000, seed: int = 2, n_centres: int = 200,
     pts = centres[owner] + sigma[owner, None] * rng.standard_normal((n_cl, 3))
     bg = rng.random((n_bg, 3))
     return _finish(rng, np.concatenate([pts, bg], axis=0))
+
+
+def skewed3d(n: int = 2_000_000, seed: int = 6, walks: int = 1000, outliers: float = 0.001,
+             step: float = 1e-6, extent: float = 1000.0) -> np.ndarray:
+    """Extreme density contrast (GPS-trajectory-like): (1 - outliers) of the
+    points lie on ``walks`` Gaussian random walks (step sigma ``step``) that
+    start in a cube of side 1e-3; the rest are U[0, extent)^3.  The scene box
+    is set by the outliers, so at 21 bits per axis the dense part falls into
+    a handful of Morton cells."""
+    rng = rng_for(seed)
+    n_out = int(round(n * outliers))
+    n_in = n - n_out
+    lens = rng.multinomial(n_in, np.full(walks, 1.0 / walks))
+    starts = 0.5 + 1e-3 * rng.random((walks, 3))
+    steps = step * rng.standard_normal((n_in, 3))
+    owner = np.repeat(np.arange(walks), lens)
+    first = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    pos = np.cumsum(steps, axis=0)
+    pos -= np.repeat(pos[first] - steps[first], lens, axis=0)  # every walk restarts at 0
+    pts = starts[owner] + pos
+    out = extent * rng.random((n_out, 3))
+    return _finish(rng, np.concatenate([pts, out], axis=0))
 
 
 def _halo_counts(rng: np.random.Generator, n_halos: int, total: int,
@@ -240,6 +262,7 @@ WORKLOADS = {
     "uniform2d_10k": dict(fn=uniform2d, n=10_000, seed=1, dim=2),
     "clustered3d_2m": dict(fn=clustered3d, n=2_000_000, seed=2, dim=3),
     "cosmology3d_37m": dict(fn=cosmology3d, n=37_000_000, seed=3, dim=3),
+    "skewed3d_2m": dict(fn=skewed3d, n=2_000_000, seed=6, dim=3),
 }
 
 

@@ -382,3 +382,25 @@ def test_tree_boxes_are_exact(ctx):
         assert seen.all() and len(order) == n - 1
         np.testing.assert_array_equal(lo, mn)
         np.testing.assert_array_equal(hi, mx)
+
+
+def test_skewed_density_rank_space_codes(ctx):
+    """Extreme density contrast (most points inside a few Morton cells of
+    the outlier-set scene box): the build switches to rank-space codes and
+    the tree is the oracle's."""
+    for n in (60_000, 250_000):
+        pts = W.make("skewed3d_2m", n)
+        print(f"case skewed3d n={n}", flush=True)
+        got = run(ctx, pts)
+        assert ctx.stats()["rank_codes"] == 1
+        assert_same(got, oracle.emst(pts, threads=16), f"skewed3d n={n}")
+    pts = W.make("clustered3d_2m", 60_000)
+    run(ctx, pts)
+    assert ctx.stats()["rank_codes"] == 0
+
+
+def test_skewed3d_2m(ctx):
+    pts = W.make("skewed3d_2m")
+    got = run(ctx, pts)
+    assert ctx.stats()["rank_codes"] == 1
+    assert_same(got, oracle.kdboruvka(pts, threads=16), "skewed3d_2m")
