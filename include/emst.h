@@ -225,9 +225,12 @@ int emst_set_counting(emst_ctx *ctx, int on);
  *  10  as 7, but each wave of 64 queries starts below the root, at the
  *      lowest ancestor of its leaves whose Morton cell holds every lane's
  *      search ball (default)
+ *  11  as 10 with the component bound shared while the round runs (every
+ *      improved candidate lowers it with an atomicMin, every node visit
+ *      re-reads it)
  * Batches (emst_build_batched) run 0, 5, 7 or 8 as chosen and 7 for any
  * other value.
- * Returns EMST_EINVAL outside [0, 10]. */
+ * Returns EMST_EINVAL outside [0, 11]. */
 int emst_set_traversal(emst_ctx *ctx, int variant);
 
 int emst_get_stats(const emst_ctx *ctx, emst_stats *out);

@@ -1161,7 +1161,7 @@ extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
     return EMST_OK;
 }
 extern "C" int emst_set_traversal(emst_ctx* ctx, int variant) {
-    if (!ctx || variant < 0 || variant > 10) return EMST_EINVAL;
+    if (!ctx || variant < 0 || variant > 11) return EMST_EINVAL;
     ctx->traversal = variant;
     return EMST_OK;
 }

@@ -35,7 +35,7 @@ struct TraverseArgs {
     const float* spts;
     const uint32_t* labels;
     const uint32_t* orig;
-    const uint32_t* ub;
+    uint32_t* ub;  // written only by variant 11 (atomicMin)
     const Rec<DIM>* recs;
     uint32_t root;
     int64_t n;
@@ -652,7 +652,14 @@ __device__ __forceinline__ float widen(float radius) { return sqrtf(radius) * 1.
 // admitted and ordered by (M, j), the radius follows the best M, and boxes
 // are still pruned by their Euclidean distance, a lower bound of M.  A
 // query whose own core distance exceeds the radius has no candidate.
-template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16, bool WSTART = false, bool MREACH = false>
+//
+// With SHARED (variant 11) the component bound is shared while the round
+// runs (the dynamic form of Optimization 2): a lane that improves its best
+// candidate lowers ub[C] with an atomicMin, and every lane re-reads ub[C]
+// at every node.  ub[C] only ever holds D values of real outgoing edges of
+// C, so it never drops below C's shortest one, whose point still admits it.
+template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16, bool WSTART = false, bool MREACH = false,
+          bool SHARED = false>
 __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
     __shared__ uint2 lds[kLdsDepth][256];
     const int t = threadIdx.x;
@@ -706,6 +713,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 c0.lab = L.x;
                 c1.lab = L.y;
             }
+            if (SHARED) radius = fminf(radius, bitsf(load_relaxed(&a.ub[c])));
             const float d0 = boxdist<DIM>(p, c0.lo, c0.hi);
             const float d1 = boxdist<DIM>(p, c1.lo, c1.hi);
             const bool in0 = (mask & 1u) && c0.lab != c;
@@ -734,7 +742,9 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 uint64_t bk = ((uint64_t)fbits(best_d) << 32) | best_j;
                 bk = (b0 & (k0 < bk)) ? k0 : bk;
                 bk = (b1 & (k1 < bk)) ? k1 : bk;
-                best_d = bitsf((uint32_t)(bk >> 32));
+                const float nd = bitsf((uint32_t)(bk >> 32));
+                if (SHARED && nd < radius) atomicMin(&a.ub[c], fbits(nd));
+                best_d = nd;
                 best_j = (uint32_t)bk;
                 radius = fminf(radius, best_d);
             }
@@ -976,6 +986,9 @@ hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count
     } else if (variant == 10) {
         if (count) k_traverse_fast<DIM, STACK, true, false, 8, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_fast<DIM, STACK, false, false, 8, true><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 11) {
+        if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, false, true><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false, 8, true, false, true><<<grid, 256, 0, st>>>(a);
     } else if (variant == 3 || variant == 4) {
         // persistent: enough waves to fill every CU several times over
         const unsigned pgrid = std::min<unsigned>(grid, 2048u);

@@ -52,7 +52,7 @@ SMALL = [(n, dim, seed, kind)
          for n, seed in ((2, 1), (3, 2), (5, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4099, 8))]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 @pytest.mark.parametrize("n,dim,seed,kind", SMALL)
 def test_small_clouds(ctx, n, dim, seed, kind, variant):
     pts = W.small_random(n, dim, seed, kind)
@@ -79,7 +79,7 @@ def test_short_runs_of_equal_edge_lengths(ctx, dim, span):
     assert ties_seen > 0
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 def test_closed_forms(ctx, variant):
     cases = {
         "identical": W.identical(1000),
@@ -94,7 +94,7 @@ def test_closed_forms(ctx, variant):
         assert_same(run(ctx, pts, variant), oracle.emst(pts, threads=8), name)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 def test_denormal_and_wide_range_coordinates(ctx, variant):
     rng = np.random.default_rng(3)
     tiny = (rng.random((500, 3)) * 1e-19).astype(np.float32)   # D is denormal
@@ -153,7 +153,7 @@ def test_errors(ctx):
 def test_variants_counting_and_repeats_agree(ctx):
     pts = W.clustered3d(60_000, seed=9)
     ref = oracle.kdboruvka(pts, threads=8)
-    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10):
+    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11):
         for counting in (False, True):
             ctx.set_counting(counting)
             print(f"variant={variant} counting={counting}", flush=True)
@@ -275,14 +275,14 @@ def test_radix_sort(ctx):
 def test_uniform2d_10k(ctx):
     pts = W.uniform2d()
     ref = oracle.prim(pts)
-    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10):
+    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11):
         assert_same(run(ctx, pts, variant), ref, f"uniform2d_10k v{variant}")
 
 
 def test_clustered3d_2m(ctx):
     pts = W.clustered3d()
     ref = oracle.kdboruvka(pts, threads=16)
-    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10):
+    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11):
         print(f"clustered3d_2m variant={variant}", flush=True)
         assert_same(run(ctx, pts, variant), ref, f"clustered3d_2m v{variant}")
 
