@@ -354,6 +354,16 @@ def bench_batched(args) -> int:
     ctx.workspace(max(sizes), 3)
     ctx.build_batched_flat(flat, sizes, dims)  # sizes the batched workspace
     torch.cuda.synchronize()
+    # autotune the traversal shape on this batch (untimed; every candidate
+    # gives the same trees), then time the automatic choice
+    from paper_2207_00514_amd import autotune
+    ms = {}
+    for v in autotune.BATCHED_CANDIDATES:
+        ctx.set_traversal(v)
+        ms[v] = 1e3 * autotune._median_seconds(lambda: ctx.build_batched_flat(flat, sizes, dims), 2)
+    best = min(ms, key=ms.get)
+    ctx.set_autotune(autotune.table_json([{"mode": "batched", "dim": 3, "n_min": 0, "variant": int(best)}]))
+    ctx.set_traversal(-1)
     for _ in range(args.warmup):
         ctx.build_batched_flat(flat, sizes, dims)
     torch.cuda.synchronize()
@@ -382,6 +392,8 @@ def bench_batched(args) -> int:
                                  "ms": round(t_solo * 1e3, 3)},
         "batched_speedup": round(t_solo / t_batched, 2),
         "batched_equals_solo": bool(same),
+        "autotuned_variant": int(best),
+        "autotune_ms": {str(k): round(v, 3) for k, v in ms.items()},
     }
     if not args.no_cpu_baseline:
         import oracle

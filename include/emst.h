@@ -59,8 +59,10 @@ extern "C" {
 typedef struct emst_ctx emst_ctx;
 
 /* Create a context bound to HIP device `hip_device` (it becomes current on
- * the calling thread).  *out receives the handle. */
-int emst_create(emst_ctx **out, int hip_device);
+ * the calling thread).  *out receives the handle.  autotune_json (nullable)
+ * is a traversal-shape table as emst_set_autotune takes it; a malformed
+ * table gives EMST_EINVAL and no context. */
+int emst_create(emst_ctx **out, int hip_device, const char *autotune_json);
 
 /* Destroy a context (NULL is allowed).  Waits for nothing: the caller
  * synchronises its streams first. */
@@ -228,10 +230,29 @@ int emst_set_counting(emst_ctx *ctx, int on);
  *  11  as 10 with the component bound shared while the round runs (every
  *      improved candidate lowers it with an atomicMin, every node visit
  *      re-reads it)
+ * -1 (the default) takes the variant from the context's autotune table
+ * (emst_set_autotune) for the call's mode, dimension and size, else 10 for
+ * emst_build and 7 for emst_build_batched.
  * Batches (emst_build_batched) run 0, 5, 7 or 8 as chosen and 7 for any
  * other value.
- * Returns EMST_EINVAL outside [0, 11]. */
+ * Returns EMST_EINVAL outside [-1, 11]. */
 int emst_set_traversal(emst_ctx *ctx, int variant);
+
+/* Traversal-shape table (the autotuner's output), a JSON document
+ *
+ *   {"entries": [{"mode": "single" | "batched", "dim": 2 | 3,
+ *                 "n_min": <points>, "variant": <0..11>}, ...]}
+ *
+ * (other keys are ignored).  A call in auto mode (emst_set_traversal -1)
+ * with n points uses the entry of its mode and dimension with the largest
+ * n_min <= n.  NULL clears the table.  EMST_EINVAL on a malformed table,
+ * which then stays as it was.  Every variant gives the same result. */
+int emst_set_autotune(emst_ctx *ctx, const char *json);
+
+/* The table as JSON into buf (capacity cap bytes, NUL-terminated); *len
+ * (nullable) receives the bytes needed.  buf = NULL only queries the
+ * length; EMST_ENOMEM if cap is too small. */
+int emst_get_autotune(const emst_ctx *ctx, char *buf, size_t cap, size_t *len);
 
 int emst_get_stats(const emst_ctx *ctx, emst_stats *out);
 

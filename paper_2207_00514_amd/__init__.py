@@ -32,7 +32,7 @@ EXPORTS = [
     "emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_get_stats",
     "emst_test_tree_from_codes", "emst_test_radix_sort",
     "emst_workspace_bytes_batched", "emst_build_batched", "emst_test_tree_boxes",
-    "emst_core_distances", "emst_build_mreach",
+    "emst_core_distances", "emst_build_mreach", "emst_set_autotune", "emst_get_autotune",
 ]
 
 
@@ -82,7 +82,7 @@ def lib():
                               "or python -m paper_2207_00514_amd._build")
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
-        L.emst_create.argtypes = [ctypes.POINTER(vp), i32]
+        L.emst_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_char_p]
         L.emst_create.restype = i32
         L.emst_destroy.argtypes = [vp]
         L.emst_destroy.restype = None
@@ -99,6 +99,10 @@ def lib():
         for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal"):
             getattr(L, f).argtypes = [vp, i32]
             getattr(L, f).restype = i32
+        L.emst_set_autotune.argtypes = [vp, ctypes.c_char_p]
+        L.emst_set_autotune.restype = i32
+        L.emst_get_autotune.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+        L.emst_get_autotune.restype = i32
         L.emst_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.emst_get_stats.restype = i32
         L.emst_workspace_bytes_batched.argtypes = [i64, ctypes.c_int32]
@@ -135,12 +139,13 @@ def _stream_handle(stream):
 class Context:
     """One emst_ctx on one HIP device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, autotune_json: str | None = None):
         import torch
         self.device = int(device)
         torch.cuda.init()
         h = ctypes.c_void_p()
-        rc = lib().emst_create(ctypes.byref(h), self.device)
+        rc = lib().emst_create(ctypes.byref(h), self.device,
+                               autotune_json.encode() if autotune_json is not None else None)
         if rc != EMST_OK:
             raise EmstError(rc, "emst_create failed")
         self._h = h
@@ -169,6 +174,18 @@ class Context:
 
     def set_traversal(self, variant: int):
         self._check(lib().emst_set_traversal(self._h, int(variant)))
+
+    def set_autotune(self, table_json: str | None):
+        """Install a traversal-shape table (JSON, see include/emst.h); None
+        clears it."""
+        self._check(lib().emst_set_autotune(self._h, table_json.encode() if table_json is not None else None))
+
+    def get_autotune(self) -> str:
+        n = ctypes.c_size_t()
+        self._check(lib().emst_get_autotune(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(lib().emst_get_autotune(self._h, buf, n.value, ctypes.byref(n)))
+        return buf.value.decode()
 
     def stats(self) -> dict:
         s = Stats()

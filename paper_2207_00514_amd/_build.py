@@ -8,8 +8,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SO = os.path.join(PKG, "libemst.so")
-SOURCES = ["radix_sort.hip", "emst_build.hip"]
-HEADERS = ["emst_common.h", "emst_kernels.h", "radix_sort.h", "traverse.h"]
+SOURCES = ["radix_sort.hip", "emst_build.hip", "tune_table.cpp"]
+HEADERS = ["emst_common.h", "emst_kernels.h", "radix_sort.h", "traverse.h", "tune_table.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -19,6 +19,7 @@
 #include "emst_kernels.h"
 #include "radix_sort.h"
 #include "traverse.h"
+#include "tune_table.h"
 
 namespace emst {
 
@@ -1069,12 +1070,15 @@ static BatchLayout make_batch_layout(int64_t n, int64_t clouds) {
 
 using namespace emst;
 
+constexpr int kMaxVariant = 11;  // traversal variants 0 .. 11
+
 struct emst_ctx {
     int device = 0;
     std::string err;
     bool profiling = false;
     bool counting = false;
-    int traversal = 10;
+    int traversal = -1;            // -1: the autotune table, else the built-in choice
+    TuneTable tune;
     emst_stats stats;
     Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
     hipEvent_t ev[2 * 64 + 8];
@@ -1114,7 +1118,7 @@ static inline unsigned grid_for(int64_t n, int threads = 256) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
-extern "C" int emst_create(emst_ctx** out, int hip_device) {
+extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_json) {
     if (!out) return EMST_EINVAL;
     *out = nullptr;
     int count = 0;
@@ -1122,6 +1126,10 @@ extern "C" int emst_create(emst_ctx** out, int hip_device) {
     emst_ctx* ctx = new (std::nothrow) emst_ctx();
     if (!ctx) return EMST_ENOMEM;
     ctx->device = hip_device;
+    if (autotune_json && !ctx->tune.parse(autotune_json, kMaxVariant, nullptr)) {
+        delete ctx;
+        return EMST_EINVAL;
+    }
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl) + 256, hipHostMallocDefault) != hipSuccess) {
@@ -1161,8 +1169,26 @@ extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
     return EMST_OK;
 }
 extern "C" int emst_set_traversal(emst_ctx* ctx, int variant) {
-    if (!ctx || variant < 0 || variant > 11) return EMST_EINVAL;
+    if (!ctx || variant < -1 || variant > kMaxVariant) return EMST_EINVAL;
     ctx->traversal = variant;
+    return EMST_OK;
+}
+extern "C" int emst_set_autotune(emst_ctx* ctx, const char* json) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (!json) {
+        ctx->tune.clear();
+        return EMST_OK;
+    }
+    if (!ctx->tune.parse(json, kMaxVariant, &ctx->err)) return EMST_EINVAL;
+    return EMST_OK;
+}
+extern "C" int emst_get_autotune(const emst_ctx* ctx, char* buf, size_t cap, size_t* len) {
+    if (!ctx) return EMST_EINVAL;
+    const std::string s = ctx->tune.dump();
+    if (len) *len = s.size() + 1;
+    if (!buf || cap < s.size() + 1) return buf ? EMST_ENOMEM : EMST_OK;
+    memcpy(buf, s.c_str(), s.size() + 1);
     return EMST_OK;
 }
 extern "C" int emst_get_stats(const emst_ctx* ctx, emst_stats* out) {
@@ -1551,7 +1577,8 @@ int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float
     }
 
     // ---- Boruvka rounds
-    if (int rc = run_rounds<DIM>(ctx, b, ta, n, 1, S.tree_height, ctx->traversal, nullptr, S, st)) return rc;
+    const int variant = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(0, DIM, n, 10);
+    if (int rc = run_rounds<DIM>(ctx, b, ta, n, 1, S.tree_height, variant, nullptr, S, st)) return rc;
     if (ctx->h_ctrl->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
 
@@ -1674,7 +1701,7 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     ta.cloud_root = d_croot;
     // variants 1-4 start every lane at one root and 6, 9, 10 need the Morton
     // cells of one cloud: a batch runs them as 7
-    const int t = ctx->traversal;
+    const int t = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(1, 3, n, 7);
     const int variant = (t == 0 || t == 5 || t == 8) ? t : 7;
     if (int rc = run_rounds<3>(ctx, b, ta, n, nonempty, S.tree_height, variant, cloud_sorted, S, st)) return rc;
     if ((int64_t)ctx->h_ctrl->edge_count != eoff) return fail(ctx, EMST_EINTERNAL, "wrong edge count");

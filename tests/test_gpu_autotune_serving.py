@@ -1,0 +1,127 @@
+"""The traversal autotuner and the continuous-batching server, on the GPU.
+
+Autotuning only chooses among traversal variants that compute the same
+tree, so every tuned call must still equal the oracle; the table must
+round-trip through the C ABI and be applied by mode, dimension and size.
+The server must return for every request exactly the tree of that request
+solved alone, whatever it was batched with."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_00514_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(pts):
+    return torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in t]
+
+
+def same_tree(a, b):
+    return (np.array_equal(a[0], b[0]) and np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
+            and np.array_equal(a[2].view(np.uint32), b[2].view(np.uint32)))
+
+
+def test_autotune_table_round_trip_and_results():
+    import paper_2207_00514_amd as emst
+    from paper_2207_00514_amd import autotune
+    ctx = emst.Context(0)
+    text = autotune.autotune(ctx, single_sizes=(3000, 30000), dims=(3,), repeats=1)
+    table = json.loads(text)["entries"]
+    assert [e["n_min"] for e in table] == [0, int((3000 * 30000) ** 0.5)]
+    assert all(e["variant"] in autotune.SINGLE_CANDIDATES for e in table)
+    back = json.loads(ctx.get_autotune())["entries"]
+    assert [(e["mode"], e["dim"], e["n_min"], e["variant"]) for e in back] == \
+        [(e["mode"], e["dim"], e["n_min"], e["variant"]) for e in table]
+    for n in (3000, 30000):
+        pts = W.clustered3d(n)
+        got = host(ctx.build(dev(pts)))
+        want = table[0]["variant"] if n < table[1]["n_min"] else table[1]["variant"]
+        assert ctx.stats()["traversal_variant"] == want
+        ref = oracle.emst(pts, threads=8)
+        assert np.array_equal(got[0], ref.edges) and np.array_equal(got[2].view(np.uint32), ref.d2.view(np.uint32))
+    # the saved table configures a new context
+    ctx2 = emst.Context(0, autotune_json=text)
+    assert json.loads(ctx2.get_autotune())["entries"] == back
+
+
+def test_autotune_lookup_by_mode_dim_and_size():
+    import paper_2207_00514_amd as emst
+    table = {"entries": [
+        {"mode": "single", "dim": 3, "n_min": 0, "variant": 7},
+        {"mode": "single", "dim": 3, "n_min": 5000, "variant": 5},
+        {"mode": "single", "dim": 2, "n_min": 0, "variant": 8},
+        {"mode": "batched", "dim": 3, "n_min": 0, "variant": 0}]}
+    ctx = emst.Context(0, autotune_json=json.dumps(table))
+    for pts, want in ((W.clustered3d(1000), 7), (W.clustered3d(6000), 5), (W.uniform2d(3000), 8)):
+        host(ctx.build(dev(pts)))
+        assert ctx.stats()["traversal_variant"] == want
+    clouds = W.batched_clouds(n_clouds=5, seed=41, lo=200, hi=3000)
+    res = ctx.build_batched([dev(c) for c in clouds])
+    torch.cuda.synchronize()
+    assert ctx.stats()["traversal_variant"] == 0
+    for c, r in zip(clouds, res):
+        ref = oracle.prim(c)
+        assert np.array_equal(r[0].cpu().numpy(), ref.edges)
+    # an explicit variant overrides the table
+    ctx.set_traversal(10)
+    host(ctx.build(dev(W.clustered3d(6000))))
+    assert ctx.stats()["traversal_variant"] == 10
+
+
+def test_autotune_bad_tables():
+    import paper_2207_00514_amd as emst
+    ctx = emst.Context(0)
+    good = '{"entries": [{"mode": "single", "dim": 3, "n_min": 0, "variant": 7}]}'
+    ctx.set_autotune(good)
+    for bad in ("{", '{"entries": [{"mode": "x", "dim": 3, "n_min": 0, "variant": 7}]}',
+                '{"entries": [{"mode": "single", "dim": 4, "n_min": 0, "variant": 7}]}',
+                '{"entries": [{"mode": "single", "dim": 3, "n_min": 0, "variant": 99}]}',
+                '{"entries": []} trailing'):
+        with pytest.raises(emst.EmstError) as ei:
+            ctx.set_autotune(bad)
+        assert ei.value.name == "EMST_EINVAL"
+        assert json.loads(ctx.get_autotune())["entries"][0]["variant"] == 7
+    with pytest.raises(emst.EmstError):
+        emst.Context(0, autotune_json="not json")
+    ctx.set_autotune(None)
+    assert json.loads(ctx.get_autotune()) == {"entries": []}
+
+
+def test_serving_results_equal_alone_and_in_the_mix():
+    import paper_2207_00514_amd as emst
+    from paper_2207_00514_amd import serve
+    sizes = np.clip(W.request_sizes(48, seed=51), 500, 40_000).astype(int)
+    reqs = [serve.Request(rid=i, points=W.request_cloud(int(n), seed=1000 + i)) for i, n in enumerate(sizes)]
+    rng = np.random.default_rng(52)
+    arrivals = np.cumsum(rng.exponential(0.002, len(reqs))).tolist()
+    server = serve.Server(workers=2, budget_bytes=1 << 30, max_batch=16)
+    serve.replay(server, reqs, arrivals)
+    assert all(r.error is None for r in reqs)
+    assert len({r.batch for r in reqs}) < len(reqs), "no request was batched with another"
+    alone = emst.Context(0)
+    for r in reqs:
+        solo = host(alone.build(dev(r.points)))
+        assert same_tree((r.edges, r.weights, r.d2), solo), f"request {r.rid}"
+    for r in reqs[:4]:
+        ref = oracle.emst(r.points, threads=8)
+        assert np.array_equal(r.edges, ref.edges)
+
+
+def test_serving_rejects_a_request_over_its_share():
+    from paper_2207_00514_amd import serve
+    server = serve.Server(workers=2, budget_bytes=64 << 20, max_batch=8)
+    big = serve.Request(rid=0, points=W.request_cloud(400_000, seed=7))
+    small = serve.Request(rid=1, points=W.request_cloud(5_000, seed=8))
+    serve.replay(server, [big, small], [0.0, 0.001])
+    assert big.error is not None and "share" in big.error
+    assert small.error is None and small.edges.shape == (4_999, 2)
