@@ -1320,51 +1320,67 @@ int read_ctrl(emst_ctx* ctx, Ctrl* ctrl, hipStream_t st) {
 // Morton neighbours in different clouds bound nothing, every query searches
 // its own cloud's subtree, and a component without an outgoing edge (its
 // cloud is finished) becomes a root.
+// One Boruvka round, enqueued on st (no host wait).
+template <int DIM>
+int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int round, int height,
+                  int variant, const uint32_t* cloud_of, bool prof, hipStream_t st) {
+    hipEvent_t* E = ctx->ev;
+    HIP_TRY(propagate_labels(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.lab2, n, st));
+    if (round == 0)
+        k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
+    else
+        k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
+    if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
+    ta.first = round == 0;
+    HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
+    if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
+    if (round > 0)
+        k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n);
+    k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.succ, b.ctrl, n,
+                                              cloud_of != nullptr);
+    k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(
+        b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud, b.ctrl, n);
+    HIP_TRY(hipGetLastError());
+    k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024);
+    k_relabel<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 4096, b.ctrl);
+    HIP_TRY(hipGetLastError());
+    return EMST_OK;
+}
+
+// The host side of a finished round: consistency checks, counters, and the
+// new component count.
+int finish_round(emst_ctx* ctx, const Ctrl* h, int round, int64_t target, int64_t& ncomp, emst_stats& S) {
+    if (h->error & kErrStack) return fail(ctx, EMST_EINTERNAL, "traversal stack overflow");
+    if (h->error & kErrJump) return fail(ctx, EMST_EINTERNAL, "component merge did not converge");
+    if (h->error) return fail(ctx, EMST_EINTERNAL, "a component found no outgoing edge");
+    if (ctx->counting) {
+        const int64_t it = (int64_t)h->internal_tests, lt = (int64_t)h->leaf_tests;
+        S.child_tests_round[round] = it - S.child_tests;
+        S.leaf_tests_round[round] = lt - S.leaf_tests;
+        S.child_tests = it;
+        S.leaf_tests = lt;
+        S.dist_evals = (int64_t)h->dist_evals;
+    }
+    const int64_t next = h->ncomp_next;
+    if (next >= ncomp || next < target) return fail(ctx, EMST_EINTERNAL, "round made no progress");
+    ncomp = next;
+    return EMST_OK;
+}
+
+// Boruvka rounds until the component count reaches `target` (the number of
+// non-empty clouds of a batch).
 template <int DIM>
 int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int64_t target, int height,
                int variant, const uint32_t* cloud_of, emst_stats& S, hipStream_t st) {
     const bool prof = ctx->profiling && ctx->ev_ok;
-    hipEvent_t* E = ctx->ev;
     int64_t ncomp = n;
     int round = 0;
     while (ncomp > target) {
         if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
         S.components[round] = ncomp;
-        HIP_TRY(propagate_labels(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.lab2, n, st));
-        if (round == 0)
-            k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
-        else
-            k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
-        if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
-        ta.first = round == 0;
-        HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
-        if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
-        if (round > 0)
-            k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n);
-        k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.succ, b.ctrl, n,
-                                                  cloud_of != nullptr);
-        k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(
-            b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud, b.ctrl, n);
-        HIP_TRY(hipGetLastError());
-        k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024);
-        k_relabel<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 4096, b.ctrl);
-        HIP_TRY(hipGetLastError());
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, round, height, variant, cloud_of, prof, st)) return rc;
         if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-        const Ctrl* h = ctx->h_ctrl;
-        if (h->error & kErrStack) return fail(ctx, EMST_EINTERNAL, "traversal stack overflow");
-        if (h->error & kErrJump) return fail(ctx, EMST_EINTERNAL, "component merge did not converge");
-        if (h->error) return fail(ctx, EMST_EINTERNAL, "a component found no outgoing edge");
-        if (ctx->counting) {
-            const int64_t it = (int64_t)h->internal_tests, lt = (int64_t)h->leaf_tests;
-            S.child_tests_round[round] = it - S.child_tests;
-            S.leaf_tests_round[round] = lt - S.leaf_tests;
-            S.child_tests = it;
-            S.leaf_tests = lt;
-            S.dist_evals = (int64_t)h->dist_evals;
-        }
-        const int64_t next = h->ncomp_next;
-        if (next >= ncomp || next < target) return fail(ctx, EMST_EINTERNAL, "round made no progress");
-        ncomp = next;
+        if (int rc = finish_round(ctx, ctx->h_ctrl, round, target, ncomp, S)) return rc;
         ++round;
     }
     S.rounds = round;
@@ -1427,21 +1443,28 @@ int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_clou
     return EMST_OK;
 }
 
-// Hierarchy (bottom-up, exchange only), then the boxes: leaves, then one
-// launch per height.  Reads the control block back for the root and height.
+// Hierarchy (bottom-up, exchange only) and the leaf boxes.
 template <int DIM>
-int build_tree(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hipStream_t st) {
+int build_hierarchy(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hipStream_t st) {
     k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, b.orig, n, b.recs, b.leaf_parent, b.node_parent, b.exch, b.rlo,
                                               b.rhi, b.height, b.ctrl);
     k_fit_leaves<DIM><<<grid_for(n), 256, 0, st>>>(b.spts, b.leaf_parent, n, b.recs);
     HIP_TRY(hipGetLastError());
-    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-    const uint32_t root = ctx->h_ctrl->root, H = ctx->h_ctrl->height;
-    if (root == kNone || root >= (uint32_t)(n - 1) || ctx->h_ctrl->error || H > 128)
+    return EMST_OK;
+}
+
+// The control block after build_hierarchy names a usable root and height.
+static int check_hierarchy(emst_ctx* ctx, const Ctrl* h, int64_t n) {
+    if (h->root == kNone || h->root >= (uint32_t)(n - 1) || h->error || h->height > 128)
         return fail(ctx, EMST_EINTERNAL, "tree construction failed");
-    // node ids grouped by height (the exchange words, the free key buffer and
-    // the index buffers are dead by now), then one launch per height below
-    // the root (the root, height H, has no parent record)
+    return EMST_OK;
+}
+
+// The internal boxes, one launch per height below the root H: node ids are
+// grouped by height first (the exchange words, the key buffer not holding
+// the codes and the index buffers are dead by now).
+template <int DIM>
+int fit_levels(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, uint32_t H, hipStream_t st) {
     const int64_t m = n - 1;
     uint64_t* hkeys = b.exch;
     uint64_t* kfree = (codes == b.k0) ? b.k1 : b.k0;
@@ -1460,6 +1483,16 @@ int build_tree(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hi
     return EMST_OK;
 }
 
+// Hierarchy and boxes in one go (reads the control block back for the root
+// and height).
+template <int DIM>
+int build_tree(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hipStream_t st) {
+    if (int rc = build_hierarchy<DIM>(ctx, b, codes, n, st)) return rc;
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+    if (int rc = check_hierarchy(ctx, ctx->h_ctrl, n)) return rc;
+    return fit_levels<DIM>(ctx, b, codes, n, ctx->h_ctrl->height, st);
+}
+
 void finish_stats(emst_ctx* ctx, emst_stats& S) {
     if (ctx->profiling && ctx->ev_ok) {
         hipEvent_t* E = ctx->ev;
@@ -1475,124 +1508,249 @@ void finish_stats(emst_ctx* ctx, emst_stats& S) {
     ctx->stats = S;
 }
 
-template <int DIM>
+// One cloud's build as a resumable sequence of phases.  Each phase
+// enqueues its work and a copy of the control block into the job's pinned
+// host mirror; after the stream has drained, advance() reads the mirror and
+// picks the next phase.  emst_build runs one job to the end; the solver
+// (emst_solver_*) runs many, one phase each per step, with one wait per
+// step for all of them.
+//
 // k_pts = 0: the EMST.  k_pts >= 1: the MST under mutual reachability with
 // core distances of k_pts (k_pts = 1 gives zero cores, hence the EMST);
-// core_out (nullable) receives the squared core distances in input order.
-// core_only stops after the core distances.
-int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float* weights, float* d2, char* ws,
-               hipStream_t st, int k_pts = 0, float* core_out = nullptr, bool core_only = false) {
-    const Layout L = make_layout(n, DIM);
-    Bufs<DIM> b = carve<DIM>(ws, L);
-    emst_stats S;
-    memset(&S, 0, sizeof(S));
-    S.n = n;
-    S.dim = DIM;
-    const bool prof = ctx->profiling && ctx->ev_ok;
-    hipEvent_t* E = ctx->ev;  // E[0..3] phases, E[8 + 2r], E[9 + 2r] traversal of round r
+// core_out (nullable) receives the squared core distances in input order;
+// core_only stops after them.
+enum JobPhase { kPhBox, kPhTree, kPhRank, kPhFit, kPhRound, kPhFinal, kPhDone };
 
-    if (prof) HIP_TRY(hipEventRecord(E[0], st));
-    // ---- validation + scene box
-    k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
-    k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, b.ctrl);
-    HIP_TRY(hipGetLastError());
-    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-    if (ctx->h_ctrl->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
-    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    for (int k = 0; k < DIM; ++k) {
-        lo[k] = ord_dec(ctx->h_ctrl->bb_min[k]);
-        hi[k] = ord_dec(ctx->h_ctrl->bb_max[k]);
+struct Job {
+    int dim = 3;
+    int64_t n = 0;
+    const float* pts = nullptr;
+    char* ws = nullptr;
+    int32_t* edges = nullptr;
+    float* weights = nullptr;
+    float* d2 = nullptr;
+    int k_pts = 0;
+    float* core_out = nullptr;
+    bool core_only = false;
+    Ctrl* h = nullptr;     // pinned host mirror of this job's control block
+    bool prof = false;     // record the context's phase and traversal events
+    int phase = kPhBox;
+    int round = 0;
+    int64_t ncomp = 0;
+    bool ranks = false;
+    int full = 0;
+    int variant = 10;
+    int codes_in1 = 0;     // which key buffer holds the sorted codes
+    MortonParams mp;
+    emst_stats S;
+};
+
+static Job make_job(emst_ctx* ctx, const float* pts, int64_t n, int dim, char* ws, int32_t* edges, float* weights,
+                    float* d2, int k_pts, float* core_out, bool core_only, Ctrl* h, bool prof) {
+    Job j;
+    j.dim = dim;
+    j.n = n;
+    j.pts = pts;
+    j.ws = ws;
+    j.edges = edges;
+    j.weights = weights;
+    j.d2 = d2;
+    j.k_pts = k_pts;
+    j.core_out = core_out;
+    j.core_only = core_only;
+    j.h = h;
+    j.prof = prof;
+    j.ncomp = n;
+    j.variant = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(0, dim, n, 10);
+    memset(&j.S, 0, sizeof(j.S));
+    j.S.n = n;
+    j.S.dim = dim;
+    return j;
+}
+
+template <int DIM>
+static TraverseArgs<DIM> job_args(const Job& j, const Bufs<DIM>& b) {
+    TraverseArgs<DIM> ta = traverse_args<DIM>(b, j.n, j.h->root);
+    if (j.k_pts >= 2) {
+        ta.core_s = b.core_s;
+        ta.core_o = b.core_o;
     }
-    if (!extent_ok(lo, hi, DIM)) return fail(ctx, EMST_ERANGE, "squared extent of the cloud overflows float32");
-    // ---- Morton codes + sort
-    const MortonParams mp = morton_params(lo, hi, DIM, DIM == 3 ? 21 : 32);
-    k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts, n, mp, b.k0, b.v0, b.ctrl);
-    HIP_TRY(hipGetLastError());
-    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-    int shifts[8], ns = 0;
-    {
-        const uint64_t vary = ctx->h_ctrl->key_or ^ ctx->h_ctrl->key_and;
-        for (int s = 0; s < 64; s += 8)
-            if ((vary >> s) & 0xFFull) shifts[ns++] = s;
+    return ta;
+}
+
+// Enqueue the current phase (ending with the control block copy).
+template <int DIM>
+int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
+    const int64_t n = j.n;
+    const Layout L = make_layout(n, DIM);
+    Bufs<DIM> b = carve<DIM>(j.ws, L);
+    hipEvent_t* E = ctx->ev;  // E[0..3] phases, E[8 + 2r], E[9 + 2r] traversal of round r
+    switch (j.phase) {
+    case kPhBox:  // validation + scene box
+        if (j.prof) HIP_TRY(hipEventRecord(E[0], st));
+        k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
+        k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(j.pts, n, b.ctrl);
+        break;
+    case kPhTree: {  // Morton codes, sort, hierarchy
+        k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(j.pts, n, j.mp, b.k0, b.v0, b.ctrl);
+        const int shifts[8] = {0, 8, 16, 24, 32, 40, 48, 56};
+        HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, 8, &j.codes_in1));
+        const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
+        k_count_dups<<<grid_for(n), 256, 0, st>>>(codes, n, b.ctrl);
+        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig, b.pos,
+                                                   b.labels, b.ub, b.compkey, b.compmax, b.exch, b.eud);
+        if (int rc = build_hierarchy<DIM>(ctx, b, codes, n, st)) return rc;
+        break;
     }
-    int in1 = 0;
-    HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, ns, &in1));
-    const uint64_t* codes = in1 ? b.k1 : b.k0;
-    const uint32_t* perm = in1 ? b.v1 : b.v0;
-    k_count_dups<<<grid_for(n), 256, 0, st>>>(codes, n, b.ctrl);
-    // ---- hierarchy + boxes
-    k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
-                                               b.compmax, b.exch, b.eud);
-    if (int rc = build_tree<DIM>(ctx, b, codes, n, st)) return rc;
-    const bool ranks = (int64_t)ctx->h_ctrl->dup_codes * 64 > n;
-    if (ranks) {
+    case kPhRank: {
         // many equal codes: rebuild on rank-space codes (the node records
-        // are rebuilt below, so they hold the codes meanwhile)
+        // are rebuilt afterwards, so they hold the codes meanwhile)
         uint64_t* acc = reinterpret_cast<uint64_t*>(b.recs);
         const int bits = DIM == 3 ? 21 : 32;
         const int ash[4] = {0, 8, 16, 24};
+        int in1 = 0;
         for (int axis = 0; axis < DIM; ++axis) {
-            k_axis_keys<DIM><<<grid_for(n), 256, 0, st>>>(pts, n, axis, b.k0, b.v0);
+            k_axis_keys<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, n, axis, b.k0, b.v0);
             HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, ash, 4, &in1));
             k_axis_rank<DIM><<<grid_for(n), 256, 0, st>>>(in1 ? b.v1 : b.v0, n, axis, bits, acc);
         }
         k_codes_from<<<grid_for(n), 256, 0, st>>>(acc, n, b.k0, b.v0);
         int csh[8], cq = 0;
         for (int s = 0; s < DIM * bits; s += 8) csh[cq++] = s;
-        HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, csh, cq, &in1));
-        codes = in1 ? b.k1 : b.k0;
-        perm = in1 ? b.v1 : b.v0;
-        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(pts, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
-                                                   b.compmax, b.exch, b.eud);
-        if (int rc = build_tree<DIM>(ctx, b, codes, n, st)) return rc;
+        HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, csh, cq, &j.codes_in1));
+        const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
+        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig, b.pos,
+                                                   b.labels, b.ub, b.compkey, b.compmax, b.exch, b.eud);
+        if (int rc = build_hierarchy<DIM>(ctx, b, codes, n, st)) return rc;
+        break;
     }
-    S.rank_codes = ranks ? 1 : 0;
-    const uint32_t root = ctx->h_ctrl->root;
-    S.tree_height = (int32_t)ctx->h_ctrl->height;
-    k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, mp, ranks, b.up);
-    k_wave_lca<<<grid_for((n + 63) / 64), 256, 0, st>>>(b.rlo, b.rhi, b.leaf_parent, b.node_parent, n,
-                                                        reinterpret_cast<uint32_t*>(b.exch));
-    HIP_TRY(hipGetLastError());
-    TraverseArgs<DIM> ta = traverse_args<DIM>(b, n, root);
-    // ---- core distances (mutual reachability)
-    if (k_pts >= 2) {
-        HIP_TRY(launch_core<DIM>(ta, S.tree_height, k_pts, b.core_s, b.core_o, core_out, st));
-        ta.core_s = b.core_s;
-        ta.core_o = b.core_o;
-    } else if (k_pts == 1 && core_out) {
-        k_fill_u32<<<grid_for(n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(core_out), n, 0u);
+    case kPhFit: {  // boxes, Morton cells, wave starts, core distances; then round 0
+        const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
+        if (int rc = fit_levels<DIM>(ctx, b, codes, n, j.h->height, st)) return rc;
+        k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, j.mp, j.ranks, b.up);
+        k_wave_lca<<<grid_for((n + 63) / 64), 256, 0, st>>>(b.rlo, b.rhi, b.leaf_parent, b.node_parent, n,
+                                                            reinterpret_cast<uint32_t*>(b.exch));
         HIP_TRY(hipGetLastError());
-    }
-    if (prof) HIP_TRY(hipEventRecord(E[1], st));
-    if (core_only) {
-        if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-        if (ctx->h_ctrl->error) return fail(ctx, EMST_EINTERNAL, "core distance search failed");
-        if (prof) {
-            HIP_TRY(hipEventRecord(E[2], st));
-            HIP_TRY(hipEventRecord(E[3], st));
+        TraverseArgs<DIM> ta = job_args<DIM>(j, b);
+        if (j.k_pts >= 2) {
+            HIP_TRY(launch_core<DIM>(ta, (int)j.h->height, j.k_pts, b.core_s, b.core_o, j.core_out, st));
+        } else if (j.k_pts == 1 && j.core_out) {
+            k_fill_u32<<<grid_for(n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(j.core_out), n, 0u);
+            HIP_TRY(hipGetLastError());
         }
-        HIP_TRY(hipStreamSynchronize(st));
-        finish_stats(ctx, S);
+        if (j.prof) HIP_TRY(hipEventRecord(E[1], st));
+        if (j.core_only) {
+            if (j.prof) {
+                HIP_TRY(hipEventRecord(E[2], st));
+                HIP_TRY(hipEventRecord(E[3], st));
+            }
+            break;
+        }
+        j.phase = kPhRound;  // round 0 goes out with this phase
+        j.S.components[0] = n;
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, 0, (int)j.h->height, j.variant, nullptr, j.prof, st))
+            return rc;
+        break;
+    }
+    case kPhRound: {
+        TraverseArgs<DIM> ta = job_args<DIM>(j, b);
+        j.S.components[j.round] = j.ncomp;
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, j.round, (int)j.h->height, j.variant, nullptr, j.prof, st))
+            return rc;
+        break;
+    }
+    case kPhFinal: {  // canonical order (the full sort only after a long run of ties)
+        const uint32_t* order = nullptr;
+        if (int rc = sort_edges<DIM>(ctx, b, n, nullptr, 0, j.full != 0, &order, st)) return rc;
+        k_edge_write<<<grid_for(n - 1), 256, 0, st>>>(b.eud, order, n - 1, j.edges, j.weights, j.d2);
+        HIP_TRY(hipGetLastError());
+        if (j.prof) HIP_TRY(hipEventRecord(E[3], st));
+        break;
+    }
+    default:
+        return fail(ctx, EMST_EINTERNAL, "job already finished");
+    }
+    HIP_TRY(hipMemcpyAsync(j.h, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    return EMST_OK;
+}
+
+// After the stream has drained: read the mirror, choose the next phase.
+template <int DIM>
+int job_advance(emst_ctx* ctx, Job& j) {
+    const Ctrl* h = j.h;
+    const int64_t n = j.n;
+    switch (j.phase) {
+    case kPhBox: {
+        if (h->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
+        float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = ord_dec(h->bb_min[k]);
+            hi[k] = ord_dec(h->bb_max[k]);
+        }
+        if (!extent_ok(lo, hi, DIM)) return fail(ctx, EMST_ERANGE, "squared extent of the cloud overflows float32");
+        j.mp = morton_params(lo, hi, DIM, DIM == 3 ? 21 : 32);
+        j.phase = kPhTree;
         return EMST_OK;
     }
-
-    // ---- Boruvka rounds
-    const int variant = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(0, DIM, n, 10);
-    if (int rc = run_rounds<DIM>(ctx, b, ta, n, 1, S.tree_height, variant, nullptr, S, st)) return rc;
-    if (ctx->h_ctrl->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
-    if (prof) HIP_TRY(hipEventRecord(E[2], st));
-
-    // ---- canonical order (the full sort only after a long run of ties)
-    const uint32_t* order = nullptr;
-    for (int full = 0; full < 2; ++full) {
-        if (int rc = sort_edges<DIM>(ctx, b, n, nullptr, 0, full != 0, &order, st)) return rc;
-        k_edge_write<<<grid_for(n - 1), 256, 0, st>>>(b.eud, order, n - 1, edges, weights, d2);
-        HIP_TRY(hipGetLastError());
-        if (prof) HIP_TRY(hipEventRecord(E[3], st));
-        if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-        if (!ctx->h_ctrl->long_ties) break;
+    case kPhTree:
+    case kPhRank:
+        if (int rc = check_hierarchy(ctx, h, n)) return rc;
+        if (j.phase == kPhTree && (int64_t)h->dup_codes * 64 > n) {
+            j.ranks = true;
+            j.phase = kPhRank;
+        } else {
+            j.S.rank_codes = j.ranks ? 1 : 0;
+            j.S.tree_height = (int32_t)h->height;
+            j.phase = kPhFit;
+        }
+        return EMST_OK;
+    case kPhFit:  // core distances only
+        if (h->error) return fail(ctx, EMST_EINTERNAL, "core distance search failed");
+        j.phase = kPhDone;
+        return EMST_OK;
+    case kPhRound: {
+        if (j.round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
+        if (int rc = finish_round(ctx, h, j.round, 1, j.ncomp, j.S)) return rc;
+        ++j.round;
+        if (j.ncomp == 1) {
+            j.S.rounds = j.round;
+            j.S.traversal_launches = j.round;
+            j.S.traversal_variant = j.variant;
+            if (h->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
+            j.phase = kPhFinal;
+        }
+        return EMST_OK;
     }
-    finish_stats(ctx, S);
+    case kPhFinal:
+        if (h->long_ties && !j.full) j.full = 1;
+        else j.phase = kPhDone;
+        return EMST_OK;
+    default:
+        return fail(ctx, EMST_EINTERNAL, "job already finished");
+    }
+}
+
+// E[2] (end of the rounds) sits between the last round and the final sort.
+template <int DIM>
+int job_run(emst_ctx* ctx, Job& j, hipStream_t st) {
+    while (j.phase != kPhDone) {
+        if (j.prof && j.phase == kPhFinal && !j.full) HIP_TRY(hipEventRecord(ctx->ev[2], st));
+        int rc = job_enqueue<DIM>(ctx, j, st);
+        const hipError_t w = hipStreamSynchronize(st);
+        if (rc) return rc;
+        if (w != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(w));
+        if (int rc2 = job_advance<DIM>(ctx, j)) return rc2;
+    }
+    return EMST_OK;
+}
+
+template <int DIM>
+int build_impl(emst_ctx* ctx, const float* pts, int64_t n, int32_t* edges, float* weights, float* d2, char* ws,
+               hipStream_t st, int k_pts = 0, float* core_out = nullptr, bool core_only = false) {
+    Job j = make_job(ctx, pts, n, DIM, ws, edges, weights, d2, k_pts, core_out, core_only, ctx->h_ctrl,
+                     ctx->profiling && ctx->ev_ok);
+    if (int rc = job_run<DIM>(ctx, j, st)) return rc;
+    finish_stats(ctx, j.S);
     return EMST_OK;
 }
 
