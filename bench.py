@@ -420,8 +420,10 @@ def bench_batched(args) -> int:
 def bench_serving(args) -> int:
     """Poisson stream of 3D requests (lognormal sizes, median 5e4, sigma 1.2,
     clipped to [5e3, 4e6]; uniform or clustered).  The continuous-batching
-    server is compared with a one-request-per-launch FIFO server on the same
-    arrival trace at 0.5 and 0.9 of the batched saturation rate."""
+    server (batch granularity, emst_build_batched) and the round-granular
+    native solver (emst_solver_*) are compared with a one-request-per-launch
+    FIFO server on the same arrival trace at 0.5 and 0.9 of the batched
+    saturation rate."""
     import numpy as np
     import torch
 
@@ -433,8 +435,11 @@ def bench_serving(args) -> int:
     clouds = [W.request_cloud(int(n), seed=5000 + i) for i, n in enumerate(sizes)]
     warm, clouds = clouds[:64], clouds[64:]
 
-    def run(workers, max_batch, rate, reqs):
-        srv = serve.Server(workers=workers, max_batch=max_batch, budget_bytes=16 << 30)
+    def run(workers, max_batch, rate, reqs, solver=False):
+        if solver:
+            srv = serve.SolverServer(budget_bytes=16 << 30, max_slots=max_batch)
+        else:
+            srv = serve.Server(workers=workers, max_batch=max_batch, budget_bytes=16 << 30)
         rq = [serve.Request(i, c) for i, c in enumerate(reqs)]
         if rate is None:
             arr = [0.0] * len(rq)
@@ -445,15 +450,19 @@ def bench_serving(args) -> int:
         return serve.summary(rq, span), rq
 
     run(2, 64, None, warm)                       # warm-up (kernels, allocator)
+    run(1, 64, None, warm[:16], solver=True)
     burst, _ = run(2, 64, None, clouds[:min(count, 150)])
     mu = burst["requests"] / burst["makespan_s"]  # saturated requests/s
     res = {}
     for frac in (0.5, 0.9):
         lam = frac * mu
         b, rq = run(2, 64, lam, clouds)
+        sv, rq2 = run(1, 64, lam, clouds, solver=True)
         f, rq1 = run(1, 1, lam, clouds)
-        same = all(np.array_equal(a.edges, c.edges) for a, c in zip(rq, rq1) if a.error is None)
-        res[f"{frac}"] = {"qps": round(lam, 1), "batched": b, "fifo_one_per_launch": f, "results_equal": same}
+        same = all(np.array_equal(a.edges, c.edges) and np.array_equal(a.edges, d.edges)
+                   for a, c, d in zip(rq, rq1, rq2) if a.error is None)
+        res[f"{frac}"] = {"qps": round(lam, 1), "batched": b, "round_granular_solver": sv,
+                          "fifo_one_per_launch": f, "results_equal": same}
     b9 = res["0.9"]["batched"]
     line = {
         "metric": METRIC, "value": round(b9["mpoints_per_s"], 3), "unit": "Mpoints/s", "n_gpus": 1,

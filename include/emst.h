@@ -173,6 +173,54 @@ int emst_build_mreach(emst_ctx *ctx, const float *d_points, int64_t n, int dim, 
                       int32_t *d_edges, float *d_weights, float *d_d2, float *d_core2,
                       void *d_workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Round-granular continuous batching (serving).  A solver keeps up to
+ * max_slots requests inside a caller-provided device budget.  Each
+ * emst_solver_step advances every running request by one phase -- its
+ * tree, then one Boruvka round per step, then its edge order -- and waits
+ * once for all of them, so a request admitted between two steps starts at
+ * the next one while the others continue.  Every result is exactly
+ * emst_build of that request alone.  All calls on one solver must come
+ * from one thread; the budget must stay allocated until
+ * emst_solver_destroy.
+ */
+typedef struct emst_solver emst_solver;
+
+/* Budget bytes one request of n points of dimension dim occupies (points,
+ * workspace and outputs); 0 for invalid arguments. */
+size_t emst_solver_slot_bytes(int64_t n, int dim);
+
+/* d_budget: device memory of budget_bytes, 256-byte aligned, owned by the
+ * caller.  1 <= max_slots <= 4096.  The solver uses the context's traversal
+ * choice and autotune table; the context must outlive it. */
+int emst_solver_create(emst_ctx *ctx, void *d_budget, size_t budget_bytes, int32_t max_slots,
+                       emst_solver **out);
+void emst_solver_destroy(emst_solver *solver);
+
+/* Admit a request: copies d_points [n][dim] into the budget (on `stream`)
+ * and returns its slot.  EMST_EBUSY if no slot or no contiguous budget is
+ * free now (retry after emst_solver_take), EMST_ENOMEM if the request does
+ * not fit even an empty budget, EMST_EINVAL for bad arguments.  A request
+ * of 0 or 1 point is finished at once.  Input problems of the points
+ * (non-finite, overflowing extent) surface as the slot's status. */
+int emst_solver_admit(emst_solver *solver, const float *d_points, int64_t n, int32_t dim, int64_t tag,
+                      void *stream, int32_t *slot);
+
+/* One phase for every running request, one wait on `stream`.  *n_finished
+ * (nullable) = requests that finished or failed in this step. */
+int emst_solver_step(emst_solver *solver, void *stream, int32_t *n_finished);
+
+/* *state: 0 free, 1 running, 2 finished, < 0 failed with that status;
+ * *tag (nullable) the admit tag. */
+int emst_solver_poll(const emst_solver *solver, int32_t slot, int32_t *state, int64_t *tag);
+
+/* Copy a finished request's n-1 edges, weights and (nullable) d2 out, as
+ * emst_build writes them, and free its slot.  A failed request returns its
+ * status (message in emst_last_error) and frees its slot; a running one
+ * gives EMST_EBUSY. */
+int emst_solver_take(emst_solver *solver, int32_t slot, int32_t *d_edges, float *d_weights, float *d_d2,
+                     void *stream);
+
 /* Per-call statistics of the last successful emst_build or
  * emst_build_batched on this context.
  * Timings are measured with HIP events on the call's stream when profiling

@@ -22,6 +22,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libemst.so")
 
 EMST_OK = 0
+EMST_EBUSY = -6
 ERRORS = {
     -1: "EMST_EINVAL", -2: "EMST_ENONFINITE", -3: "EMST_ERANGE", -4: "EMST_ENOMEM",
     -5: "EMST_EHIP", -6: "EMST_EBUSY", -7: "EMST_EINTERNAL",
@@ -33,6 +34,8 @@ EXPORTS = [
     "emst_test_tree_from_codes", "emst_test_radix_sort",
     "emst_workspace_bytes_batched", "emst_build_batched", "emst_test_tree_boxes",
     "emst_core_distances", "emst_build_mreach", "emst_set_autotune", "emst_get_autotune",
+    "emst_solver_slot_bytes", "emst_solver_create", "emst_solver_destroy", "emst_solver_admit",
+    "emst_solver_step", "emst_solver_poll", "emst_solver_take",
 ]
 
 
@@ -103,6 +106,20 @@ def lib():
         L.emst_set_autotune.restype = i32
         L.emst_get_autotune.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
         L.emst_get_autotune.restype = i32
+        L.emst_solver_slot_bytes.argtypes = [i64, i32]
+        L.emst_solver_slot_bytes.restype = sz
+        L.emst_solver_create.argtypes = [vp, vp, sz, i32, ctypes.POINTER(vp)]
+        L.emst_solver_create.restype = i32
+        L.emst_solver_destroy.argtypes = [vp]
+        L.emst_solver_destroy.restype = None
+        L.emst_solver_admit.argtypes = [vp, vp, i64, i32, i64, vp, ctypes.POINTER(i32)]
+        L.emst_solver_admit.restype = i32
+        L.emst_solver_step.argtypes = [vp, vp, ctypes.POINTER(i32)]
+        L.emst_solver_step.restype = i32
+        L.emst_solver_poll.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.emst_solver_poll.restype = i32
+        L.emst_solver_take.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.emst_solver_take.restype = i32
         L.emst_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.emst_get_stats.restype = i32
         L.emst_workspace_bytes_batched.argtypes = [i64, ctypes.c_int32]
@@ -379,3 +396,73 @@ def context(device: int = 0) -> Context:
 def build(points, **kw):
     """EMST of a device tensor with the default context of its device."""
     return context(points.device.index or 0).build(points, **kw)
+
+
+class Solver:
+    """Round-granular continuous batching on one context (emst_solver_*):
+    ``admit`` requests at any time, ``step`` advances every running one by
+    one phase, ``take`` returns a finished result exactly as ``build``."""
+
+    def __init__(self, ctx: "Context", budget_bytes: int, max_slots: int = 64):
+        import torch
+        self.ctx = ctx
+        self._mem = torch.empty(int(budget_bytes) + 256, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        base = (self._mem.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p()
+        ctx._check(lib().emst_solver_create(ctx._h, ctypes.c_void_p(base), ctypes.c_size_t(int(budget_bytes)),
+                                            int(max_slots), ctypes.byref(h)))
+        self._h = h
+        self._pending = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().emst_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def slot_bytes(n: int, dim: int) -> int:
+        return int(lib().emst_solver_slot_bytes(int(n), int(dim)))
+
+    def admit(self, points, tag: int = 0, stream=None):
+        """Slot of the admitted request, or None if no slot or budget is free
+        right now (EMST_EBUSY)."""
+        points = Context._check_points(points)
+        n, dim = points.shape
+        slot = ctypes.c_int32(-1)
+        rc = lib().emst_solver_admit(self._h, ctypes.c_void_p(points.data_ptr()), int(n), int(dim), int(tag),
+                                     _stream_handle(stream), ctypes.byref(slot))
+        if rc == EMST_EBUSY:
+            return None
+        self.ctx._check(rc)
+        self._pending[slot.value] = (int(n), points.device)
+        return slot.value
+
+    def step(self, stream=None) -> int:
+        fin = ctypes.c_int32(0)
+        self.ctx._check(lib().emst_solver_step(self._h, _stream_handle(stream), ctypes.byref(fin)))
+        return fin.value
+
+    def poll(self, slot: int):
+        state = ctypes.c_int32(0)
+        tag = ctypes.c_int64(0)
+        self.ctx._check(lib().emst_solver_poll(self._h, int(slot), ctypes.byref(state), ctypes.byref(tag)))
+        return state.value, tag.value
+
+    def take(self, slot: int, want_d2: bool = True, stream=None):
+        import torch
+        n, device = self._pending.pop(slot)
+        m = max(n - 1, 0)
+        edges = torch.empty((m, 2), dtype=torch.int32, device=device)
+        weights = torch.empty(m, dtype=torch.float32, device=device)
+        d2 = torch.empty(m, dtype=torch.float32, device=device) if want_d2 else None
+        self.ctx._check(lib().emst_solver_take(self._h, int(slot), ctypes.c_void_p(edges.data_ptr()),
+                                               ctypes.c_void_p(weights.data_ptr()),
+                                               ctypes.c_void_p(d2.data_ptr() if d2 is not None else 0),
+                                               _stream_handle(stream)))
+        return edges, weights, d2

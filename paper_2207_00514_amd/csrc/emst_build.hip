@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -1964,6 +1965,192 @@ extern "C" int emst_build_mreach(emst_ctx* ctx, const float* d_points, int64_t n
     if (dim == 3)
         return build_impl<3>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st, k_pts, d_core2);
     return build_impl<2>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st, k_pts, d_core2);
+}
+
+// ---------------------------------------------------------------------------
+// Round-granular continuous batching: a solver holds up to max_slots
+// requests in a caller-provided device budget; every step advances every
+// running request by one phase (its tree, then one Boruvka round per step,
+// then its edge order) with one wait for all of them, so a request admitted
+// between two steps starts at the next one while the others keep going.
+
+struct SolverSlot {
+    int state = 0;          // 0 free, 1 running, 2 done, < 0: failed with that status
+    int64_t tag = 0;
+    size_t off = 0, bytes = 0;
+    int64_t n = 0;
+    int dim = 3;
+    Job job;
+    std::string err;
+};
+
+struct emst_solver {
+    emst_ctx* ctx = nullptr;
+    char* base = nullptr;
+    size_t budget = 0;
+    std::vector<SolverSlot> slots;
+    Ctrl* h = nullptr;      // pinned mirrors, one per slot
+};
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" size_t emst_solver_slot_bytes(int64_t n, int dim) {
+    if (n < 0 || n > 0x7FFFFFFFll || (dim != 2 && dim != 3)) return 0;
+    const size_t m = (size_t)(n > 1 ? n - 1 : 0);
+    return a256((size_t)n * dim * 4) + emst_workspace_bytes(n > 1 ? n : 2, dim) + a256(m * 8) + 2 * a256(m * 4);
+}
+
+extern "C" int emst_solver_create(emst_ctx* ctx, void* d_budget, size_t budget_bytes, int32_t max_slots,
+                                  emst_solver** out) {
+    if (!ctx || !out || max_slots < 1 || max_slots > 4096) return EMST_EINVAL;
+    *out = nullptr;
+    if (!d_budget || ((uintptr_t)d_budget & 255u)) return fail(ctx, EMST_EINVAL, "budget must be 256-byte aligned");
+    emst_solver* sv = new (std::nothrow) emst_solver();
+    if (!sv) return EMST_ENOMEM;
+    sv->ctx = ctx;
+    sv->base = (char*)d_budget;
+    sv->budget = budget_bytes;
+    sv->slots.resize(max_slots);
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipHostMalloc((void**)&sv->h, sizeof(Ctrl) * (size_t)max_slots, hipHostMallocDefault) != hipSuccess) {
+        delete sv;
+        return fail(ctx, EMST_EHIP, "hipHostMalloc failed");
+    }
+    *out = sv;
+    return EMST_OK;
+}
+
+extern "C" void emst_solver_destroy(emst_solver* sv) {
+    if (!sv) return;
+    if (sv->h) (void)hipHostFree(sv->h);
+    delete sv;
+}
+
+extern "C" int emst_solver_admit(emst_solver* sv, const float* d_points, int64_t n, int32_t dim, int64_t tag,
+                                 void* stream, int32_t* slot) {
+    if (!sv || !slot) return EMST_EINVAL;
+    emst_ctx* ctx = sv->ctx;
+    ctx->err.clear();
+    *slot = -1;
+    if (n < 0 || n > 0x7FFFFFFFll) return fail(ctx, EMST_EINVAL, "n out of range");
+    if (dim != 2 && dim != 3) return fail(ctx, EMST_EINVAL, "dim must be 2 or 3");
+    if (n > 0 && !d_points) return fail(ctx, EMST_EINVAL, "null pointer");
+    const size_t need = emst_solver_slot_bytes(n, dim);
+    if (need > sv->budget) return fail(ctx, EMST_ENOMEM, "request larger than the whole budget");
+    int free_slot = -1;
+    for (int s = 0; s < (int)sv->slots.size() && free_slot < 0; ++s)
+        if (sv->slots[s].state == 0) free_slot = s;
+    if (free_slot < 0) return fail(ctx, EMST_EBUSY, "no free slot");
+    // first fit in the budget, between the regions held by other slots
+    std::vector<std::pair<size_t, size_t>> used;
+    for (const SolverSlot& q : sv->slots)
+        if (q.state != 0) used.push_back({q.off, q.off + q.bytes});
+    std::sort(used.begin(), used.end());
+    size_t at = 0;
+    bool found = false;
+    for (const auto& u : used) {
+        if (u.first >= at + need) {
+            found = true;
+            break;
+        }
+        at = std::max(at, u.second);
+    }
+    if (!found && at + need > sv->budget) return fail(ctx, EMST_EBUSY, "budget full");
+    SolverSlot& q = sv->slots[free_slot];
+    q.tag = tag;
+    q.off = at;
+    q.bytes = need;
+    q.n = n;
+    q.dim = dim;
+    q.err.clear();
+    char* mem = sv->base + at;
+    const size_t m = (size_t)(n > 1 ? n - 1 : 0);
+    float* pts = reinterpret_cast<float*>(mem);
+    char* ws = mem + a256((size_t)n * dim * 4);
+    char* outs = ws + emst_workspace_bytes(n > 1 ? n : 2, dim);
+    int32_t* edges = reinterpret_cast<int32_t*>(outs);
+    float* weights = reinterpret_cast<float*>(outs + a256(m * 8));
+    float* d2 = reinterpret_cast<float*>(outs + a256(m * 8) + a256(m * 4));
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (n > 0) HIP_TRY(hipMemcpyAsync(pts, d_points, (size_t)n * dim * 4, hipMemcpyDeviceToDevice, st));
+    q.job = make_job(ctx, pts, n, dim, ws, edges, weights, d2, 0, nullptr, false, sv->h + free_slot, false);
+    q.state = n < 2 ? 2 : 1;  // 0 or 1 point: nothing to do
+    *slot = free_slot;
+    return EMST_OK;
+}
+
+extern "C" int emst_solver_step(emst_solver* sv, void* stream, int32_t* n_finished) {
+    if (!sv) return EMST_EINVAL;
+    emst_ctx* ctx = sv->ctx;
+    ctx->err.clear();
+    if (n_finished) *n_finished = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    std::vector<int> go;
+    for (int s = 0; s < (int)sv->slots.size(); ++s) {
+        SolverSlot& q = sv->slots[s];
+        if (q.state != 1) continue;
+        if (q.job.prof) q.job.prof = false;
+        const int rc = q.dim == 3 ? job_enqueue<3>(ctx, q.job, st) : job_enqueue<2>(ctx, q.job, st);
+        if (rc) {
+            q.state = rc;
+            q.err = ctx->err;
+        } else {
+            go.push_back(s);
+        }
+    }
+    const hipError_t w = hipStreamSynchronize(st);
+    if (w != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(w));
+    int done = 0;
+    for (int s : go) {
+        SolverSlot& q = sv->slots[s];
+        const int rc = q.dim == 3 ? job_advance<3>(ctx, q.job) : job_advance<2>(ctx, q.job);
+        if (rc) {
+            q.state = rc;
+            q.err = ctx->err;
+            ++done;
+        } else if (q.job.phase == kPhDone) {
+            q.state = 2;
+            ++done;
+        }
+    }
+    if (n_finished) *n_finished = done;
+    return EMST_OK;
+}
+
+extern "C" int emst_solver_poll(const emst_solver* sv, int32_t slot, int32_t* state, int64_t* tag) {
+    if (!sv || slot < 0 || slot >= (int)sv->slots.size() || !state) return EMST_EINVAL;
+    *state = sv->slots[slot].state;
+    if (tag) *tag = sv->slots[slot].tag;
+    return EMST_OK;
+}
+
+extern "C" int emst_solver_take(emst_solver* sv, int32_t slot, int32_t* d_edges, float* d_weights, float* d_d2,
+                                void* stream) {
+    if (!sv || slot < 0 || slot >= (int)sv->slots.size()) return EMST_EINVAL;
+    emst_ctx* ctx = sv->ctx;
+    SolverSlot& q = sv->slots[slot];
+    if (q.state == 0) return fail(ctx, EMST_EINVAL, "slot is free");
+    if (q.state == 1) return fail(ctx, EMST_EBUSY, "request still running");
+    if (q.state < 0) {
+        const int rc = q.state;
+        ctx->err = q.err;
+        q.state = 0;
+        return rc;
+    }
+    const size_t m = (size_t)(q.n > 1 ? q.n - 1 : 0);
+    if (m) {
+        if (!d_edges || !d_weights) return fail(ctx, EMST_EINVAL, "null pointer");
+        if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+        hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+        HIP_TRY(hipMemcpyAsync(d_edges, q.job.edges, m * 8, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_weights, q.job.weights, m * 4, hipMemcpyDeviceToDevice, st));
+        if (d_d2) HIP_TRY(hipMemcpyAsync(d_d2, q.job.d2, m * 4, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    q.state = 0;
+    return EMST_OK;
 }
 
 extern "C" size_t emst_workspace_bytes_batched(int64_t total_points, int32_t n_clouds) {

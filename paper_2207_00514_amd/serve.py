@@ -12,6 +12,10 @@ the EMST of its cloud alone: a batch only groups independent clouds.
 
 Latency of a request = completion on the host - arrival.  The server
 reports p50/p99 latency and Mpoints/s over the run.
+
+``SolverServer`` is the round-granular form on the native solver: requests
+join between any two steps (one Boruvka round each) instead of between
+batches.
 """
 from __future__ import annotations
 
@@ -141,7 +145,95 @@ class Server:
                     r.done = t_done
 
 
-def replay(server: Server, requests: List[Request], arrivals: List[float],
+class SolverServer:
+    """Round-granular continuous batching on the native solver
+    (``emst_solver_*``): one driver thread admits every queued request that
+    finds a slot and budget, advances all running requests by one phase per
+    step (tree, one Boruvka round, edge order) and hands finished results
+    back.  A request arriving while others run joins at the next step."""
+
+    def __init__(self, budget_bytes: int = 8 << 30, max_slots: int = 64, device: int = 0):
+        import torch
+        from . import Context, Solver
+        self.device = device
+        self._ctx = Context(device)
+        self._solver = Solver(self._ctx, budget_bytes, max_slots)
+        self._stream = torch.cuda.Stream(device=device)
+        self.budget = budget_bytes
+        self._queue: collections.deque = collections.deque()
+        self._cv = threading.Condition()
+        self._closed = False
+        self._thread: Optional[threading.Thread] = None
+        self._steps = 0
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request) -> None:
+        n, dim = req.points.shape
+        if self._solver.slot_bytes(n, dim) > self.budget:
+            req.error = "EMST_ENOMEM: request larger than the solver budget"
+            req.done = self.now()
+            return
+        with self._cv:
+            req.arrival = self.now() if req.arrival == 0.0 else req.arrival
+            self._queue.append(req)
+            self._cv.notify()
+
+    def start(self) -> None:
+        self._thread = threading.Thread(target=self._run, daemon=True)
+        self._thread.start()
+
+    def close(self) -> None:
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        if self._thread:
+            self._thread.join()
+        self._solver.close()
+
+    def _run(self) -> None:
+        import torch
+        running = {}   # slot -> (request, device copy of its points until the next step)
+        while True:
+            with self._cv:
+                while not self._queue and not running and not self._closed:
+                    self._cv.wait()
+                if not self._queue and not running and self._closed:
+                    return
+                waiting = list(self._queue)
+            with torch.cuda.stream(self._stream):
+                for r in waiting:
+                    pts = torch.from_numpy(r.points).to(f"cuda:{self.device}")
+                    slot = self._solver.admit(pts, tag=r.rid, stream=self._stream)
+                    if slot is None:
+                        break
+                    with self._cv:
+                        self._queue.popleft()
+                    r.start = self.now()
+                    r.batch = self._steps
+                    running[slot] = (r, pts)
+                if not running:
+                    continue
+                self._solver.step(stream=self._stream)
+                self._steps += 1
+                for slot in list(running):
+                    state, _ = self._solver.poll(slot)
+                    if state == 1:
+                        running[slot] = (running[slot][0], None)
+                        continue
+                    r = running.pop(slot)[0]
+                    try:
+                        e, w, d = self._solver.take(slot, stream=self._stream)
+                        self._stream.synchronize()
+                        r.edges, r.weights, r.d2 = e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()
+                    except Exception as exc:  # a failed request fails alone
+                        r.error = str(exc)
+                    r.done = self.now()
+
+
+def replay(server, requests: List[Request], arrivals: List[float],
            on_submit: Optional[Callable[[Request], None]] = None) -> float:
     """Submit `requests` at the given arrival times (seconds from now) and
     wait for all of them; returns the makespan in seconds."""

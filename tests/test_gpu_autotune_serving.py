@@ -125,3 +125,89 @@ def test_serving_rejects_a_request_over_its_share():
     serve.replay(server, [big, small], [0.0, 0.001])
     assert big.error is not None and "share" in big.error
     assert small.error is None and small.edges.shape == (4_999, 2)
+
+
+def _solve_all(solver, ctx, limit=400):
+    done = {}
+    for _ in range(limit):
+        solver.step()
+        for s in list(solver._pending):
+            state, _ = solver.poll(s)
+            if state != 1:
+                done[s] = state
+        if all(solver.poll(s)[0] != 1 for s in solver._pending):
+            break
+    return done
+
+
+def test_solver_round_granular_admission_equals_alone():
+    import paper_2207_00514_amd as emst
+    ctx = emst.Context(0)
+    alone = emst.Context(0)
+    solver = emst.Solver(ctx, 256 << 20, max_slots=16)
+    clouds = [W.small_random(n, d, 70 + i, k) for i, (n, d, k) in enumerate(
+        [(3000, 3, "uniform"), (20000, 2, "uniform"), (1, 3, "uniform"), (0, 2, "uniform"),
+         (5000, 3, "dup"), (40000, 3, "outlier"), (2, 2, "int"), (12000, 3, "int")])]
+    first = [solver.admit(dev(c), tag=i) for i, c in enumerate(clouds[:4])]
+    assert None not in first
+    solver.step()
+    solver.step()
+    later = [solver.admit(dev(c), tag=4 + i) for i, c in enumerate(clouds[4:])]  # join mid-flight
+    assert None not in later
+    slots = first + later
+    _solve_all(solver, ctx)
+    for i, (s, c) in enumerate(zip(slots, clouds)):
+        state, tag = solver.poll(s)
+        assert state == 2 and tag == i
+        got = host(solver.take(s))
+        if len(c) < 2:
+            assert got[0].shape == (0, 2)
+            continue
+        assert same_tree(got, host(alone.build(dev(c)))), f"cloud {i}"
+    solver.close()
+
+
+def test_solver_budget_busy_and_failures():
+    import paper_2207_00514_amd as emst
+    ctx = emst.Context(0)
+    one = emst.Solver.slot_bytes(20000, 3)
+    solver = emst.Solver(ctx, 2 * one + emst.Solver.slot_bytes(500, 3) + 4096, max_slots=8)
+    a = solver.admit(dev(W.small_random(20000, 3, 1)))
+    b = solver.admit(dev(W.small_random(20000, 3, 2)))
+    assert a is not None and b is not None
+    assert solver.admit(dev(W.small_random(20000, 3, 3))) is None        # budget full: EBUSY
+    with pytest.raises(emst.EmstError) as ei:
+        solver.admit(dev(W.small_random(60000, 3, 4)))                  # larger than the budget
+    assert ei.value.name == "EMST_ENOMEM"
+    _solve_all(solver, ctx)
+    host(solver.take(a))
+    c = solver.admit(dev(W.small_random(20000, 3, 3)))                   # fits again
+    assert c is not None
+    bad = W.small_random(500, 3, 5)
+    bad[7, 2] = np.inf
+    f = solver.admit(dev(bad))
+    assert f is not None
+    _solve_all(solver, ctx)
+    assert solver.poll(f)[0] == -2
+    with pytest.raises(emst.EmstError) as ei:
+        solver.take(f)
+    assert ei.value.name == "EMST_ENONFINITE"
+    for s, seed in ((b, 2), (c, 3)):
+        pts = W.small_random(20000, 3, seed)
+        assert np.array_equal(host(solver.take(s))[0], oracle.emst(pts, threads=8).edges)
+    solver.close()
+
+
+def test_solver_server_results_equal_alone():
+    import paper_2207_00514_amd as emst
+    from paper_2207_00514_amd import serve
+    sizes = np.clip(W.request_sizes(40, seed=61), 500, 30_000).astype(int)
+    reqs = [serve.Request(rid=i, points=W.request_cloud(int(n), seed=2000 + i)) for i, n in enumerate(sizes)]
+    rng = np.random.default_rng(62)
+    arrivals = np.cumsum(rng.exponential(0.003, len(reqs))).tolist()
+    server = serve.SolverServer(budget_bytes=512 << 20, max_slots=32)
+    serve.replay(server, reqs, arrivals)
+    assert all(r.error is None for r in reqs)
+    alone = emst.Context(0)
+    for r in reqs:
+        assert same_tree((r.edges, r.weights, r.d2), host(alone.build(dev(r.points)))), f"request {r.rid}"
