@@ -83,7 +83,7 @@ __global__ void k_init_ctrl(Ctrl* ctrl) {
         ctrl->ncomp_next = 0; ctrl->edge_count = 0; ctrl->error = 0;
         ctrl->key_or = 0ull; ctrl->key_and = ~0ull;
         ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0; ctrl->trav_next = 0;
-        ctrl->long_ties = 0; ctrl->dup_codes = 0;
+        ctrl->long_ties = 0; ctrl->dup_codes = 0; ctrl->done = 0;
     }
 }
 
@@ -483,7 +483,8 @@ __device__ __forceinline__ uint32_t block_max_scan_incl(uint32_t x, uint32_t* s_
 }
 
 __global__ __launch_bounds__(256) void k_runs_reduce(const uint32_t* __restrict__ labels, int64_t n,
-                                                     uint32_t* __restrict__ part) {
+                                                     uint32_t* __restrict__ part, const Ctrl* ctrl) {
+    if (ctrl->done) return;
     __shared__ uint32_t s_w[4];
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
     uint32_t m = 0;
@@ -496,7 +497,8 @@ __global__ __launch_bounds__(256) void k_runs_reduce(const uint32_t* __restrict_
 }
 
 // part[b] <- max(part[0..b-1]) (0 for b = 0); one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_runs_scan(uint32_t* part, int nb) {
+__global__ __launch_bounds__(1024) void k_runs_scan(uint32_t* part, int nb, const Ctrl* ctrl) {
+    if (ctrl->done) return;
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_incl[1024];
     uint32_t carry = 0;
@@ -514,7 +516,8 @@ __global__ __launch_bounds__(1024) void k_runs_scan(uint32_t* part, int nb) {
 
 __global__ __launch_bounds__(256) void k_runs_down(const uint32_t* __restrict__ labels, int64_t n,
                                                    const uint32_t* __restrict__ part,
-                                                   uint32_t* __restrict__ run_start) {
+                                                   uint32_t* __restrict__ run_start, const Ctrl* ctrl) {
+    if (ctrl->done) return;
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_last;
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
@@ -537,9 +540,9 @@ __global__ __launch_bounds__(256) void k_record_labels(const uint32_t* __restric
                                                        const uint32_t* __restrict__ run_start,
                                                        const uint32_t* __restrict__ rlo,
                                                        const uint32_t* __restrict__ rhi, uint2* __restrict__ lab2,
-                                                       int64_t m) {
+                                                       int64_t m, const Ctrl* ctrl) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
+    if (k >= m || ctrl->done) return;
     const uint32_t lo = rlo[k], hi = rhi[k];
     const uint32_t a = labels[k], b = labels[k + 1];
     lab2[k] = make_uint2((run_start[k] <= lo) ? a : kInvalid, (run_start[hi] <= (uint32_t)(k + 1)) ? b : kInvalid);
@@ -557,6 +560,7 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, 
                                                 const uint32_t* __restrict__ cloud_of,
                                                 const float* __restrict__ core_s, int64_t n, uint32_t* ub,
                                                 Ctrl* ctrl) {
+    if (ctrl->done) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) {
         ctrl->ncomp_next = 0u;
@@ -608,9 +612,9 @@ __global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ ca
                                                  const uint32_t* __restrict__ labels,
                                                  const uint32_t* __restrict__ orig,
                                                  const uint64_t* __restrict__ compkey, uint32_t* compmax,
-                                                 int64_t n) {
+                                                 int64_t n, const Ctrl* ctrl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || ctrl->done) return;
     const uint32_t cd = cand_d[i];
     if (cd == kNone) return;
     const uint32_t j = cand_j[i], oi = orig[i], c = labels[i];
@@ -626,7 +630,7 @@ __global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ compmax, uint32_t* succ,
                                                     Ctrl* ctrl, int64_t n, bool allow_isolated) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n || labels[c] != (uint32_t)c) return;
+    if (c >= n || ctrl->done || labels[c] != (uint32_t)c) return;
     const uint64_t key = compkey[c];
     const uint32_t v = compmax[c];
     if (key == kKeyMax || v == kNone) {
@@ -650,6 +654,7 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ succ, uint32_t* par,
                                                       uint64_t* compkey, uint32_t* compmax, uint32_t* ub,
                                                       uint4* __restrict__ eud, Ctrl* ctrl, int64_t n) {
+    if (ctrl->done) return;
     __shared__ uint32_t s_cnt[2];
     if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -691,7 +696,8 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
 // ever replace a pointer by one of its ancestors, so any interleaving is
 // safe; the loop is capped and the relabel step finishes any remaining hops.
 __global__ __launch_bounds__(256) void k_merge_jump(const uint32_t* __restrict__ labels, uint32_t* par,
-                                                    int64_t n, int steps) {
+                                                    int64_t n, int steps, const Ctrl* ctrl) {
+    if (ctrl->done) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n || labels[c] != (uint32_t)c) return;
     uint32_t p = load_relaxed(&par[c]);
@@ -704,10 +710,16 @@ __global__ __launch_bounds__(256) void k_merge_jump(const uint32_t* __restrict__
 }
 
 // Merge, step 4: every point takes its component's root as its new label
-// (following any hops the jumping step left, up to a cap).
+// (following any hops the jumping step left, up to a cap).  It is the last
+// kernel of a round; its first thread raises `done` once the new component
+// count has reached the loop's target, so that every kernel of a round
+// already queued behind this one returns at once (this kernel itself always
+// runs: on a finished loop it rewrites the same labels).
 __global__ __launch_bounds__(256) void k_relabel(uint32_t* labels, const uint32_t* __restrict__ par, int64_t n,
-                                                 int steps, Ctrl* ctrl) {
+                                                 int steps, Ctrl* ctrl, int64_t target) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the loop ends here (or stops on an error): a round queued after this one does nothing
+    if (i == 0 && ((int64_t)ctrl->ncomp_next <= target || ctrl->error)) ctrl->done = 1u;
     if (i >= n) return;
     uint32_t r = par[labels[i]];
     int it = 0;
@@ -1084,6 +1096,7 @@ struct emst_ctx {
     Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
     hipEvent_t ev[2 * 64 + 8];
     bool ev_ok = false;
+    hipEvent_t sev[2] = {nullptr, nullptr};  // completion of the control copies of two rounds in flight
     void* h_stage = nullptr;       // pinned host staging for per-cloud tables
     size_t h_stage_bytes = 0;
 };
@@ -1133,7 +1146,12 @@ extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_
     }
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (hipSetDevice(hip_device) != hipSuccess ||
-        hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl) + 256, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&ctx->h_ctrl, 2 * sizeof(Ctrl) + 256, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->sev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->sev[1], hipEventDisableTiming) != hipSuccess) {
+        for (auto& e : ctx->sev)
+            if (e) (void)hipEventDestroy(e);
+        if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
         delete ctx;
         return EMST_EHIP;
     }
@@ -1147,6 +1165,8 @@ extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_
 extern "C" void emst_destroy(emst_ctx* ctx) {
     if (!ctx) return;
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+    for (auto& e : ctx->sev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     delete ctx;
@@ -1230,12 +1250,12 @@ MortonParams morton_params(const float* lo, const float* hi, int dim, int bits) 
 }
 
 hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_start, uint32_t* run_part, const uint32_t* rlo,
-                            const uint32_t* rhi, uint2* lab2, int64_t n, hipStream_t st) {
+                            const uint32_t* rhi, uint2* lab2, int64_t n, const Ctrl* ctrl, hipStream_t st) {
     const int nb = (int)((n + kRunTile - 1) / kRunTile);
-    k_runs_reduce<<<nb, 256, 0, st>>>(labels, n, run_part);
-    k_runs_scan<<<1, 1024, 0, st>>>(run_part, nb);
-    k_runs_down<<<nb, 256, 0, st>>>(labels, n, run_part, run_start);
-    k_record_labels<<<grid_for(n - 1), 256, 0, st>>>(labels, run_start, rlo, rhi, lab2, n - 1);
+    k_runs_reduce<<<nb, 256, 0, st>>>(labels, n, run_part, ctrl);
+    k_runs_scan<<<1, 1024, 0, st>>>(run_part, nb, ctrl);
+    k_runs_down<<<nb, 256, 0, st>>>(labels, n, run_part, run_start, ctrl);
+    k_record_labels<<<grid_for(n - 1), 256, 0, st>>>(labels, run_start, rlo, rhi, lab2, n - 1, ctrl);
     return hipGetLastError();
 }
 
@@ -1324,9 +1344,9 @@ int read_ctrl(emst_ctx* ctx, Ctrl* ctrl, hipStream_t st) {
 // One Boruvka round, enqueued on st (no host wait).
 template <int DIM>
 int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int round, int height,
-                  int variant, const uint32_t* cloud_of, bool prof, hipStream_t st) {
+                  int variant, const uint32_t* cloud_of, int64_t target, bool prof, hipStream_t st) {
     hipEvent_t* E = ctx->ev;
-    HIP_TRY(propagate_labels(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.lab2, n, st));
+    HIP_TRY(propagate_labels(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.lab2, n, b.ctrl, st));
     if (round == 0)
         k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
     else
@@ -1336,14 +1356,15 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
     if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
     if (round > 0)
-        k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n);
+        k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
+                                               b.ctrl);
     k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.succ, b.ctrl, n,
                                               cloud_of != nullptr);
     k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(
         b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud, b.ctrl, n);
     HIP_TRY(hipGetLastError());
-    k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024);
-    k_relabel<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 4096, b.ctrl);
+    k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024, b.ctrl);
+    k_relabel<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 4096, b.ctrl, target);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
 }
@@ -1379,7 +1400,8 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
     while (ncomp > target) {
         if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
         S.components[round] = ncomp;
-        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, round, height, variant, cloud_of, prof, st)) return rc;
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, round, height, variant, cloud_of, target, prof, st))
+            return rc;
         if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
         if (int rc = finish_round(ctx, ctx->h_ctrl, round, target, ncomp, S)) return rc;
         ++round;
@@ -1541,6 +1563,8 @@ struct Job {
     bool ranks = false;
     int full = 0;
     int variant = 10;
+    uint32_t root = 0;     // of the finished hierarchy
+    int height = 0;
     int codes_in1 = 0;     // which key buffer holds the sorted codes
     MortonParams mp;
     emst_stats S;
@@ -1571,7 +1595,7 @@ static Job make_job(emst_ctx* ctx, const float* pts, int64_t n, int dim, char* w
 
 template <int DIM>
 static TraverseArgs<DIM> job_args(const Job& j, const Bufs<DIM>& b) {
-    TraverseArgs<DIM> ta = traverse_args<DIM>(b, j.n, j.h->root);
+    TraverseArgs<DIM> ta = traverse_args<DIM>(b, j.n, j.root);
     if (j.k_pts >= 2) {
         ta.core_s = b.core_s;
         ta.core_o = b.core_o;
@@ -1627,14 +1651,14 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
     }
     case kPhFit: {  // boxes, Morton cells, wave starts, core distances; then round 0
         const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
-        if (int rc = fit_levels<DIM>(ctx, b, codes, n, j.h->height, st)) return rc;
+        if (int rc = fit_levels<DIM>(ctx, b, codes, n, (uint32_t)j.height, st)) return rc;
         k_cells<DIM><<<grid_for(n - 1), 256, 0, st>>>(codes, b.node_parent, n - 1, j.mp, j.ranks, b.up);
         k_wave_lca<<<grid_for((n + 63) / 64), 256, 0, st>>>(b.rlo, b.rhi, b.leaf_parent, b.node_parent, n,
                                                             reinterpret_cast<uint32_t*>(b.exch));
         HIP_TRY(hipGetLastError());
         TraverseArgs<DIM> ta = job_args<DIM>(j, b);
         if (j.k_pts >= 2) {
-            HIP_TRY(launch_core<DIM>(ta, (int)j.h->height, j.k_pts, b.core_s, b.core_o, j.core_out, st));
+            HIP_TRY(launch_core<DIM>(ta, j.height, j.k_pts, b.core_s, b.core_o, j.core_out, st));
         } else if (j.k_pts == 1 && j.core_out) {
             k_fill_u32<<<grid_for(n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(j.core_out), n, 0u);
             HIP_TRY(hipGetLastError());
@@ -1649,14 +1673,13 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
         }
         j.phase = kPhRound;  // round 0 goes out with this phase
         j.S.components[0] = n;
-        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, 0, (int)j.h->height, j.variant, nullptr, j.prof, st))
-            return rc;
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, 0, j.height, j.variant, nullptr, 1, j.prof, st)) return rc;
         break;
     }
     case kPhRound: {
         TraverseArgs<DIM> ta = job_args<DIM>(j, b);
         j.S.components[j.round] = j.ncomp;
-        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, j.round, (int)j.h->height, j.variant, nullptr, j.prof, st))
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, j.round, j.height, j.variant, nullptr, 1, j.prof, st))
             return rc;
         break;
     }
@@ -1702,6 +1725,8 @@ int job_advance(emst_ctx* ctx, Job& j) {
         } else {
             j.S.rank_codes = j.ranks ? 1 : 0;
             j.S.tree_height = (int32_t)h->height;
+            j.root = h->root;
+            j.height = (int)h->height;
             j.phase = kPhFit;
         }
         return EMST_OK;
@@ -1731,12 +1756,53 @@ int job_advance(emst_ctx* ctx, Job& j) {
     }
 }
 
+// The rounds of one job with the next round always queued before the host
+// reads the last one back, so the device never idles while the host checks
+// a round: round r's control block goes to mirror r % 2 and an event marks
+// its arrival.  When round r ends the loop, the queued round r + 1 finds
+// `done` raised and returns at once.  Round 0 is already queued (by the fit
+// phase) with its copy going to mirror 0.
+template <int DIM>
+int job_rounds(emst_ctx* ctx, Job& j, hipStream_t st) {
+    Ctrl* mirror[2] = {ctx->h_ctrl, ctx->h_ctrl + 1};
+    HIP_TRY(hipEventRecord(ctx->sev[0], st));
+    const Layout L = make_layout(j.n, DIM);
+    Bufs<DIM> b = carve<DIM>(j.ws, L);
+    TraverseArgs<DIM> ta = job_args<DIM>(j, b);
+    for (int r = 0;; ++r) {
+        const int nxt = r + 1;
+        if (nxt < 64) {
+            if (int rc = enqueue_round<DIM>(ctx, b, ta, j.n, nxt, j.height, j.variant, nullptr, 1, j.prof, st))
+                return rc;
+            HIP_TRY(hipMemcpyAsync(mirror[nxt & 1], b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipEventRecord(ctx->sev[nxt & 1], st));
+        }
+        HIP_TRY(hipEventSynchronize(ctx->sev[r & 1]));
+        j.h = mirror[r & 1];
+        j.round = r;
+        j.S.components[r] = j.ncomp;
+        const int rc = job_advance<DIM>(ctx, j);
+        j.h = mirror[0];
+        if (rc) return rc;
+        if (j.phase != kPhRound) return EMST_OK;
+    }
+}
+
 // E[2] (end of the rounds) sits between the last round and the final sort.
 template <int DIM>
 int job_run(emst_ctx* ctx, Job& j, hipStream_t st) {
     while (j.phase != kPhDone) {
         if (j.prof && j.phase == kPhFinal && !j.full) HIP_TRY(hipEventRecord(ctx->ev[2], st));
+        const bool to_rounds = j.phase == kPhFit && !j.core_only;
         int rc = job_enqueue<DIM>(ctx, j, st);
+        if (rc == EMST_OK && to_rounds) {
+            rc = job_rounds<DIM>(ctx, j, st);
+            if (rc) {
+                (void)hipStreamSynchronize(st);
+                return rc;
+            }
+            continue;
+        }
         const hipError_t w = hipStreamSynchronize(st);
         if (rc) return rc;
         if (w != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(w));
@@ -2276,7 +2342,7 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint8_t* height = reinterpret_cast<uint8_t*>(ws + L.height);
     k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, n, recs, leaf_parent, node_parent, exch, rlo, rhi, height,
                                             ctrl);
-    HIP_TRY(propagate_labels(labels, run_start, run_part, rlo, rhi, lab2, n, st));
+    HIP_TRY(propagate_labels(labels, run_start, run_part, rlo, rhi, lab2, n, ctrl, st));
     k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, lab2, node_parent, n - 1, d_left, d_right, d_label);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));

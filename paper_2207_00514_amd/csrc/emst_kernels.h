@@ -24,7 +24,8 @@ struct Ctrl {
     unsigned long long trav_next;   // next query handed out by the persistent traversal
     uint32_t long_ties;      // the edge order met a run of equal keys too long to fix in place
     uint32_t dup_codes;      // sorted positions whose Morton code equals the previous one
-    uint32_t pad[4];
+    uint32_t done;           // the round loop has reached its target: later round kernels return at once
+    uint32_t pad[3];
 };
 
 constexpr uint32_t kErrStack = 1u;

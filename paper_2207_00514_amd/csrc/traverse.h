@@ -191,6 +191,7 @@ __device__ __forceinline__ void descend(const TraverseArgs<DIM>& a, uint32_t nod
 
 template <int DIM, int STACK, bool COUNT>
 __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
+    if (a.ctrl->done) return;  // the round loop has already finished
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
     uint32_t c = kNone, best_j = kNone;
@@ -213,6 +214,7 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
 
 template <int DIM, int STACK, bool COUNT>
 __global__ __launch_bounds__(256) void k_traverse_up(TraverseArgs<DIM> a) {
+    if (a.ctrl->done) return;  // the round loop has already finished
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
     uint32_t c = kNone, best_j = kNone;
@@ -321,6 +323,7 @@ __global__ __launch_bounds__(256) void k_traverse_up(TraverseArgs<DIM> a) {
 
 template <int DIM, int STACK, bool COUNT>
 __global__ __launch_bounds__(256) void k_traverse_wave(TraverseArgs<DIM> a) {
+    if (a.ctrl->done) return;  // the round loop has already finished
     constexpr int W = 4;  // waves per block
     __shared__ uint32_t s_node[W][STACK];
     __shared__ uint64_t s_mask[W][STACK];
@@ -461,6 +464,7 @@ __device__ __forceinline__ void finish_one(const TraverseArgs<DIM>& a, int64_t i
 
 template <int DIM, int STACK, bool COUNT, bool UPWARD>
 __global__ __launch_bounds__(256) void k_traverse_pool(TraverseArgs<DIM> a) {
+    if (a.ctrl->done) return;  // the round loop has already finished
     constexpr int64_t kChunk = 512;
     const int lane = lane_id();
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -661,6 +665,7 @@ __device__ __forceinline__ float widen(float radius) { return sqrtf(radius) * 1.
 template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16, bool WSTART = false, bool MREACH = false,
           bool SHARED = false>
 __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
+    if (a.ctrl->done) return;  // the round loop has already finished
     __shared__ uint2 lds[kLdsDepth][256];
     const int t = threadIdx.x;
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + t;
