@@ -27,8 +27,23 @@ namespace emst {
 // ===========================================================================
 // tree construction
 
+// Workgroups of 256 threads covering n items (at least one).
+static inline unsigned grid_for(int64_t n, int threads = 256) {
+    int64_t g = (n + threads - 1) / threads;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Device-scope atomics on one address from many workgroups serialise at the
+// memory side (the XCDs' L2s are not coherent with each other), a few ns
+// each; kernels that reduce to a single value therefore leave one partial
+// per workgroup in `part` (at most kPartBlocks of them) and a small kernel
+// or the next kernel folds them.
+constexpr int kPartBlocks = 2048;
+
+// Scene box and non-finite check: workgroup b leaves (ord_enc of min x,y,z,
+// ord_enc of max x,y,z, non-finite flag) in part[8b .. 8b+6].
 template <int DIM>
-__global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts, int64_t n, Ctrl* ctrl) {
+__global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts, int64_t n, uint32_t* part) {
     __shared__ float s_lo[4][DIM], s_hi[4][DIM];
     __shared__ uint32_t s_bad[4];
     float lo[DIM], hi[DIM];
@@ -65,15 +80,64 @@ __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts, int
 #pragma unroll
             for (int k = 0; k < DIM; ++k) { lo[k] = fminf(lo[k], s_lo[v][k]); hi[k] = fmaxf(hi[k], s_hi[v][k]); }
         }
+        uint32_t* o = part + 8 * (int64_t)blockIdx.x;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            if (lo[k] <= hi[k]) {
-                atomicMin(&ctrl->bb_min[k], ord_enc(lo[k]));
-                atomicMax(&ctrl->bb_max[k], ord_enc(hi[k]));
-            }
+        for (int k = 0; k < 3; ++k) {
+            const bool some = k < DIM && lo[k % DIM] <= hi[k % DIM];
+            o[k] = some ? ord_enc(lo[k % DIM]) : 0xFFFFFFFFu;
+            o[3 + k] = some ? ord_enc(hi[k % DIM]) : 0u;
         }
-        if (b) atomicOr(&ctrl->nonfinite, 1u);
+        o[6] = b;
     }
+}
+
+// Folds the nb partials of k_bbox into the control block (one workgroup).
+__global__ __launch_bounds__(256) void k_bbox_final(const uint32_t* __restrict__ part, int nb, Ctrl* ctrl) {
+    __shared__ uint32_t s[4][7];
+    uint32_t v[7] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[k] = min(v[k], part[8 * b + k]);
+            v[3 + k] = max(v[3 + k], part[8 * b + 3 + k]);
+        }
+        v[6] |= part[8 * b + 6];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[k] = min(v[k], (uint32_t)__shfl_xor(v[k], off));
+            v[3 + k] = max(v[3 + k], (uint32_t)__shfl_xor(v[3 + k], off));
+        }
+        v[6] |= (uint32_t)__shfl_xor(v[6], off);
+    }
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0)
+        for (int k = 0; k < 7; ++k) s[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int u = 1; u < (int)blockDim.x / 64; ++u) {
+            for (int k = 0; k < 3; ++k) {
+                v[k] = min(v[k], s[u][k]);
+                v[3 + k] = max(v[3 + k], s[u][3 + k]);
+            }
+            v[6] |= s[u][6];
+        }
+        for (int k = 0; k < 3; ++k) {
+            ctrl->bb_min[k] = v[k];
+            ctrl->bb_max[k] = v[3 + k];
+        }
+        ctrl->nonfinite = v[6] ? 1u : 0u;
+    }
+}
+
+template <int DIM>
+hipError_t launch_bbox(const float* pts, int64_t n, uint32_t* part, Ctrl* ctrl, hipStream_t st) {
+    const int nb = (int)std::min<unsigned>(grid_for(n), 1024);
+    k_bbox<DIM><<<nb, 256, 0, st>>>(pts, n, part);
+    k_bbox_final<<<1, 256, 0, st>>>(part, nb, ctrl);
+    return hipGetLastError();
 }
 
 __global__ void k_init_ctrl(Ctrl* ctrl) {
@@ -117,10 +181,7 @@ struct MortonParams {
 // the tree; the EMST does not depend on it.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, int64_t n, MortonParams mp,
-                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                Ctrl* ctrl) {
-    __shared__ uint64_t s_or[4], s_and[4];
-    uint64_t kor = 0, kand = ~0ull;
+                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t q[DIM];
 #pragma unroll
@@ -134,20 +195,6 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, i
         else code = (spread2(q[0]) << 1) | spread2(q[1 % DIM]);
         keys[i] = code;
         vals[i] = (uint32_t)i;
-        kor |= code;
-        kand &= code;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        kor |= __shfl_xor(kor, off);
-        kand &= __shfl_xor(kand, off);
-    }
-    const int w = threadIdx.x / 64;
-    if (lane_id() == 0) { s_or[w] = kor; s_and[w] = kand; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int v = 1; v < 4; ++v) { kor |= s_or[v]; kand &= s_and[v]; }
-        atomicOr((unsigned long long*)&ctrl->key_or, (unsigned long long)kor);
-        atomicAnd((unsigned long long*)&ctrl->key_and, (unsigned long long)kand);
     }
 }
 
@@ -453,16 +500,81 @@ __global__ __launch_bounds__(256) void k_wave_lca(const uint32_t* __restrict__ r
 // Optimization 1 (Section 3): every internal node gets its leaves' common
 // component label, or kInvalid.  The paper propagates labels bottom-up with
 // first/second-arrival threads; here the same labels come from the leaf
-// ranges instead: in Morton order a node's leaves are the range [lo, hi],
-// and they share one label exactly when the run of equal labels containing
-// hi starts at or before lo.  run_start[p] is a max-scan of the positions
-// where the label changes, so the pass is three streaming kernels plus one
-// thread per record, with no inter-thread hand-off.
+// ranges instead.  In Morton order record k holds the leaf ranges [lo, k]
+// and [k+1, hi]; the first shares one label exactly when the run of equal
+// labels containing k starts at or before lo, the second when the run
+// containing k+1 ends at or after hi.  Both tests are local to k once every
+// tile of kRunTile positions knows where the run crossing its left edge
+// starts and where the run crossing its right edge ends:
+//   - per tile, the last position where a run starts and the first where
+//     one ends (left by the previous round's relabel kernel, or by
+//     k_run_partials for arbitrary labels);
+//   - k_tile_carries: an exclusive max-scan and an exclusive suffix
+//     min-scan of those over the tiles;
+//   - k_round_prep: per tile, the run starts and ends of every position by
+//     scans in LDS, then the record labels and, in the same pass, the
+//     Morton-neighbour bounds of Optimization 2.
+// No thread ever waits on another.
 
-constexpr int kRunTile = 4096;  // 256 threads x 16 positions
+constexpr int kRunPer = 8;                        // positions per thread
+constexpr int kRunTile = 256 * kRunPer;           // positions per tile (one workgroup)
+constexpr int kRunLds = kRunTile + kRunTile / 16 + 8;
 
-__device__ __forceinline__ uint32_t run_head(const uint32_t* __restrict__ labels, int64_t p) {
-    return (p == 0 || labels[p - 1] != labels[p]) ? (uint32_t)p : 0u;
+static inline int run_tiles(int64_t n) { return (int)((n + kRunTile - 1) / kRunTile); }
+
+// LDS slot of tile-local index x: one pad word per 16 keeps the
+// consecutive positions of one thread in distinct banks.
+__device__ __forceinline__ int run_lds(int x) { return x + (x >> 4); }
+
+// Reduce (max, min) over the 256 threads of the workgroup; s_w holds 8 words.
+__device__ __forceinline__ void block_max_min256(uint32_t& mx, uint32_t& mn, uint32_t* s_w) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor(mx, off));
+        mn = min(mn, (uint32_t)__shfl_xor(mn, off));
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        s_w[w] = mx;
+        s_w[4 + w] = mn;
+    }
+    __syncthreads();
+    mx = max(max(s_w[0], s_w[1]), max(s_w[2], s_w[3]));
+    mn = min(min(s_w[4], s_w[5]), min(s_w[6], s_w[7]));
+}
+
+// Exclusive max-scan in thread order over the 256 threads (0 for thread 0).
+__device__ __forceinline__ uint32_t block_excl_max256(uint32_t x, uint32_t* s_w4) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off);
+        if (lane >= off) inc = max(inc, y);
+    }
+    if (lane == 63) s_w4[w] = inc;
+    __syncthreads();
+    uint32_t ex = __shfl_up(inc, 1);
+    if (lane == 0) ex = 0u;
+    for (int k = 0; k < w; ++k) ex = max(ex, s_w4[k]);
+    return ex;
+}
+
+// Exclusive min-scan in reverse thread order (kNone for thread 255).
+__device__ __forceinline__ uint32_t block_excl_min256_rev(uint32_t x, uint32_t* s_w4) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_down(inc, off);
+        if (lane + off < 64) inc = min(inc, y);
+    }
+    if (lane == 0) s_w4[w] = inc;
+    __syncthreads();
+    uint32_t ex = __shfl_down(inc, 1);
+    if (lane == 63) ex = kNone;
+    for (int k = w + 1; k < 4; ++k) ex = min(ex, s_w4[k]);
+    return ex;
 }
 
 // Inclusive max-scan over the block (blockDim.x a multiple of 64, at most
@@ -482,126 +594,196 @@ __device__ __forceinline__ uint32_t block_max_scan_incl(uint32_t x, uint32_t* s_
     return max(x, before);
 }
 
-__global__ __launch_bounds__(256) void k_runs_reduce(const uint32_t* __restrict__ labels, int64_t n,
-                                                     uint32_t* __restrict__ part, const Ctrl* ctrl) {
-    if (ctrl->done) return;
-    __shared__ uint32_t s_w[4];
+// Tile partials of arbitrary labels: part[2t] = the last position p of tile
+// t where a run starts (p = 0 or labels[p-1] != labels[p]), 0 if none;
+// part[2t+1] = the first position where a run ends (p = n-1 or
+// labels[p] != labels[p+1]), kNone if none.
+__global__ __launch_bounds__(256) void k_run_partials(const uint32_t* __restrict__ labels, int64_t n,
+                                                      uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_w[8];
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
-    uint32_t m = 0;
-    for (int q = 0; q < kRunTile / 256; ++q) {
+    uint32_t hmax = 0u, tmin = kNone;
+    for (int q = 0; q < kRunPer; ++q) {
         const int64_t p = base + (int64_t)q * 256 + threadIdx.x;
-        if (p < n) m = max(m, run_head(labels, p));
+        if (p >= n) break;
+        const uint32_t l = labels[p];
+        if (p == 0 || labels[p - 1] != l) hmax = max(hmax, (uint32_t)p);
+        if (p == n - 1 || labels[p + 1] != l) tmin = min(tmin, (uint32_t)p);
     }
-    m = block_max_scan_incl(m, s_w);
-    if (threadIdx.x == 255) part[blockIdx.x] = m;
+    block_max_min256(hmax, tmin, s_w);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = hmax;
+        part[2 * blockIdx.x + 1] = tmin;
+    }
 }
 
-// part[b] <- max(part[0..b-1]) (0 for b = 0); one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_runs_scan(uint32_t* part, int nb, const Ctrl* ctrl) {
+// Exclusive scan over the nb tile partials in scan order j (tile j, or tile
+// nb-1-j when REV): carry[2t] = max(part[2u], u < t) (0 for the first tile);
+// REV: carry[2t+1] = min(part[2u+1], u > t) (kNone for the last tile), as a
+// max-scan of complements.
+template <bool REV>
+__device__ __forceinline__ void tiles_excl_scan(const uint32_t* __restrict__ part, uint32_t* __restrict__ carry,
+                                                int nb, uint32_t* s_w, uint32_t* s_incl) {
+    uint32_t run = 0u;
+    for (int c0 = 0; c0 < nb; c0 += 1024) {
+        const int j = c0 + (int)threadIdx.x;
+        const int t = REV ? nb - 1 - j : j;
+        uint32_t x = 0u;
+        if (j < nb) x = REV ? ~part[2 * t + 1] : part[2 * t];
+        const uint32_t incl = block_max_scan_incl(x, s_w);
+        s_incl[threadIdx.x] = incl;
+        __syncthreads();
+        const uint32_t ex = max(run, threadIdx.x > 0 ? s_incl[threadIdx.x - 1] : 0u);
+        if (j < nb) carry[2 * t + (REV ? 1 : 0)] = REV ? ~ex : ex;
+        run = max(run, s_incl[1023]);
+        __syncthreads();
+    }
+}
+
+// One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_tile_carries(const uint32_t* __restrict__ part, int nb,
+                                                       uint32_t* __restrict__ carry, const Ctrl* ctrl) {
     if (ctrl->done) return;
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_incl[1024];
-    uint32_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += 1024) {
-        const int b = b0 + (int)threadIdx.x;
-        const uint32_t incl = block_max_scan_incl(b < nb ? part[b] : 0u, s_w);
-        s_incl[threadIdx.x] = incl;
-        __syncthreads();
-        const uint32_t excl = threadIdx.x > 0 ? s_incl[threadIdx.x - 1] : 0u;
-        if (b < nb) part[b] = max(carry, excl);
-        carry = max(carry, s_incl[1023]);
-        __syncthreads();
-    }
+    tiles_excl_scan<false>(part, carry, nb, s_w, s_incl);
+    tiles_excl_scan<true>(part, carry, nb, s_w, s_incl);
 }
 
-__global__ __launch_bounds__(256) void k_runs_down(const uint32_t* __restrict__ labels, int64_t n,
-                                                   const uint32_t* __restrict__ part,
-                                                   uint32_t* __restrict__ run_start, const Ctrl* ctrl) {
+// Per tile: the record labels lab2[k] of every record k in the tile and,
+// with BOUNDS, the Morton-neighbour bound of every component (Optimization
+// 2): a Morton-adjacent pair with different labels bounds the shortest
+// outgoing edge of both components by its D.  Every position takes the
+// smaller D to its neighbours outside its component (its M under mutual
+// reachability, core_s set; pairs in different clouds of a batch bound
+// nothing).  FIRST: the first round, where every position is its own
+// component: the tests reduce to lo == k and hi == k + 1, and every
+// position writes its own bound.  Later the positions of a run of equal
+// labels within a wave combine first and one lane per run lowers the
+// component's bound.
+template <int DIM, bool FIRST, bool BOUNDS>
+__global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__ labels,
+                                                    const uint32_t* __restrict__ carry,
+                                                    const uint32_t* __restrict__ rlo,
+                                                    const uint32_t* __restrict__ rhi, uint2* __restrict__ lab2,
+                                                    const float* __restrict__ spts,
+                                                    const uint32_t* __restrict__ cloud_of,
+                                                    const float* __restrict__ core_s, int64_t n, uint32_t* ub,
+                                                    Ctrl* ctrl) {
     if (ctrl->done) return;
-    __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_last;
+    __shared__ uint32_t s_lab[kRunLds];               // labels of positions base-1 .. base+kRunTile
+    __shared__ uint32_t s_rs[FIRST ? 1 : kRunLds];    // start of the run containing each position
+    __shared__ uint32_t s_re[FIRST ? 1 : kRunLds];    // end of the run containing each position
+    __shared__ uint32_t s_w[8];
+    const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
-    uint32_t carry = part[blockIdx.x];
-    for (int q = 0; q < kRunTile / 256; ++q) {
-        const int64_t p = base + (int64_t)q * 256 + threadIdx.x;
-        const uint32_t v = (p < n) ? run_head(labels, p) : 0u;
-        const uint32_t x = max(block_max_scan_incl(v, s_w), carry);
-        if (p < n) run_start[p] = x;
-        if (threadIdx.x == 255) s_last = x;
-        __syncthreads();
-        carry = s_last;
-        __syncthreads();
+    if (BOUNDS && blockIdx.x == 0 && tid == 0) ctrl->trav_next = 0ull;
+    for (int x = tid; x < kRunTile + 2; x += 256) {
+        int64_t p = base + x - 1;
+        p = p < 0 ? 0 : (p >= n ? n - 1 : p);
+        s_lab[run_lds(x)] = labels[p];
     }
-}
-
-// Record k holds the children [lo_k, k] and [k+1, hi_k]; their labels go to
-// lab2[k], one 8-byte entry per record.
-__global__ __launch_bounds__(256) void k_record_labels(const uint32_t* __restrict__ labels,
-                                                       const uint32_t* __restrict__ run_start,
-                                                       const uint32_t* __restrict__ rlo,
-                                                       const uint32_t* __restrict__ rhi, uint2* __restrict__ lab2,
-                                                       int64_t m, const Ctrl* ctrl) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m || ctrl->done) return;
-    const uint32_t lo = rlo[k], hi = rhi[k];
-    const uint32_t a = labels[k], b = labels[k + 1];
-    lab2[k] = make_uint2((run_start[k] <= lo) ? a : kInvalid, (run_start[hi] <= (uint32_t)(k + 1)) ? b : kInvalid);
-}
-
-// Optimization 2 (Section 3): a Morton-adjacent pair with different labels
-// bounds the shortest outgoing edge of both components by its D.  Every
-// position takes the smaller D to its neighbours outside its component; in
-// the first round every point is its own component and writes its bound
-// directly, later the positions of a run of equal labels within a wave
-// combine first and one lane per run updates the component.  Under mutual
-// reachability (core_s set) the pair's value is its M.
-template <int DIM, bool FIRST>
-__global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ spts, const uint32_t* __restrict__ labels,
-                                                const uint32_t* __restrict__ cloud_of,
-                                                const float* __restrict__ core_s, int64_t n, uint32_t* ub,
-                                                Ctrl* ctrl) {
-    if (ctrl->done) return;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0) {
-        ctrl->ncomp_next = 0u;
-        ctrl->trav_next = 0ull;
-    }
-    // every position reads itself and both neighbours directly (cached
-    // re-reads), so the wave waits for memory once
-    const bool valid = k < n;
-    uint32_t v = kInfBits, lab = kNone;
-    if (valid) {
-        const int64_t kl = k > 0 ? k - 1 : k, kr = k + 1 < n ? k + 1 : k;
-        lab = labels[k];
-        const uint32_t llab = labels[kl], rlab = labels[kr];
-        uint32_t cl = 0u, lcl = 0u, rcl = 0u;
-        if (cloud_of) {
-            cl = cloud_of[k];
-            lcl = cloud_of[kl];
-            rcl = cloud_of[kr];
-        }
-        float p[DIM], o[DIM], q[DIM];
+    __syncthreads();
+    if (!FIRST) {
+        // thread tid owns the local positions [kRunPer tid, kRunPer (tid + 1))
+        const int x0 = tid * kRunPer;
+        uint32_t agg_h = 0u, agg_t = kNone;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            p[c] = spts[k * DIM + c];
-            o[c] = spts[kl * DIM + c];
-            q[c] = spts[kr * DIM + c];
+        for (int j = 0; j < kRunPer; ++j) {
+            const int x = x0 + j;
+            const int64_t p = base + x;
+            if (p < n) {
+                const uint32_t l = s_lab[run_lds(x + 1)];
+                if (p == 0 || s_lab[run_lds(x)] != l) agg_h = max(agg_h, (uint32_t)p);
+                if (p == n - 1 || s_lab[run_lds(x + 2)] != l) agg_t = min(agg_t, (uint32_t)p);
+            }
         }
-        // D of the pairs (k-1, k) and (k, k+1) when they join two components
-        // of one cloud (D(k-1, k) evaluated as the previous position does)
-        // mutual reachability: M = max(core2 of both ends, D)
-        const float ck = core_s ? core_s[k] : 0.f;
-        const float cll = core_s ? core_s[kl] : 0.f, crr = core_s ? core_s[kr] : 0.f;
-        if (llab != lab && lcl == cl) v = min(v, fbits(fmaxf(fmaxf(cll, ck), sqdist<DIM>(o, p))));
-        if (rlab != lab && rcl == cl) v = min(v, fbits(fmaxf(fmaxf(ck, crr), sqdist<DIM>(p, q))));
+        uint32_t cur = max(block_excl_max256(agg_h, s_w), carry[2 * blockIdx.x]);
+        const uint32_t cr = min(block_excl_min256_rev(agg_t, s_w + 4), carry[2 * blockIdx.x + 1]);
+#pragma unroll
+        for (int j = 0; j < kRunPer; ++j) {
+            const int x = x0 + j;
+            const int64_t p = base + x;
+            if (p < n && (p == 0 || s_lab[run_lds(x)] != s_lab[run_lds(x + 1)])) cur = (uint32_t)p;
+            s_rs[run_lds(x)] = cur;
+        }
+        cur = cr;
+#pragma unroll
+        for (int j = kRunPer - 1; j >= 0; --j) {
+            const int x = x0 + j;
+            const int64_t p = base + x;
+            if (p < n && (p == n - 1 || s_lab[run_lds(x + 2)] != s_lab[run_lds(x + 1)])) cur = (uint32_t)p;
+            s_re[run_lds(x)] = cur;
+        }
+        __syncthreads();
     }
-    if (FIRST) {
-        if (valid) ub[k] = v;
-        return;
+    // record labels; record k has the children [rlo[k], k] and [k+1, rhi[k]]
+    const uint32_t carry_r = FIRST ? kNone : carry[2 * blockIdx.x + 1];
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int x = q * 256 + tid;
+        const int64_t k = base + x;
+        if (k < n - 1) {
+            const uint32_t lo = rlo[k], hi = rhi[k];
+            bool left, right;
+            if (FIRST) {
+                left = lo == (uint32_t)k;
+                right = hi == (uint32_t)(k + 1);
+            } else {
+                left = s_rs[run_lds(x)] <= lo;
+                right = (x + 1 < kRunTile ? s_re[run_lds(x + 1)] : carry_r) >= hi;
+            }
+            lab2[k] = make_uint2(left ? s_lab[run_lds(x + 1)] : kInvalid,
+                                 right ? s_lab[run_lds(x + 2)] : kInvalid);
+        }
     }
-    bool run_end;
-    v = wave_seg_min<uint32_t>(lab, v, &run_end);
-    if (valid && run_end && v != kInfBits && v < load_relaxed(&ub[lab])) atomicMin(&ub[lab], v);
+    if (!BOUNDS) return;
+    uint32_t v[kRunPer];
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int x = q * 256 + tid;
+        const int64_t k = base + x;
+        v[q] = kInfBits;
+        if (k < n) {
+            const int64_t kl = k > 0 ? k - 1 : k, kr = k + 1 < n ? k + 1 : k;
+            const uint32_t lab = s_lab[run_lds(x + 1)];
+            const uint32_t llab = s_lab[run_lds(x)], rlab = s_lab[run_lds(x + 2)];
+            uint32_t cl = 0u, lcl = 0u, rcl = 0u;
+            if (cloud_of) {
+                cl = cloud_of[k];
+                lcl = cloud_of[kl];
+                rcl = cloud_of[kr];
+            }
+            float pp[DIM], o[DIM], r[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                pp[c] = spts[k * DIM + c];
+                o[c] = spts[kl * DIM + c];
+                r[c] = spts[kr * DIM + c];
+            }
+            // D(k-1, k) is evaluated as position k-1 evaluates D(k-1, k)
+            const float ck = core_s ? core_s[k] : 0.f;
+            const float cll = core_s ? core_s[kl] : 0.f, crr = core_s ? core_s[kr] : 0.f;
+            if (kl != k && llab != lab && lcl == cl)
+                v[q] = min(v[q], fbits(fmaxf(fmaxf(cll, ck), sqdist<DIM>(o, pp))));
+            if (kr != k && rlab != lab && rcl == cl)
+                v[q] = min(v[q], fbits(fmaxf(fmaxf(ck, crr), sqdist<DIM>(pp, r))));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int x = q * 256 + tid;
+        const int64_t k = base + x;
+        if (FIRST) {
+            if (k < n) ub[k] = v[q];
+            continue;
+        }
+        if (base + q * 256 >= n) break;  // uniform over the workgroup
+        const uint32_t lab = k < n ? s_lab[run_lds(x + 1)] : kNone;
+        bool run_end;
+        const uint32_t m = wave_seg_min<uint32_t>(lab, v[q], &run_end);
+        if (k < n && run_end && m != kInfBits && m < load_relaxed(&ub[lab])) atomicMin(&ub[lab], m);
+    }
 }
 
 // Stage B of the component minimum: among the points whose candidate matches
@@ -653,7 +835,8 @@ __global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__
 __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict__ labels,
                                                       const uint32_t* __restrict__ succ, uint32_t* par,
                                                       uint64_t* compkey, uint32_t* compmax, uint32_t* ub,
-                                                      uint4* __restrict__ eud, Ctrl* ctrl, int64_t n) {
+                                                      uint4* __restrict__ eud, uint2* __restrict__ part,
+                                                      const Ctrl* ctrl, int64_t n) {
     if (ctrl->done) return;
     __shared__ uint32_t s_cnt[2];
     if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
@@ -686,10 +869,8 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
         if (emitted) atomicAdd(&s_cnt[1], emitted);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_cnt[0]) atomicAdd(&ctrl->ncomp_next, s_cnt[0]);
-        if (s_cnt[1]) atomicAdd(&ctrl->edge_count, s_cnt[1]);
-    }
+    // (new roots, emitted edges) of this workgroup; k_relabel adds them up
+    if (threadIdx.x == 0) part[blockIdx.x] = make_uint2(s_cnt[0], s_cnt[1]);
 }
 
 // Merge, step 3: pointer jumping towards the roots.  Concurrent updates only
@@ -710,26 +891,105 @@ __global__ __launch_bounds__(256) void k_merge_jump(const uint32_t* __restrict__
 }
 
 // Merge, step 4: every point takes its component's root as its new label
-// (following any hops the jumping step left, up to a cap).  It is the last
-// kernel of a round; its first thread raises `done` once the new component
-// count has reached the loop's target, so that every kernel of a round
-// already queued behind this one returns at once (this kernel itself always
-// runs: on a finished loop it rewrites the same labels).
+// (following any hops the jumping step left, up to a cap), and every tile
+// leaves the run partials of the new labels for the next round (see
+// k_run_partials).  The labels of the two positions just outside the tile
+// are read while their own tiles rewrite them; the old and the new value
+// lead to the same root, so either serves.  It is the last kernel of a
+// round: workgroup 0 also totals k_merge_parent's partials into the new
+// component count and raises `done` once that reaches the loop's target,
+// so that every kernel of a round already queued behind this one returns
+// at once (this kernel itself always runs: on a finished loop it rewrites
+// the same labels).
 __global__ __launch_bounds__(256) void k_relabel(uint32_t* labels, const uint32_t* __restrict__ par, int64_t n,
-                                                 int steps, Ctrl* ctrl, int64_t target) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // the loop ends here (or stops on an error): a round queued after this one does nothing
-    if (i == 0 && ((int64_t)ctrl->ncomp_next <= target || ctrl->error)) ctrl->done = 1u;
-    if (i >= n) return;
-    uint32_t r = par[labels[i]];
-    int it = 0;
-    for (; it < steps; ++it) {
-        const uint32_t rr = par[r];
-        if (rr == r) break;
-        r = rr;
+                                                 int steps, uint32_t* __restrict__ tile_part,
+                                                 const uint2* __restrict__ part, int nparts, Ctrl* ctrl,
+                                                 int64_t target) {
+    __shared__ uint32_t s_new[kRunLds];
+    __shared__ uint32_t s_w[8];
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0) {
+        // (unless the loop had already finished, when k_merge_parent left
+        // its partials untouched)
+        const bool was_done = ctrl->done != 0u;
+        uint32_t r = 0, e = 0;
+        for (int b = tid; b < nparts; b += blockDim.x) {
+            r += part[b].x;
+            e += part[b].y;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            r += __shfl_xor(r, off);
+            e += __shfl_xor(e, off);
+        }
+        if (lane_id() == 0) { s_w[tid / 64] = r; s_w[4 + tid / 64] = e; }
+        __syncthreads();
+        if (tid == 0 && !was_done) {
+            r = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+            e = s_w[4] + s_w[5] + s_w[6] + s_w[7];
+            ctrl->ncomp_next = r;
+            ctrl->edge_count += e;
+            // the loop ends here (or stops on an error)
+            if ((int64_t)r <= target || ctrl->error) ctrl->done = 1u;
+        }
+        __syncthreads();
     }
-    if (it == steps) atomicOr(&ctrl->error, kErrJump);
-    labels[i] = r;
+    const int64_t base = (int64_t)blockIdx.x * kRunTile;
+    // thread 0 also follows position base-1, thread 1 position base+kRunTile
+    const int64_t hp = tid == 0 ? base - 1 : (tid == 1 ? base + kRunTile : -1);
+    const bool halo = hp >= 0 && hp < n;
+    uint32_t r[kRunPer];
+    uint32_t h = halo ? labels[hp] : 0u;
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int64_t p = base + (int64_t)q * 256 + tid;
+        r[q] = p < n ? labels[p] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q)
+        if (base + (int64_t)q * 256 + tid < n) r[q] = par[r[q]];
+    if (halo) h = par[h];
+    // finish the chains in lockstep: one batch of independent loads per hop
+    bool more = true;
+    for (int it = 0; it < steps && more; ++it) {
+        more = false;
+        uint32_t rr[kRunPer];
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) rr[q] = (base + (int64_t)q * 256 + tid < n) ? par[r[q]] : r[q];
+        const uint32_t hh = halo ? par[h] : h;
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) {
+            more |= rr[q] != r[q];
+            r[q] = rr[q];
+        }
+        more |= hh != h;
+        h = hh;
+    }
+    if (more) atomicOr(&ctrl->error, kErrJump);
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int x = q * 256 + tid;
+        if (base + x < n) labels[base + x] = r[q];
+        s_new[run_lds(x + 1)] = r[q];
+    }
+    if (tid == 0) s_new[run_lds(0)] = h;
+    if (tid == 1) s_new[run_lds(kRunTile + 1)] = h;
+    __syncthreads();
+    uint32_t hmax = 0u, tmin = kNone;
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int x = q * 256 + tid;
+        const int64_t p = base + x;
+        if (p < n) {
+            const uint32_t l = s_new[run_lds(x + 1)];
+            if (p == 0 || s_new[run_lds(x)] != l) hmax = max(hmax, (uint32_t)p);
+            if (p == n - 1 || s_new[run_lds(x + 2)] != l) tmin = min(tmin, (uint32_t)p);
+        }
+    }
+    block_max_min256(hmax, tmin, s_w);
+    if (tid == 0) {
+        tile_part[2 * blockIdx.x] = hmax;
+        tile_part[2 * blockIdx.x + 1] = tmin;
+    }
 }
 
 // ===========================================================================
@@ -912,7 +1172,7 @@ __global__ __launch_bounds__(256) void k_batch_morton(const float* __restrict__ 
                                                       const uint32_t* __restrict__ cloud_of,
                                                       const CloudMorton* __restrict__ cm, int64_t n, int cloud_shift,
                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                      Ctrl* ctrl) {
+                                                      uint64_t* part) {
     __shared__ uint64_t s_or[4], s_and[4];
     uint64_t kor = 0, kand = ~0ull;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -941,8 +1201,30 @@ __global__ __launch_bounds__(256) void k_batch_morton(const float* __restrict__ 
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int v = 1; v < 4; ++v) { kor |= s_or[v]; kand &= s_and[v]; }
-        atomicOr((unsigned long long*)&ctrl->key_or, (unsigned long long)kor);
-        atomicAnd((unsigned long long*)&ctrl->key_and, (unsigned long long)kand);
+        part[2 * blockIdx.x] = kor;
+        part[2 * blockIdx.x + 1] = kand;
+    }
+}
+
+// Folds the nb (OR, AND) partials of k_batch_morton into the control block.
+__global__ __launch_bounds__(256) void k_or_and_final(const uint64_t* __restrict__ part, int nb, Ctrl* ctrl) {
+    __shared__ uint64_t s_or[4], s_and[4];
+    uint64_t kor = 0, kand = ~0ull;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        kor |= part[2 * b];
+        kand &= part[2 * b + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        kor |= __shfl_xor(kor, off);
+        kand &= __shfl_xor(kand, off);
+    }
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) { s_or[w] = kor; s_and[w] = kand; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)blockDim.x / 64; ++v) { kor |= s_or[v]; kand &= s_and[v]; }
+        ctrl->key_or = kor;
+        ctrl->key_and = kand;
     }
 }
 
@@ -999,7 +1281,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint4* __restric
 // workspace layout
 
 struct Layout {
-    size_t ctrl, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_start, run_part, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, core_s, core_o, total;
+    size_t ctrl, bpart, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_part, run_carry, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, core_s, core_o, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1021,6 +1303,7 @@ static Layout make_layout(int64_t n, int dim) {
     };
     const size_t N = (size_t)(n > 0 ? n : 1), M = (size_t)(n > 1 ? n - 1 : 1);
     L.ctrl = take(sizeof(Ctrl));
+    L.bpart = take(32 * (size_t)kPartBlocks);
     L.k0 = take(8 * N);
     L.k1 = take(8 * N);
     L.v0 = take(4 * N);
@@ -1038,8 +1321,8 @@ static Layout make_layout(int64_t n, int dim) {
     L.exch = take(8 * M);
     L.rlo = take(4 * M);
     L.rhi = take(4 * M);
-    L.run_start = take(4 * N);
-    L.run_part = take(4 * (N / kRunTile + 2));
+    L.run_part = take(8 * (N / kRunTile + 2));
+    L.run_carry = take(8 * (N / kRunTile + 2));
     L.labels = take(4 * N);
     L.ub = take(4 * N);
     L.compkey = take(8 * N);
@@ -1125,11 +1408,6 @@ static void* stage(emst_ctx* ctx, size_t bytes) {
 static int fail(emst_ctx* ctx, int code, const char* msg) {
     if (ctx) ctx->err = msg;
     return code;
-}
-
-static inline unsigned grid_for(int64_t n, int threads = 256) {
-    int64_t g = (n + threads - 1) / threads;
-    return (unsigned)(g < 1 ? 1 : g);
 }
 
 extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_json) {
@@ -1249,13 +1527,14 @@ MortonParams morton_params(const float* lo, const float* hi, int dim, int bits) 
     return mp;
 }
 
-hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_start, uint32_t* run_part, const uint32_t* rlo,
-                            const uint32_t* rhi, uint2* lab2, int64_t n, const Ctrl* ctrl, hipStream_t st) {
-    const int nb = (int)((n + kRunTile - 1) / kRunTile);
-    k_runs_reduce<<<nb, 256, 0, st>>>(labels, n, run_part, ctrl);
-    k_runs_scan<<<1, 1024, 0, st>>>(run_part, nb, ctrl);
-    k_runs_down<<<nb, 256, 0, st>>>(labels, n, run_part, run_start, ctrl);
-    k_record_labels<<<grid_for(n - 1), 256, 0, st>>>(labels, run_start, rlo, rhi, lab2, n - 1, ctrl);
+// The record labels of arbitrary labels (no bounds).
+hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_part, uint32_t* run_carry, const uint32_t* rlo,
+                            const uint32_t* rhi, uint2* lab2, int64_t n, Ctrl* ctrl, hipStream_t st) {
+    const int nb = run_tiles(n);
+    k_run_partials<<<nb, 256, 0, st>>>(labels, n, run_part);
+    k_tile_carries<<<1, 1024, 0, st>>>(run_part, nb, run_carry, ctrl);
+    k_round_prep<3, false, false><<<nb, 256, 0, st>>>(labels, run_carry, rlo, rhi, lab2, nullptr, nullptr, nullptr,
+                                                      n, nullptr, ctrl);
     return hipGetLastError();
 }
 
@@ -1263,6 +1542,7 @@ hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_start, uint32_
 template <int DIM>
 struct Bufs {
     Ctrl* ctrl;
+    uint32_t* bpart;  // per-workgroup partials (kPartBlocks x 32 bytes)
     uint64_t *k0, *k1;
     uint32_t *v0, *v1, *hist;
     float* spts;
@@ -1273,7 +1553,7 @@ struct Bufs {
     uint32_t *node_parent, *leaf_parent;
     Up* up;
     uint64_t* exch;
-    uint32_t *rlo, *rhi, *run_start, *run_part, *labels, *ub;
+    uint32_t *rlo, *rhi, *run_part, *run_carry, *labels, *ub;
     uint64_t* compkey;
     uint32_t *compmax, *succ, *par, *cand_d, *cand_j;
     uint4* eud;
@@ -1284,6 +1564,7 @@ template <int DIM>
 Bufs<DIM> carve(char* ws, const Layout& L) {
     Bufs<DIM> b;
     b.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+    b.bpart = reinterpret_cast<uint32_t*>(ws + L.bpart);
     b.k0 = reinterpret_cast<uint64_t*>(ws + L.k0);
     b.k1 = reinterpret_cast<uint64_t*>(ws + L.k1);
     b.v0 = reinterpret_cast<uint32_t*>(ws + L.v0);
@@ -1301,8 +1582,8 @@ Bufs<DIM> carve(char* ws, const Layout& L) {
     b.exch = reinterpret_cast<uint64_t*>(ws + L.exch);
     b.rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
     b.rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
-    b.run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
     b.run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
+    b.run_carry = reinterpret_cast<uint32_t*>(ws + L.run_carry);
     b.labels = reinterpret_cast<uint32_t*>(ws + L.labels);
     b.ub = reinterpret_cast<uint32_t*>(ws + L.ub);
     b.compkey = reinterpret_cast<uint64_t*>(ws + L.compkey);
@@ -1346,11 +1627,17 @@ template <int DIM>
 int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int round, int height,
                   int variant, const uint32_t* cloud_of, int64_t target, bool prof, hipStream_t st) {
     hipEvent_t* E = ctx->ev;
-    HIP_TRY(propagate_labels(b.labels, b.run_start, b.run_part, b.rlo, b.rhi, b.lab2, n, b.ctrl, st));
-    if (round == 0)
-        k_bounds<DIM, true><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
-    else
-        k_bounds<DIM, false><<<grid_for(n), 256, 0, st>>>(b.spts, b.labels, cloud_of, ta.core_s, n, b.ub, b.ctrl);
+    // record labels and bounds; the run partials of round r > 0 come from
+    // the relabel kernel of round r - 1
+    const int nt = run_tiles(n);
+    if (round == 0) {
+        k_round_prep<DIM, true, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
+                                                          cloud_of, ta.core_s, n, b.ub, b.ctrl);
+    } else {
+        k_tile_carries<<<1, 1024, 0, st>>>(b.run_part, nt, b.run_carry, b.ctrl);
+        k_round_prep<DIM, false, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
+                                                           cloud_of, ta.core_s, n, b.ub, b.ctrl);
+    }
     if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
     ta.first = round == 0;
     HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
@@ -1360,11 +1647,13 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
                                                b.ctrl);
     k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.succ, b.ctrl, n,
                                               cloud_of != nullptr);
-    k_merge_parent<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(
-        b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud, b.ctrl, n);
+    const int mp_blocks = (int)std::min<unsigned>(grid_for(n), kPartBlocks);
+    k_merge_parent<<<mp_blocks, 256, 0, st>>>(b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud,
+                                              reinterpret_cast<uint2*>(b.bpart), b.ctrl, n);
     HIP_TRY(hipGetLastError());
     k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024, b.ctrl);
-    k_relabel<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 4096, b.ctrl, target);
+    k_relabel<<<nt, 256, 0, st>>>(b.labels, b.par, n, 4096, b.run_part, reinterpret_cast<const uint2*>(b.bpart),
+                                  mp_blocks, b.ctrl, target);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
 }
@@ -1614,10 +1903,10 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
     case kPhBox:  // validation + scene box
         if (j.prof) HIP_TRY(hipEventRecord(E[0], st));
         k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
-        k_bbox<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(j.pts, n, b.ctrl);
+        HIP_TRY(launch_bbox<DIM>(j.pts, n, b.bpart, b.ctrl, st));
         break;
     case kPhTree: {  // Morton codes, sort, hierarchy
-        k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(j.pts, n, j.mp, b.k0, b.v0, b.ctrl);
+        k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(j.pts, n, j.mp, b.k0, b.v0);
         const int shifts[8] = {0, 8, 16, 24, 32, 40, 48, 56};
         HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, 8, &j.codes_in1));
         const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
@@ -1895,8 +2184,12 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     memcpy(h, cm.data(), sizeof(CloudMorton) * B);
     HIP_TRY(hipMemcpyAsync(d_cm, h, sizeof(CloudMorton) * B, hipMemcpyHostToDevice, st));
     // ---- codes (cloud id on top) + sort
-    k_batch_morton<<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(pts3, cloud_of, d_cm, n, avail, b.k0,
-                                                                           b.v0, b.ctrl);
+    {
+        const int nb = (int)std::min<unsigned>(grid_for(n), kPartBlocks);
+        uint64_t* part = reinterpret_cast<uint64_t*>(b.bpart);
+        k_batch_morton<<<nb, 256, 0, st>>>(pts3, cloud_of, d_cm, n, avail, b.k0, b.v0, part);
+        k_or_and_final<<<1, 256, 0, st>>>(part, nb, b.ctrl);
+    }
     HIP_TRY(hipGetLastError());
     if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
     int shifts[8], ns = 0;
@@ -2331,8 +2624,8 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint64_t* exch = reinterpret_cast<uint64_t*>(ws + L.exch);
     uint32_t* rlo = reinterpret_cast<uint32_t*>(ws + L.rlo);
     uint32_t* rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
-    uint32_t* run_start = reinterpret_cast<uint32_t*>(ws + L.run_start);
     uint32_t* run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
+    uint32_t* run_carry = reinterpret_cast<uint32_t*>(ws + L.run_carry);
     Rec<3>* recs = reinterpret_cast<Rec<3>*>(ws + L.recs);
     uint2* lab2 = reinterpret_cast<uint2*>(ws + L.lab2);
     uint32_t* node_parent = reinterpret_cast<uint32_t*>(ws + L.node_parent);
@@ -2342,7 +2635,7 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     uint8_t* height = reinterpret_cast<uint8_t*>(ws + L.height);
     k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, n, recs, leaf_parent, node_parent, exch, rlo, rhi, height,
                                             ctrl);
-    HIP_TRY(propagate_labels(labels, run_start, run_part, rlo, rhi, lab2, n, ctrl, st));
+    HIP_TRY(propagate_labels(labels, run_part, run_carry, rlo, rhi, lab2, n, ctrl, st));
     k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, lab2, node_parent, n - 1, d_left, d_right, d_label);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ctx->h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
@@ -2396,14 +2689,14 @@ extern "C" int emst_test_tree_boxes(emst_ctx* ctx, const float* d_points, int64_
     const Layout L = make_layout(n, 3);
     Bufs<3> b = carve<3>(ws, L);
     k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
-    k_bbox<3><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(d_points, n, b.ctrl);
+    HIP_TRY(launch_bbox<3>(d_points, n, b.bpart, b.ctrl, st));
     HIP_TRY(hipGetLastError());
     if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
     if (ctx->h_ctrl->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
     float lo[3], hi[3];
     for (int k = 0; k < 3; ++k) { lo[k] = ord_dec(ctx->h_ctrl->bb_min[k]); hi[k] = ord_dec(ctx->h_ctrl->bb_max[k]); }
     const MortonParams mp = morton_params(lo, hi, 3, 21);
-    k_morton<3><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(d_points, n, mp, b.k0, b.v0, b.ctrl);
+    k_morton<3><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(d_points, n, mp, b.k0, b.v0);
     int shifts[8];
     for (int q = 0; q < 8; ++q) shifts[q] = 8 * q;
     int in1 = 0;

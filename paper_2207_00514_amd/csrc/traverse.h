@@ -778,14 +778,15 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             }
             bool found = false;
             while (sp > 0) {
-                --sp;
-                uint2 e;
-                if (sp < base) {
-                    base = sp;
-                    e = spill[sp];
-                } else {
-                    e = lds[sp % kLdsDepth][t];
+                if (sp == base) {
+                    // ring empty: move spilled entries back first (rare), so
+                    // that every pop is a plain LDS read
+                    const int back = base < kLdsDepth ? base : kLdsDepth;
+                    for (int q = 1; q <= back; ++q) lds[(base - q) % kLdsDepth][t] = spill[base - q];
+                    base -= back;
                 }
+                --sp;
+                const uint2 e = lds[sp % kLdsDepth][t];
                 if (bitsf(e.y) <= radius) {
                     node = e.x;
                     found = true;
@@ -913,14 +914,13 @@ __global__ __launch_bounds__(256) void k_core_dist(TraverseArgs<DIM> a, int k, f
         }
         bool found = false;
         while (sp > 0) {
-            --sp;
-            uint2 e;
-            if (sp < base) {
-                base = sp;
-                e = spill[sp];
-            } else {
-                e = lds[sp % kDepth][t];
+            if (sp == base) {  // as in k_traverse_fast
+                const int back = base < kDepth ? base : kDepth;
+                for (int q = 1; q <= back; ++q) lds[(base - q) % kDepth][t] = spill[base - q];
+                base -= back;
             }
+            --sp;
+            const uint2 e = lds[sp % kDepth][t];
             if (bitsf(e.y) <= radius) {
                 node = e.x;
                 found = true;
