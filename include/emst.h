@@ -274,22 +274,28 @@ int emst_set_counting(emst_ctx *ctx, int on);
  *   9  as 6 with an 8-deep LDS stack
  *  10  as 7, but each wave of 64 queries starts below the root, at the
  *      lowest ancestor of its leaves whose Morton cell holds every lane's
- *      search ball (default)
+ *      search ball
  *  11  as 10 with the component bound shared while the round runs (every
  *      improved candidate lowers it with an atomicMin, every node visit
  *      re-reads it)
+ *  12  as 10 with two pending nodes per lane: both records are loaded
+ *      together, the two nearest admissible internal children of the four
+ *      become the next pair, the others are deferred
+ *  13  as 10, and a point keeps last round's result where it still holds:
+ *      its candidate if that is still outside its component, or "nothing"
+ *      if it found nothing within a radius at least the new one (default)
  * -1 (the default) takes the variant from the context's autotune table
- * (emst_set_autotune) for the call's mode, dimension and size, else 10 for
+ * (emst_set_autotune) for the call's mode, dimension and size, else 13 for
  * emst_build and 7 for emst_build_batched.
  * Batches (emst_build_batched) run 0, 5, 7 or 8 as chosen and 7 for any
  * other value.
- * Returns EMST_EINVAL outside [-1, 11]. */
+ * Returns EMST_EINVAL outside [-1, 13]. */
 int emst_set_traversal(emst_ctx *ctx, int variant);
 
 /* Traversal-shape table (the autotuner's output), a JSON document
  *
  *   {"entries": [{"mode": "single" | "batched", "dim": 2 | 3,
- *                 "n_min": <points>, "variant": <0..11>}, ...]}
+ *                 "n_min": <points>, "variant": <0..13>}, ...]}
  *
  * (other keys are ignored).  A call in auto mode (emst_set_traversal -1)
  * with n points uses the entry of its mode and dimension with the largest

@@ -21,7 +21,7 @@ import numpy as np
 
 from . import workloads as W
 
-SINGLE_CANDIDATES = (5, 7, 8, 10, 11)
+SINGLE_CANDIDATES = (5, 7, 8, 10, 11, 13)
 BATCHED_CANDIDATES = (0, 5, 7, 8)
 
 

@@ -786,6 +786,138 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Query lists (traversal variant 13 from the third round on): the points
+// that still have to search, in Morton order, so that the traversal's waves
+// run full.  A point whose last result still holds (see k_traverse_fast,
+// REUSE) offers its kept candidate to its component here instead.
+
+// Per tile of kRunTile positions: qflag[i] = 1 for a point that must
+// search, qcnt[t] = their number.  A kept candidate farther than the
+// component's bound cannot be the component's shortest edge (the bound is
+// the length of one of its outgoing edges), so only the others are offered.
+__global__ __launch_bounds__(256) void k_reuse_mark(const uint32_t* __restrict__ labels,
+                                                    const uint32_t* __restrict__ ub,
+                                                    const uint32_t* __restrict__ cand_d,
+                                                    const uint32_t* __restrict__ cand_j,
+                                                    const uint32_t* __restrict__ pos,
+                                                    const uint32_t* __restrict__ orig, uint64_t* compkey,
+                                                    uint8_t* __restrict__ qflag, uint32_t* __restrict__ qcnt,
+                                                    int64_t n, const Ctrl* ctrl) {
+    if (ctrl->done) return;
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kRunTile;
+    uint32_t c[kRunPer], pj[kRunPer], pd[kRunPer], other[kRunPer], bound[kRunPer];
+    // all loads of the tile first, one dependent step at a time
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        const bool valid = i < n;
+        c[q] = valid ? labels[i] : kNone;
+        pj[q] = valid ? cand_j[i] : kNone;
+        pd[q] = valid ? cand_d[i] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        other[q] = pj[q] != kNone ? pos[pj[q]] : 0u;
+        bound[q] = c[q] != kNone ? ub[c[q]] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) other[q] = pj[q] != kNone ? labels[other[q]] : kNone;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = kKeyMax;
+        if (valid) {
+            bool need;
+            if (pj[q] != kNone) {
+                const bool keep = other[q] != c[q];
+                if (keep && pd[q] <= bound[q]) key = ((uint64_t)pd[q] << 32) | (uint64_t)min(orig[i], pj[q]);
+                need = !keep;
+            } else {
+                need = bound[q] > pd[q];
+            }
+            qflag[i] = need ? 1u : 0u;
+            cnt += need;
+        }
+        if (base + q * 256 < n) {  // uniform over the workgroup
+            bool run_end;
+            key = wave_seg_min<uint64_t>(c[q], key, &run_end);
+            if (valid && run_end && key != kKeyMax && key < load_relaxed64(&compkey[c[q]]))
+                atomicMin((unsigned long long*)&compkey[c[q]], (unsigned long long)key);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) qcnt[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// qoff[t] = sum(qcnt[u], u < t); ctrl->qcount = the total.  One workgroup
+// of 1024 threads.
+__global__ __launch_bounds__(1024) void k_qlist_scan(const uint32_t* __restrict__ qcnt, int nt,
+                                                     uint32_t* __restrict__ qoff, Ctrl* ctrl) {
+    if (ctrl->done) return;
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_incl[1024];
+    uint32_t run = 0;
+    for (int c0 = 0; c0 < nt; c0 += 1024) {
+        const int t = c0 + (int)threadIdx.x;
+        uint32_t x = t < nt ? qcnt[t] : 0u;
+        const int lane = lane_id(), w = threadIdx.x / 64;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int k = 0; k < w; ++k) before += s_w[k];
+        s_incl[threadIdx.x] = x + before;
+        __syncthreads();
+        const uint32_t ex = run + (threadIdx.x > 0 ? s_incl[threadIdx.x - 1] : 0u);
+        if (t < nt) qoff[t] = ex;
+        run += s_incl[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctrl->qcount = run;
+}
+
+// qlist[qoff[t] + k] = the k-th flagged position of tile t, in order.
+__global__ __launch_bounds__(256) void k_qlist_write(const uint8_t* __restrict__ qflag,
+                                                     const uint32_t* __restrict__ qoff, int64_t n,
+                                                     uint32_t* __restrict__ qlist, const Ctrl* ctrl) {
+    if (ctrl->done) return;
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kRunTile;
+    const int64_t x0 = base + (int64_t)threadIdx.x * kRunPer;  // this thread's kRunPer consecutive positions
+    uint32_t f[kRunPer];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kRunPer; ++j) {
+        f[j] = x0 + j < n ? qflag[x0 + j] : 0u;
+        cnt += f[j];
+    }
+    // exclusive sum over the threads of the workgroup
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t at = qoff[blockIdx.x] + inc - cnt;
+    for (int k = 0; k < w; ++k) at += s_w[k];
+#pragma unroll
+    for (int j = 0; j < kRunPer; ++j)
+        if (f[j]) qlist[at++] = (uint32_t)(x0 + j);
+}
+
 // Stage B of the component minimum: among the points whose candidate matches
 // the component's (D bits, min index) key, the smallest max index wins, so
 // the component edge is the minimum under (D, min, max).
@@ -797,9 +929,9 @@ __global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ ca
                                                  int64_t n, const Ctrl* ctrl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || ctrl->done) return;
-    const uint32_t cd = cand_d[i];
-    if (cd == kNone) return;
-    const uint32_t j = cand_j[i], oi = orig[i], c = labels[i];
+    const uint32_t j = cand_j[i];
+    if (j == kNone) return;  // no candidate
+    const uint32_t cd = cand_d[i], oi = orig[i], c = labels[i];
     const uint64_t key = ((uint64_t)cd << 32) | (uint64_t)min(oi, j);
     if (key == compkey[c]) atomicMin(&compmax[c], max(oi, j));
 }
@@ -1281,7 +1413,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint4* __restric
 // workspace layout
 
 struct Layout {
-    size_t ctrl, bpart, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_part, run_carry, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, core_s, core_o, total;
+    size_t ctrl, bpart, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_part, run_carry, qcnt, qoff, qflag, qlist, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, core_s, core_o, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1323,6 +1455,10 @@ static Layout make_layout(int64_t n, int dim) {
     L.rhi = take(4 * M);
     L.run_part = take(8 * (N / kRunTile + 2));
     L.run_carry = take(8 * (N / kRunTile + 2));
+    L.qcnt = take(4 * (N / kRunTile + 2));
+    L.qoff = take(4 * (N / kRunTile + 2));
+    L.qflag = take(N);
+    L.qlist = take(4 * N);
     L.labels = take(4 * N);
     L.ub = take(4 * N);
     L.compkey = take(8 * N);
@@ -1366,7 +1502,7 @@ static BatchLayout make_batch_layout(int64_t n, int64_t clouds) {
 
 using namespace emst;
 
-constexpr int kMaxVariant = 11;  // traversal variants 0 .. 11
+constexpr int kMaxVariant = 13;  // traversal variants 0 .. 13
 
 struct emst_ctx {
     int device = 0;
@@ -1554,6 +1690,8 @@ struct Bufs {
     Up* up;
     uint64_t* exch;
     uint32_t *rlo, *rhi, *run_part, *run_carry, *labels, *ub;
+    uint32_t *qcnt, *qoff, *qlist;
+    uint8_t* qflag;
     uint64_t* compkey;
     uint32_t *compmax, *succ, *par, *cand_d, *cand_j;
     uint4* eud;
@@ -1584,6 +1722,10 @@ Bufs<DIM> carve(char* ws, const Layout& L) {
     b.rhi = reinterpret_cast<uint32_t*>(ws + L.rhi);
     b.run_part = reinterpret_cast<uint32_t*>(ws + L.run_part);
     b.run_carry = reinterpret_cast<uint32_t*>(ws + L.run_carry);
+    b.qcnt = reinterpret_cast<uint32_t*>(ws + L.qcnt);
+    b.qoff = reinterpret_cast<uint32_t*>(ws + L.qoff);
+    b.qflag = reinterpret_cast<uint8_t*>(ws + L.qflag);
+    b.qlist = reinterpret_cast<uint32_t*>(ws + L.qlist);
     b.labels = reinterpret_cast<uint32_t*>(ws + L.labels);
     b.ub = reinterpret_cast<uint32_t*>(ws + L.ub);
     b.compkey = reinterpret_cast<uint64_t*>(ws + L.compkey);
@@ -1608,6 +1750,8 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     ta.wave_lca = reinterpret_cast<const uint32_t*>(b.exch);  // the build's exchange words are free by now
     ta.core_s = nullptr;
     ta.core_o = nullptr;
+    ta.pos = b.pos;
+    ta.qlist = nullptr;
     return ta;
 }
 
@@ -1638,8 +1782,20 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
         k_round_prep<DIM, false, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
                                                            cloud_of, ta.core_s, n, b.ub, b.ctrl);
     }
-    if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
     ta.first = round == 0;
+    // from the third round on (the second keeps nothing: every point's
+    // nearest neighbour joins its component in the first), variant 13
+    // searches only the points whose last result no longer holds
+    ta.qlist = nullptr;
+    if (variant == 13 && round >= 2 && !cloud_of) {
+        k_reuse_mark<<<nt, 256, 0, st>>>(b.labels, b.ub, b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag,
+                                         b.qcnt, n, b.ctrl);
+        k_qlist_scan<<<1, 1024, 0, st>>>(b.qcnt, nt, b.qoff, b.ctrl);
+        k_qlist_write<<<nt, 256, 0, st>>>(b.qflag, b.qoff, n, b.qlist, b.ctrl);
+        HIP_TRY(hipGetLastError());
+        ta.qlist = b.qlist;
+    }
+    if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
     HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
     if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
     if (round > 0)
@@ -1875,7 +2031,7 @@ static Job make_job(emst_ctx* ctx, const float* pts, int64_t n, int dim, char* w
     j.h = h;
     j.prof = prof;
     j.ncomp = n;
-    j.variant = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(0, dim, n, 10);
+    j.variant = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(0, dim, n, 13);
     memset(&j.S, 0, sizeof(j.S));
     j.S.n = n;
     j.S.dim = dim;
@@ -2045,11 +2201,13 @@ int job_advance(emst_ctx* ctx, Job& j) {
     }
 }
 
-// The rounds of one job with the next round always queued before the host
-// reads the last one back, so the device never idles while the host checks
-// a round: round r's control block goes to mirror r % 2 and an event marks
-// its arrival.  When round r ends the loop, the queued round r + 1 finds
-// `done` raised and returns at once.  Round 0 is already queued (by the fit
+// The rounds of one job, with the next round queued before the host reads
+// the last one back, so that the device does not idle while the host
+// checks a round: round r's control block goes to mirror r % 2 and an event
+// marks its arrival.  A round queued past the end finds `done` raised and
+// returns at once, but still costs its launches, so round r + 1 is queued
+// early only while the shrink of the last round predicts that round r
+// leaves at least two components.  Round 0 is already queued (by the fit
 // phase) with its copy going to mirror 0.
 template <int DIM>
 int job_rounds(emst_ctx* ctx, Job& j, hipStream_t st) {
@@ -2058,22 +2216,35 @@ int job_rounds(emst_ctx* ctx, Job& j, hipStream_t st) {
     const Layout L = make_layout(j.n, DIM);
     Bufs<DIM> b = carve<DIM>(j.ws, L);
     TraverseArgs<DIM> ta = job_args<DIM>(j, b);
+    auto queue = [&](int r) -> int {
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, j.n, r, j.height, j.variant, nullptr, 1, j.prof, st)) return rc;
+        HIP_TRY(hipMemcpyAsync(mirror[r & 1], b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(ctx->sev[r & 1], st));
+        return EMST_OK;
+    };
+    int queued = 0;      // last round on the stream
+    int64_t prev = 0;    // components entering the previous round (0: none yet)
     for (int r = 0;; ++r) {
-        const int nxt = r + 1;
-        if (nxt < 64) {
-            if (int rc = enqueue_round<DIM>(ctx, b, ta, j.n, nxt, j.height, j.variant, nullptr, 1, j.prof, st))
-                return rc;
-            HIP_TRY(hipMemcpyAsync(mirror[nxt & 1], b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipEventRecord(ctx->sev[nxt & 1], st));
+        const int64_t now = j.ncomp;  // components entering round r
+        const bool more = prev == 0 || (double)now * (double)now >= 2.0 * (double)prev;
+        if (queued == r && r + 1 < 64 && more) {
+            if (int rc = queue(r + 1)) return rc;
+            queued = r + 1;
         }
         HIP_TRY(hipEventSynchronize(ctx->sev[r & 1]));
         j.h = mirror[r & 1];
         j.round = r;
-        j.S.components[r] = j.ncomp;
+        j.S.components[r] = now;
         const int rc = job_advance<DIM>(ctx, j);
         j.h = mirror[0];
         if (rc) return rc;
         if (j.phase != kPhRound) return EMST_OK;
+        prev = now;
+        if (queued == r) {
+            if (r + 1 >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
+            if (int rc2 = queue(r + 1)) return rc2;
+            queued = r + 1;
+        }
     }
 }
 

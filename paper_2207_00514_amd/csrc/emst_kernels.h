@@ -25,7 +25,8 @@ struct Ctrl {
     uint32_t long_ties;      // the edge order met a run of equal keys too long to fix in place
     uint32_t dup_codes;      // sorted positions whose Morton code equals the previous one
     uint32_t done;           // the round loop has reached its target: later round kernels return at once
-    uint32_t pad[3];
+    uint32_t qcount;         // length of this round's query list
+    uint32_t pad[2];
 };
 
 constexpr uint32_t kErrStack = 1u;

@@ -59,6 +59,10 @@ struct TraverseArgs {
     // original index (null for the Euclidean tree)
     const float* core_s;
     const float* core_o;
+    const uint32_t* pos;  // sorted position of every original index
+    // this round's query list (the points that still search, in Morton
+    // order; length ctrl->qcount)
+    const uint32_t* qlist;
 };
 
 // Where a top-down search of query i starts.
@@ -92,15 +96,17 @@ __device__ __forceinline__ void flush_counts(Ctrl* ctrl, uint64_t internal, uint
 // candidate, its max index) directly.  Later the queries of a run of equal
 // labels within the wave combine first and one lane per run updates the
 // component with a 64-bit atomicMin.  Every lane of the wave must call it.
+// Without a candidate the point stores `miss` as its cand_d (cand_j is
+// kNone either way).
 template <int DIM>
 __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t i, uint32_t c, float best_d,
-                                             uint32_t best_j) {
+                                             uint32_t best_j, uint32_t miss = kNone) {
     const bool valid = i < a.n;
     const bool found = valid && best_j != kNone;
     uint64_t key = kKeyMax;
     if (valid) {
         const uint32_t oi = a.orig[i];
-        const uint32_t db = found ? fbits(best_d) : kNone;
+        const uint32_t db = found ? fbits(best_d) : miss;
         a.cand_d[i] = db;
         a.cand_j[i] = best_j;
         if (found) key = ((uint64_t)db << 32) | (uint64_t)min(oi, best_j);
@@ -662,15 +668,41 @@ __device__ __forceinline__ float widen(float radius) { return sqrtf(radius) * 1.
 // candidate lowers ub[C] with an atomicMin, and every lane re-reads ub[C]
 // at every node.  ub[C] only ever holds D values of real outgoing edges of
 // C, so it never drops below C's shortest one, whose point still admits it.
+//
+// With REUSE (variant 13) a point keeps last round's result where it still
+// holds.  The components only grow, so the points outside a point's
+// component only get fewer: if its candidate j is still outside, j is
+// still the nearest in (D, j) order and the point skips the search; if it
+// found nothing within last round's radius R, nothing outside lies within
+// R, and it skips the search whenever the new radius does not exceed R.
+// Such a point stores R in cand_d (with cand_j = kNone).  With LIST the
+// lanes take the points of the query list, which holds exactly the points
+// that must search (k_reuse_mark), so waves run full.  A wave of the list
+// spans more than 64 positions; its climb starts at the start node of the
+// 64 positions around its first point, an ancestor of that point's leaf,
+// and the climb's stopping rule (every lane's ball inside the cell) still
+// puts every lane's search region below the node it stops at.
 template <int DIM, int STACK, bool COUNT, bool UPWARD, int kLdsDepth = 16, bool WSTART = false, bool MREACH = false,
-          bool SHARED = false>
+          bool SHARED = false, bool REUSE = false, bool LIST = false>
 __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
     if (a.ctrl->done) return;  // the round loop has already finished
     __shared__ uint2 lds[kLdsDepth][256];
     const int t = threadIdx.x;
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + t;
+    int64_t i;
+    uint32_t first = 0;  // LIST: the wave's first point (its lane 0 holds the smallest position)
+    if (LIST) {
+        // the grid covers every point; only the blocks the list needs run
+        const int64_t cnt = a.ctrl->qcount;
+        const int64_t active = ((cnt + 255) / 256 + kXcds - 1) / kXcds * kXcds;
+        if ((int64_t)blockIdx.x >= active) return;
+        const int64_t li = xcd_block(blockIdx.x, active) * blockDim.x + t;
+        i = li < cnt ? (int64_t)a.qlist[li] : a.n;
+        first = __builtin_amdgcn_readfirstlane((uint32_t)i);
+    } else {
+        i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + t;
+    }
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
-    uint32_t c = kNone, best_j = kNone;
+    uint32_t c = kNone, best_j = kNone, miss = kNone;
     float best_d = INFINITY;
     if (i < a.n) {
         float p[DIM];
@@ -679,6 +711,23 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
         c = a.labels[i];
         float radius = bitsf(a.ub[c]);
         const float core_p = MREACH ? a.core_s[i] : 0.f;
+        bool search = true;
+        if (REUSE) {
+            miss = fbits(radius);
+            if (!a.first && !LIST) {
+                const uint32_t pj = a.cand_j[i], pd = a.cand_d[i];
+                if (pj != kNone) {
+                    if (a.labels[a.pos[pj]] != c) {
+                        best_d = bitsf(pd);
+                        best_j = pj;
+                        search = false;
+                    }
+                } else if (miss <= pd) {
+                    miss = pd;
+                    search = false;
+                }
+            }
+        }
         uint2 spill[STACK];
         int sp = 0, base = 0;  // entries [0, base) spilled, [base, sp) in the LDS ring
         uint32_t node, mask, anc = 0;
@@ -691,11 +740,11 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             u = a.up[anc];
         } else {
             node = start_node<DIM>(a, i);
-            mask = (node == kNone || (MREACH && core_p > radius)) ? 0u : 3u;
+            mask = (node == kNone || (MREACH && core_p > radius) || !search) ? 0u : 3u;
             if (WSTART && mask) {
                 // wave-uniform climb; lanes past the end take no part
                 const float rr = widen(radius);
-                uint32_t s = a.wave_lca[i >> 6];
+                uint32_t s = a.wave_lca[(LIST ? (int64_t)first : i) >> 6];
                 for (int h = 0; h < 160 && s != node; ++h) {
                     const Up cu = a.up[s];
                     if (__all(ball_in_cell<DIM>(p, rr, cu))) break;
@@ -804,6 +853,171 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             node = anc;
             mask = 2u >> (link & 1u);
             u = a.up[anc];
+        }
+    }
+    finish_query<DIM>(a, i, c, best_d, best_j, miss);
+    flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
+}
+
+// ---------------------------------------------------------------------------
+// variant 12: two nodes per step
+//
+// The search of variant 10 (per-wave start, LDS ring stack) with a lane
+// holding up to two pending nodes: it loads both records together, tests
+// up to four children, keeps the two nearest admissible internal children
+// as its next pair and defers the others (the farther first).  A step
+// issues the loads of two nodes at once, so the chain of dependent record
+// loads of the slowest lane, which sets the wave's time, is about half as
+// long; the price is that the second node of a pair is opened before the
+// first one's leaves could shrink the radius.  Every step pushes at most
+// two entries and descends both nodes one level, so twice the tree height
+// bounds the stack.
+
+// Compare-exchange of (key, ref) pairs so that the smaller key comes first.
+__device__ __forceinline__ void cmpx(uint32_t& ka, uint32_t& ra, uint32_t& kb, uint32_t& rb) {
+    const bool sw = kb < ka;
+    const uint32_t k = sw ? kb : ka, r = sw ? rb : ra;
+    kb = sw ? ka : kb;
+    rb = sw ? ra : rb;
+    ka = k;
+    ra = r;
+}
+
+template <int DIM, int STACK, bool COUNT, int kLdsDepth>
+__global__ __launch_bounds__(256) void k_traverse_dual(TraverseArgs<DIM> a) {
+    if (a.ctrl->done) return;  // the round loop has already finished
+    __shared__ uint2 lds[kLdsDepth][256];
+    const int t = threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + t;
+    uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
+    uint32_t c = kNone, best_j = kNone;
+    float best_d = INFINITY;
+    if (i < a.n) {
+        float p[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
+        c = a.labels[i];
+        float radius = bitsf(a.ub[c]);
+        constexpr int kCap = 2 * STACK + 4;
+        uint2 spill[kCap];
+        int sp = 0, base = 0;  // entries [0, base) spilled, [base, sp) in the LDS ring
+        bool overflow = false;
+        auto push = [&](uint32_t ref, uint32_t dbits) {
+            if (sp - base == kLdsDepth) {  // ring full: move its oldest entry out
+                if (base >= kCap) {
+                    overflow = true;
+                    return;
+                }
+                spill[base] = lds[base % kLdsDepth][t];
+                ++base;
+            }
+            lds[sp % kLdsDepth][t] = make_uint2(ref, dbits);
+            ++sp;
+        };
+        // the nearest deferred node still within the radius, or kNone
+        auto pop = [&]() -> uint32_t {
+            while (sp > 0) {
+                if (sp == base) {  // ring empty: move spilled entries back first
+                    const int back = base < kLdsDepth ? base : kLdsDepth;
+                    for (int q = 1; q <= back; ++q) lds[(base - q) % kLdsDepth][t] = spill[base - q];
+                    base -= back;
+                }
+                --sp;
+                const uint2 e = lds[sp % kLdsDepth][t];
+                if (bitsf(e.y) <= radius) return e.x;
+            }
+            return kNone;
+        };
+        uint32_t n0 = start_node<DIM>(a, i), n1 = kNone;
+        if (n0 != kNone) {
+            // per-wave start as in variant 10; lanes past the end take no part
+            const uint32_t root = n0;
+            const float rr = widen(radius);
+            uint32_t s = a.wave_lca[i >> 6];
+            for (int h = 0; h < 160 && s != root; ++h) {
+                const Up cu = a.up[s];
+                if (__all(ball_in_cell<DIM>(p, rr, cu))) break;
+                const uint32_t link = fbits(cu.a.w);
+                s = link == kNone ? root : link >> 1;
+            }
+            n0 = s;
+        }
+        for (int64_t guard = 0; n0 != kNone; ++guard) {
+            if (guard > 2 * a.n + 256 || overflow) {
+                atomicOr(&a.ctrl->error, kErrStack);
+                break;
+            }
+            const bool two = n1 != kNone;
+            Child<DIM> ch[4];
+            {
+                const Rec<DIM> r0 = a.recs[n0];
+                const uint2 l0 = a.lab2[n0];
+                unpack<DIM>(r0, ch[0], ch[1]);
+                ch[0].lab = l0.x;
+                ch[1].lab = l0.y;
+                Rec<DIM> r1 = r0;
+                uint2 l1 = l0;
+                if (two) {
+                    r1 = a.recs[n1];
+                    l1 = a.lab2[n1];
+                }
+                unpack<DIM>(r1, ch[2], ch[3]);
+                ch[2].lab = l1.x;
+                ch[3].lab = l1.y;
+            }
+            float d[4];
+            bool in[4], lf[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                d[q] = boxdist<DIM>(p, ch[q].lo, ch[q].hi);
+                in[q] = (q < 2 || two) && ch[q].lab != c;
+                lf[q] = (ch[q].ref & kLeafFlag) != 0u;
+                if (COUNT) {
+                    const bool v = q < 2 || two;
+                    n_leaf += v && lf[q];
+                    n_int += v && !lf[q];
+                    n_eval += in[q] && lf[q];
+                }
+            }
+            // leaf candidates in (D, j) order (a leaf box is its point)
+            {
+                uint64_t bk = ((uint64_t)fbits(best_d) << 32) | best_j;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t kq = ((uint64_t)fbits(d[q]) << 32) | (ch[q].ref & ~kLeafFlag);
+                    bk = (in[q] & lf[q] & (d[q] <= radius) & (kq < bk)) ? kq : bk;
+                }
+                best_d = bitsf((uint32_t)(bk >> 32));
+                best_j = (uint32_t)bk;
+                radius = fminf(radius, best_d);
+            }
+            // admissible internal children, nearest first
+            uint32_t k[4], r[4];
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool go = in[q] && !lf[q] && d[q] <= radius;
+                cnt += go;
+                k[q] = go ? fbits(d[q]) : 0xFFFFFFFFu;
+                r[q] = ch[q].ref;
+            }
+            cmpx(k[0], r[0], k[1], r[1]);
+            cmpx(k[2], r[2], k[3], r[3]);
+            cmpx(k[0], r[0], k[2], r[2]);
+            cmpx(k[1], r[1], k[3], r[3]);
+            cmpx(k[1], r[1], k[2], r[2]);
+            if (cnt == 4) push(r[3], k[3]);
+            if (cnt >= 3) push(r[2], k[2]);
+            if (cnt >= 2) {
+                n0 = r[0];
+                n1 = r[1];
+            } else if (cnt == 1) {
+                n0 = r[0];
+                n1 = pop();
+            } else {
+                n0 = pop();
+                n1 = n0 == kNone ? kNone : pop();
+            }
         }
     }
     finish_query<DIM>(a, i, c, best_d, best_j);
@@ -962,9 +1176,17 @@ template <int DIM, int STACK>
 hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count, hipStream_t st) {
     // a multiple of the XCD count, for the XCD-contiguous block mapping
     const unsigned grid = (unsigned)(((a.n + 255) / 256 + kXcds - 1) / kXcds * kXcds);
-    if (a.core_s) {  // mutual reachability: the loop and start of variant 10
-        if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, true><<<grid, 256, 0, st>>>(a);
-        else k_traverse_fast<DIM, STACK, false, false, 8, true, true><<<grid, 256, 0, st>>>(a);
+    if (a.core_s) {  // mutual reachability: the loop and start of variant 10 (with the reuse of 13)
+        if (variant == 13 && a.qlist) {
+            if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, true, false, true, true><<<grid, 256, 0, st>>>(a);
+            else k_traverse_fast<DIM, STACK, false, false, 8, true, true, false, true, true><<<grid, 256, 0, st>>>(a);
+        } else if (variant == 13) {
+            if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, true, false, true><<<grid, 256, 0, st>>>(a);
+            else k_traverse_fast<DIM, STACK, false, false, 8, true, true, false, true><<<grid, 256, 0, st>>>(a);
+        } else {
+            if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, true><<<grid, 256, 0, st>>>(a);
+            else k_traverse_fast<DIM, STACK, false, false, 8, true, true><<<grid, 256, 0, st>>>(a);
+        }
         return hipGetLastError();
     }
     if (variant == 1) {
@@ -991,6 +1213,15 @@ hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count
     } else if (variant == 10) {
         if (count) k_traverse_fast<DIM, STACK, true, false, 8, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_fast<DIM, STACK, false, false, 8, true><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 13 && a.qlist) {
+        if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, false, false, true, true><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false, 8, true, false, false, true, true><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 13) {
+        if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, false, false, true><<<grid, 256, 0, st>>>(a);
+        else k_traverse_fast<DIM, STACK, false, false, 8, true, false, false, true><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 12) {
+        if (count) k_traverse_dual<DIM, STACK, true, 8><<<grid, 256, 0, st>>>(a);
+        else k_traverse_dual<DIM, STACK, false, 8><<<grid, 256, 0, st>>>(a);
     } else if (variant == 11) {
         if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, false, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_fast<DIM, STACK, false, false, 8, true, false, true><<<grid, 256, 0, st>>>(a);

@@ -52,7 +52,7 @@ SMALL = [(n, dim, seed, kind)
          for n, seed in ((2, 1), (3, 2), (5, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4099, 8))]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
 @pytest.mark.parametrize("n,dim,seed,kind", SMALL)
 def test_small_clouds(ctx, n, dim, seed, kind, variant):
     pts = W.small_random(n, dim, seed, kind)
@@ -79,7 +79,7 @@ def test_short_runs_of_equal_edge_lengths(ctx, dim, span):
     assert ties_seen > 0
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_closed_forms(ctx, variant):
     cases = {
         "identical": W.identical(1000),
@@ -94,7 +94,7 @@ def test_closed_forms(ctx, variant):
         assert_same(run(ctx, pts, variant), oracle.emst(pts, threads=8), name)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_denormal_and_wide_range_coordinates(ctx, variant):
     rng = np.random.default_rng(3)
     tiny = (rng.random((500, 3)) * 1e-19).astype(np.float32)   # D is denormal
