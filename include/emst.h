@@ -285,10 +285,9 @@ int emst_set_counting(emst_ctx *ctx, int on);
  *      its candidate if that is still outside its component, or "nothing"
  *      if it found nothing within a radius at least the new one (default)
  * -1 (the default) takes the variant from the context's autotune table
- * (emst_set_autotune) for the call's mode, dimension and size, else 13 for
- * emst_build and 7 for emst_build_batched.
- * Batches (emst_build_batched) run 0, 5, 7 or 8 as chosen and 7 for any
- * other value.
+ * (emst_set_autotune) for the call's mode, dimension and size, else 13.
+ * Batches (emst_build_batched) run 0, 5, 7, 8 or 13 (with the start of 7)
+ * as chosen and 7 for any other value.
  * Returns EMST_EINVAL outside [-1, 13]. */
 int emst_set_traversal(emst_ctx *ctx, int variant);
 

@@ -22,7 +22,7 @@ import numpy as np
 from . import workloads as W
 
 SINGLE_CANDIDATES = (5, 7, 8, 10, 11, 13)
-BATCHED_CANDIDATES = (0, 5, 7, 8)
+BATCHED_CANDIDATES = (0, 5, 7, 8, 13)
 
 
 def _median_seconds(fn, repeats: int) -> float:

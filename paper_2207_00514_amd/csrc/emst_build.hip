@@ -256,12 +256,13 @@ __global__ __launch_bounds__(256) void k_codes_from(const uint64_t* __restrict__
 // per-component state: labels = own sorted position (Figure 3: every vertex
 // starts as its own component), bounds = +inf, component keys = max.
 template <int DIM>
+// (The per-component arrays need no initial values: the first round writes
+// every bound and key, and every component id writes its edge slot when it
+// merges or resets it while it is a root.)
 __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, const uint32_t* __restrict__ perm,
                                                 int64_t n, float* __restrict__ spts, uint32_t* __restrict__ orig,
                                                 uint32_t* __restrict__ pos, uint32_t* __restrict__ labels,
-                                                uint32_t* __restrict__ ub, uint64_t* __restrict__ compkey,
-                                                uint32_t* __restrict__ compmax, uint64_t* __restrict__ exch,
-                                                uint4* __restrict__ eud) {
+                                                uint64_t* __restrict__ exch) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t o = perm[i];
@@ -270,10 +271,6 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, c
     orig[i] = o;
     pos[o] = (uint32_t)i;
     labels[i] = (uint32_t)i;
-    ub[i] = kInfBits;
-    compkey[i] = kKeyMax;
-    compmax[i] = kNone;
-    eud[i] = make_uint4(kNone, kNone, kNone, 0u);   // the final root's slot keeps these and sorts last
     if (i + 1 < n) exch[i] = ~0ull;
 }
 
@@ -984,6 +981,7 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
             ub[c] = kInfBits;
             compkey[c] = kKeyMax;
             compmax[c] = kNone;
+            eud[c] = make_uint4(kNone, kNone, kNone, 0u);  // a final root's slot keeps this and sorts last
         } else {
             // a component id stops being one once it is merged, so every id
             // emits at most once over the whole run: its slot is its own
@@ -1787,7 +1785,7 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     // nearest neighbour joins its component in the first), variant 13
     // searches only the points whose last result no longer holds
     ta.qlist = nullptr;
-    if (variant == 13 && round >= 2 && !cloud_of) {
+    if (variant == 13 && round >= 2) {
         k_reuse_mark<<<nt, 256, 0, st>>>(b.labels, b.ub, b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag,
                                          b.qcnt, n, b.ctrl);
         k_qlist_scan<<<1, 1024, 0, st>>>(b.qcnt, nt, b.qoff, b.ctrl);
@@ -2068,7 +2066,7 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
         const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
         k_count_dups<<<grid_for(n), 256, 0, st>>>(codes, n, b.ctrl);
         k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig, b.pos,
-                                                   b.labels, b.ub, b.compkey, b.compmax, b.exch, b.eud);
+                                                   b.labels, b.exch);
         if (int rc = build_hierarchy<DIM>(ctx, b, codes, n, st)) return rc;
         break;
     }
@@ -2090,7 +2088,7 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
         HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, csh, cq, &j.codes_in1));
         const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
         k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig, b.pos,
-                                                   b.labels, b.ub, b.compkey, b.compmax, b.exch, b.eud);
+                                                   b.labels, b.exch);
         if (int rc = build_hierarchy<DIM>(ctx, b, codes, n, st)) return rc;
         break;
     }
@@ -2374,8 +2372,9 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     const uint64_t* codes = in1 ? b.k1 : b.k0;
     const uint32_t* perm = in1 ? b.v1 : b.v0;
     // ---- one tree over all clouds
-    k_gather<3><<<grid_for(n), 256, 0, st>>>(pts3, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
-                                             b.compmax, b.exch, b.eud);
+    k_gather<3><<<grid_for(n), 256, 0, st>>>(pts3, perm, n, b.spts, b.orig, b.pos, b.labels, b.exch);
+    // a batch of single points runs no round, so every edge slot starts empty
+    k_fill_u32<<<grid_for(4 * n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(b.eud), 4 * n, kNone);
     k_batch_sorted_cloud<<<grid_for(n), 256, 0, st>>>(cloud_of, perm, n, cloud_sorted);
     if (int rc = build_tree<3>(ctx, b, codes, n, st)) return rc;
     k_fill_u32<<<grid_for(B), 256, 0, st>>>(d_croot, B, kNone);
@@ -2388,10 +2387,10 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     TraverseArgs<3> ta = traverse_args<3>(b, n, ctx->h_ctrl->root);
     ta.cloud_of = cloud_sorted;
     ta.cloud_root = d_croot;
-    // variants 1-4 start every lane at one root and 6, 9, 10 need the Morton
-    // cells of one cloud: a batch runs them as 7
-    const int t = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(1, 3, n, 7);
-    const int variant = (t == 0 || t == 5 || t == 8) ? t : 7;
+    // variants 1-4 start every lane at one root and 6, 9-12 need the Morton
+    // cells of one cloud: a batch runs them as 7 (and 13 with the start of 7)
+    const int t = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(1, 3, n, 13);
+    const int variant = (t == 0 || t == 5 || t == 8 || t == 13) ? t : 7;
     if (int rc = run_rounds<3>(ctx, b, ta, n, nonempty, S.tree_height, variant, cloud_sorted, S, st)) return rc;
     if ((int64_t)ctx->h_ctrl->edge_count != eoff) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));
@@ -2874,8 +2873,7 @@ extern "C" int emst_test_tree_boxes(emst_ctx* ctx, const float* d_points, int64_
     HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, 8, &in1));
     const uint64_t* codes = in1 ? b.k1 : b.k0;
     const uint32_t* perm = in1 ? b.v1 : b.v0;
-    k_gather<3><<<grid_for(n), 256, 0, st>>>(d_points, perm, n, b.spts, b.orig, b.pos, b.labels, b.ub, b.compkey,
-                                             b.compmax, b.exch, b.eud);
+    k_gather<3><<<grid_for(n), 256, 0, st>>>(d_points, perm, n, b.spts, b.orig, b.pos, b.labels, b.exch);
     if (int rc = build_tree<3>(ctx, b, codes, n, st)) return rc;
     k_test_boxes<<<grid_for(n - 1), 256, 0, st>>>(b.recs, n - 1, d_left, d_right, d_lo, d_hi);
     HIP_TRY(hipGetLastError());

@@ -1213,6 +1213,15 @@ hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count
     } else if (variant == 10) {
         if (count) k_traverse_fast<DIM, STACK, true, false, 8, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_fast<DIM, STACK, false, false, 8, true><<<grid, 256, 0, st>>>(a);
+    } else if (variant == 13 && a.cloud_of) {
+        // batches: the start of variant 7 (each cloud's root) with the reuse
+        if (a.qlist) {
+            if (count) k_traverse_fast<DIM, STACK, true, false, 8, false, false, false, true, true><<<grid, 256, 0, st>>>(a);
+            else k_traverse_fast<DIM, STACK, false, false, 8, false, false, false, true, true><<<grid, 256, 0, st>>>(a);
+        } else {
+            if (count) k_traverse_fast<DIM, STACK, true, false, 8, false, false, false, true><<<grid, 256, 0, st>>>(a);
+            else k_traverse_fast<DIM, STACK, false, false, 8, false, false, false, true><<<grid, 256, 0, st>>>(a);
+        }
     } else if (variant == 13 && a.qlist) {
         if (count) k_traverse_fast<DIM, STACK, true, false, 8, true, false, false, true, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_fast<DIM, STACK, false, false, 8, true, false, false, true, true><<<grid, 256, 0, st>>>(a);

@@ -298,7 +298,7 @@ def run_batched(ctx, clouds):
     return [(e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()) for e, w, d in out]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 5, 7, 8, 10])
+@pytest.mark.parametrize("variant", [0, 1, 5, 7, 8, 10, 13])
 def test_batched_small_mixed(ctx, variant):
     ctx.set_traversal(variant)
     rng = np.random.default_rng(11)
