@@ -73,7 +73,7 @@ const char *emst_last_error(const emst_ctx *ctx);
 
 /* Exact number of workspace bytes emst_build, emst_core_distances and
  * emst_build_mreach need for n points of dimension dim (0 for invalid
- * arguments).  Grows linearly in n, 233 bytes per point in 3D. */
+ * arguments).  Grows linearly in n, 238 bytes per point in 3D. */
 size_t emst_workspace_bytes(int64_t n, int dim);
 
 /*
