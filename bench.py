@@ -43,8 +43,8 @@ TRAFFIC_SOURCES = ("traverse.h", "emst_common.h", "emst_kernels.h")
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 MEASURED_TRAFFIC = {
     # (workload, variant, source hash): (FETCH_SIZE KiB, WRITE_SIZE KiB, TCC hit fraction, profile)
-    ("clustered3d_2m", 10, "e873c24fee91cffd"):
-        (72378.0, 22329.6, 0.929, "profiles/k_traverse_fast_clustered3d_2m.md"),
+    ("clustered3d_2m", 13, "b71efd74f8dce137"):
+        (80808.0, 17174.2, 0.902, "profiles/k_traverse_fast_clustered3d_2m.md"),
 }
 
 
@@ -154,8 +154,11 @@ def main() -> int:
     value = n * args.steps / secs / 1e6
 
     rounds = cst["rounds"]
-    bytes_per_step = sum(algorithmic_bytes(dim, n, ci, li)
-                         for ci, li in zip(cst["child_tests_round"], cst["leaf_tests_round"]))
+    # per round: the queries the traversal ran (all n, or a query list's
+    # length), and the children they examined
+    bytes_per_step = sum(algorithmic_bytes(dim, q, ci, li)
+                         for q, ci, li in zip(cst["queries_round"], cst["child_tests_round"],
+                                              cst["leaf_tests_round"]))
     avg_launch_ms = trav_ms / max(launches, 1)
     bytes_per_launch = bytes_per_step / max(rounds, 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
@@ -205,7 +208,8 @@ def main() -> int:
             "compulsory_frac": round(b_min / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if avg_launch_ms > 0 else 0.0,
             "l2_hit": None if meas is None else meas[2],
             "traffic_profile": None if meas is None else meas[3],
-            "children_examined_per_query_round": round((cst["child_tests"] + cst["leaf_tests"]) / (n * rounds), 2),
+            "children_examined_per_query_round": round((cst["child_tests"] + cst["leaf_tests"])
+                                                       / max(sum(cst["queries_round"]), 1), 2),
             "dist_evals_per_query_round": round(cst["dist_evals"] / (n * rounds), 2),
         },
     }

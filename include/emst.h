@@ -251,6 +251,9 @@ typedef struct emst_stats {
     int32_t rank_codes;             /* 1 if the tree was built on rank-space
                                        codes (many points shared a Morton
                                        code), else 0 */
+    int64_t queries_round[64];      /* points the traversal searched in each
+                                       round: n, or the length of the round's
+                                       query list (variant 13, third round on) */
 } emst_stats;
 
 /* Time every phase with HIP events (adds synchronisation; off by default). */

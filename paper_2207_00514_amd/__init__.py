@@ -57,6 +57,7 @@ class Stats(ctypes.Structure):
         ("leaf_tests", ctypes.c_int64), ("child_tests_round", ctypes.c_int64 * 64),
         ("leaf_tests_round", ctypes.c_int64 * 64), ("dist_evals", ctypes.c_int64),
         ("traversal_variant", ctypes.c_int32), ("rank_codes", ctypes.c_int32),
+        ("queries_round", ctypes.c_int64 * 64),
     ]
 
     def as_dict(self) -> dict:
@@ -70,6 +71,7 @@ class Stats(ctypes.Structure):
             child_tests_round=list(self.child_tests_round[:r]),
             leaf_tests_round=list(self.leaf_tests_round[:r]), dist_evals=self.dist_evals,
             traversal_variant=self.traversal_variant, rank_codes=self.rank_codes,
+            queries_round=list(self.queries_round[:r]),
         )
 
 

@@ -1764,6 +1764,11 @@ int read_ctrl(emst_ctx* ctx, Ctrl* ctrl, hipStream_t st) {
 // Morton neighbours in different clouds bound nothing, every query searches
 // its own cloud's subtree, and a component without an outgoing edge (its
 // cloud is finished) becomes a root.
+// Variant 13 searches from a query list from the third round on (the
+// second keeps nothing: in the first round every point joins its nearest
+// neighbour's component).
+static inline bool uses_qlist(int variant, int round) { return variant == 13 && round >= 2; }
+
 // One Boruvka round, enqueued on st (no host wait).
 template <int DIM>
 int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int round, int height,
@@ -1781,11 +1786,9 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
                                                            cloud_of, ta.core_s, n, b.ub, b.ctrl);
     }
     ta.first = round == 0;
-    // from the third round on (the second keeps nothing: every point's
-    // nearest neighbour joins its component in the first), variant 13
-    // searches only the points whose last result no longer holds
+    // variant 13: only the points whose last result no longer holds search
     ta.qlist = nullptr;
-    if (variant == 13 && round >= 2) {
+    if (uses_qlist(variant, round)) {
         k_reuse_mark<<<nt, 256, 0, st>>>(b.labels, b.ub, b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag,
                                          b.qcnt, n, b.ctrl);
         k_qlist_scan<<<1, 1024, 0, st>>>(b.qcnt, nt, b.qoff, b.ctrl);
@@ -1846,6 +1849,7 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
         if (int rc = enqueue_round<DIM>(ctx, b, ta, n, round, height, variant, cloud_of, target, prof, st))
             return rc;
         if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+        S.queries_round[round] = uses_qlist(variant, round) ? (int64_t)ctx->h_ctrl->qcount : n;
         if (int rc = finish_round(ctx, ctx->h_ctrl, round, target, ncomp, S)) return rc;
         ++round;
     }
@@ -2179,6 +2183,7 @@ int job_advance(emst_ctx* ctx, Job& j) {
         return EMST_OK;
     case kPhRound: {
         if (j.round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
+        j.S.queries_round[j.round] = uses_qlist(j.variant, j.round) ? (int64_t)h->qcount : n;
         if (int rc = finish_round(ctx, h, j.round, 1, j.ncomp, j.S)) return rc;
         ++j.round;
         if (j.ncomp == 1) {
