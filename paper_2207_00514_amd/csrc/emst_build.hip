@@ -519,6 +519,11 @@ constexpr int kRunLds = kRunTile + kRunTile / 16 + 8;
 
 static inline int run_tiles(int64_t n) { return (int)((n + kRunTile - 1) / kRunTile); }
 
+// LDS hash table of the bound pass (k_round_prep), in the run arrays
+constexpr int kBoundHashBits = 11;
+constexpr int kBoundHash = 1 << kBoundHashBits;
+static_assert(kBoundHash <= kRunLds, "the bound hash fits in the run arrays");
+
 // LDS slot of tile-local index x: one pad word per 16 keeps the
 // consecutive positions of one thread in distinct banks.
 __device__ __forceinline__ int run_lds(int x) { return x + (x >> 4); }
@@ -767,19 +772,57 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
                 v[q] = min(v[q], fbits(fmaxf(fmaxf(ck, crr), sqdist<DIM>(pp, r))));
         }
     }
+    if constexpr (FIRST) {
 #pragma unroll
-    for (int q = 0; q < kRunPer; ++q) {
-        const int x = q * 256 + tid;
-        const int64_t k = base + x;
-        if (FIRST) {
+        for (int q = 0; q < kRunPer; ++q) {
+            const int64_t k = base + q * 256 + tid;
             if (k < n) ub[k] = v[q];
-            continue;
         }
-        if (base + q * 256 >= n) break;  // uniform over the workgroup
-        const uint32_t lab = k < n ? s_lab[run_lds(x + 1)] : kNone;
-        bool run_end;
-        const uint32_t m = wave_seg_min<uint32_t>(lab, v[q], &run_end);
-        if (k < n && run_end && m != kInfBits && m < load_relaxed(&ub[lab])) atomicMin(&ub[lab], m);
+    } else {
+        // Later rounds: the runs of a wave combine first (segmented min over the
+        // lanes), then the tile's components combine in an LDS hash table (the
+        // run-start and run-end arrays are free by now), so a component gets
+        // one global atomic per tile instead of one per run.  A full probe
+        // sequence falls back to the global atomic.
+        uint32_t* h_lab = s_rs;
+        uint32_t* h_val = s_re;
+        __syncthreads();
+        for (int e = tid; e < kBoundHash; e += 256) {
+            h_lab[e] = kNone;
+            h_val[e] = kInfBits;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) {
+            const int x = q * 256 + tid;
+            const int64_t k = base + x;
+            if (base + q * 256 < n) {  // uniform over the workgroup
+                const uint32_t lab = k < n ? s_lab[run_lds(x + 1)] : kNone;
+                bool run_end;
+                const uint32_t m = wave_seg_min<uint32_t>(lab, v[q], &run_end);
+                if (k < n && run_end && m != kInfBits) {
+                    uint32_t h = (lab * 2654435761u) >> (32 - kBoundHashBits);
+                    bool placed = false;
+                    for (int probe = 0; probe < 8; ++probe) {
+                        const uint32_t old = atomicCAS(&h_lab[h], kNone, lab);
+                        if (old == kNone || old == lab) {
+                            atomicMin(&h_val[h], m);
+                            placed = true;
+                            break;
+                        }
+                        h = (h + 1) & (kBoundHash - 1);
+                    }
+                    if (!placed && m < load_relaxed(&ub[lab])) atomicMin(&ub[lab], m);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < kBoundHash; e += 256) {
+            const uint32_t lab = h_lab[e];
+            if (lab == kNone) continue;
+            const uint32_t m = h_val[e];
+            if (m < load_relaxed(&ub[lab])) atomicMin(&ub[lab], m);
+        }
     }
 }
 
