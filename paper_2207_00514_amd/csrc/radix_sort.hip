@@ -22,13 +22,17 @@
 namespace emst {
 
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 8;
-constexpr int kRsTile = kRsThreads * kRsItems;
 constexpr int kRsWaves = kRsThreads / 64;
+// Items per thread of a tile: 8 for small sorts, 16 (longer runs of equal
+// digits per tile, so longer write segments; fewer resident blocks) from
+// kRsBigN keys on, where that measures faster.
+constexpr int64_t kRsBigN = (int64_t)1 << 23;
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void rs_upsweep(const uint64_t* __restrict__ keys, int64_t n,
                                                          int shift, int64_t tiles_per_block,
                                                          uint32_t* __restrict__ hist, int nb) {
+    constexpr int kRsTile = kRsThreads * ITEMS;
     __shared__ uint32_t h[kRsWaves][256];
     const int t = threadIdx.x, w = t / 64;
     for (int k = t; k < kRsWaves * 256; k += kRsThreads) (&h[0][0])[k] = 0;
@@ -77,6 +81,7 @@ __global__ __launch_bounds__(1024) void rs_rowscan(uint32_t* __restrict__ hist, 
     if (t == 1023) row_total[d] = incl;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
                                                            uint64_t* __restrict__ kout,
@@ -84,6 +89,8 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
                                                            int64_t tiles_per_block,
                                                            const uint32_t* __restrict__ hist, int nb,
                                                            const uint32_t* __restrict__ row_total) {
+    constexpr int kRsItems = ITEMS;
+    constexpr int kRsTile = kRsThreads * ITEMS;
     __shared__ uint32_t gbase[256];   // running global start of every digit for this block
     __shared__ uint32_t lstart[256];  // tile-local start of every digit
     __shared__ uint32_t wsum[kRsWaves];
@@ -201,13 +208,25 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
     }
 }
 
+static int rs_items(int64_t n) { return n >= kRsBigN ? 16 : 8; }
+
 RadixPlan radix_plan(int64_t n) {
     RadixPlan p;
-    const int64_t tiles = (n + kRsTile - 1) / kRsTile;
+    const int64_t tile = (int64_t)kRsThreads * rs_items(n);
+    const int64_t tiles = (n + tile - 1) / tile;
     p.blocks = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), kRadixMaxBlocks);
     p.tiles_per_block = (tiles + p.blocks - 1) / p.blocks;
     if (p.tiles_per_block < 1) p.tiles_per_block = 1;
     return p;
+}
+
+template <int ITEMS>
+static void rs_pass(hipStream_t stream, const RadixPlan& p, const uint64_t* ka, const uint32_t* va, uint64_t* kb,
+                    uint32_t* vb, uint32_t* hist, int64_t n, int shift) {
+    rs_upsweep<ITEMS><<<p.blocks, kRsThreads, 0, stream>>>(ka, n, shift, p.tiles_per_block, hist, p.blocks);
+    rs_rowscan<<<256, 1024, 0, stream>>>(hist, p.blocks, hist + 256 * kRadixMaxBlocks);
+    rs_downsweep<ITEMS><<<p.blocks, kRsThreads, 0, stream>>>(ka, va, kb, vb, n, shift, p.tiles_per_block, hist,
+                                                             p.blocks, hist + 256 * kRadixMaxBlocks);
 }
 
 hipError_t radix_sort_pairs(hipStream_t stream, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
@@ -218,10 +237,8 @@ hipError_t radix_sort_pairs(hipStream_t stream, uint64_t* k0, uint32_t* v0, uint
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     for (int q = 0; q < nshifts; ++q) {
-        rs_upsweep<<<p.blocks, kRsThreads, 0, stream>>>(ka, n, shifts[q], p.tiles_per_block, hist, p.blocks);
-        rs_rowscan<<<256, 1024, 0, stream>>>(hist, p.blocks, hist + 256 * kRadixMaxBlocks);
-        rs_downsweep<<<p.blocks, kRsThreads, 0, stream>>>(ka, va, kb, vb, n, shifts[q], p.tiles_per_block,
-                                                           hist, p.blocks, hist + 256 * kRadixMaxBlocks);
+        if (rs_items(n) == 16) rs_pass<16>(stream, p, ka, va, kb, vb, hist, n, shifts[q]);
+        else rs_pass<8>(stream, p, ka, va, kb, vb, hist, n, shifts[q]);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
