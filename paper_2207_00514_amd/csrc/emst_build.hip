@@ -1809,8 +1809,13 @@ int read_ctrl(emst_ctx* ctx, Ctrl* ctrl, hipStream_t st) {
 // cloud is finished) becomes a root.
 // Variant 13 searches from a query list from the third round on (the
 // second keeps nothing: in the first round every point joins its nearest
-// neighbour's component).
-static inline bool uses_qlist(int variant, int round) { return variant == 13 && round >= 2; }
+// neighbour's component).  Below kQlistMinN points the list's three extra
+// launches per round cost more than the idle lanes they save, and the
+// points skip inside the traversal instead.
+constexpr int64_t kQlistMinN = (int64_t)1 << 18;
+static inline bool uses_qlist(int variant, int round, int64_t n) {
+    return variant == 13 && round >= 2 && n >= kQlistMinN;
+}
 
 // One Boruvka round, enqueued on st (no host wait).
 template <int DIM>
@@ -1831,7 +1836,7 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     ta.first = round == 0;
     // variant 13: only the points whose last result no longer holds search
     ta.qlist = nullptr;
-    if (uses_qlist(variant, round)) {
+    if (uses_qlist(variant, round, n)) {
         k_reuse_mark<<<nt, 256, 0, st>>>(b.labels, b.ub, b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag,
                                          b.qcnt, n, b.ctrl);
         k_qlist_scan<<<1, 1024, 0, st>>>(b.qcnt, nt, b.qoff, b.ctrl);
@@ -1892,7 +1897,7 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
         if (int rc = enqueue_round<DIM>(ctx, b, ta, n, round, height, variant, cloud_of, target, prof, st))
             return rc;
         if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-        S.queries_round[round] = uses_qlist(variant, round) ? (int64_t)ctx->h_ctrl->qcount : n;
+        S.queries_round[round] = uses_qlist(variant, round, n) ? (int64_t)ctx->h_ctrl->qcount : n;
         if (int rc = finish_round(ctx, ctx->h_ctrl, round, target, ncomp, S)) return rc;
         ++round;
     }
@@ -2226,7 +2231,7 @@ int job_advance(emst_ctx* ctx, Job& j) {
         return EMST_OK;
     case kPhRound: {
         if (j.round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
-        j.S.queries_round[j.round] = uses_qlist(j.variant, j.round) ? (int64_t)h->qcount : n;
+        j.S.queries_round[j.round] = uses_qlist(j.variant, j.round, n) ? (int64_t)h->qcount : n;
         if (int rc = finish_round(ctx, h, j.round, 1, j.ncomp, j.S)) return rc;
         ++j.round;
         if (j.ncomp == 1) {

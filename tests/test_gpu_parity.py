@@ -153,7 +153,7 @@ def test_errors(ctx):
 def test_variants_counting_and_repeats_agree(ctx):
     pts = W.clustered3d(60_000, seed=9)
     ref = oracle.kdboruvka(pts, threads=8)
-    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11):
+    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13):
         for counting in (False, True):
             ctx.set_counting(counting)
             print(f"variant={variant} counting={counting}", flush=True)
@@ -276,14 +276,14 @@ def test_radix_sort(ctx):
 def test_uniform2d_10k(ctx):
     pts = W.uniform2d()
     ref = oracle.prim(pts)
-    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11):
+    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13):
         assert_same(run(ctx, pts, variant), ref, f"uniform2d_10k v{variant}")
 
 
 def test_clustered3d_2m(ctx):
     pts = W.clustered3d()
     ref = oracle.kdboruvka(pts, threads=16)
-    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11):
+    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13):
         print(f"clustered3d_2m variant={variant}", flush=True)
         assert_same(run(ctx, pts, variant), ref, f"clustered3d_2m v{variant}")
 
