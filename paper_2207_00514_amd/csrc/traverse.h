@@ -762,7 +762,13 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             const Rec<DIM> r = a.recs[node];
             Child<DIM> c0, c1;
             unpack<DIM>(r, c0, c1);
-            {
+            if (a.first) {
+                // first round: every leaf is its own component, labelled by
+                // its sorted position (the left leaf of record k is k, the
+                // right one k + 1), and every internal node holds several
+                c0.lab = (c0.ref & kLeafFlag) ? node : kInvalid;
+                c1.lab = (c1.ref & kLeafFlag) ? node + 1u : kInvalid;
+            } else {
                 const uint2 L = a.lab2[node];
                 c0.lab = L.x;
                 c1.lab = L.y;
