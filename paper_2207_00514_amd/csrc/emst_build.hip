@@ -981,8 +981,9 @@ __global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ ca
 __global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__ labels,
                                                     const uint32_t* __restrict__ pos,
                                                     const uint64_t* __restrict__ compkey,
-                                                    const uint32_t* __restrict__ compmax, uint32_t* succ,
-                                                    Ctrl* ctrl, int64_t n, bool allow_isolated) {
+                                                    const uint32_t* __restrict__ compmax,
+                                                    const uint32_t* __restrict__ orig, uint32_t* succ,
+                                                    Ctrl* ctrl, int64_t n, bool allow_isolated, bool first) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n || ctrl->done || labels[c] != (uint32_t)c) return;
     const uint64_t key = compkey[c];
@@ -994,6 +995,14 @@ __global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__
         return;
     }
     const uint32_t u = (uint32_t)(key & 0xFFFFFFFFu);
+    if (first) {
+        // first round: component c is the point at position c alone, and a
+        // point's label is its position
+        const uint32_t own = orig[c];
+        if (u != own && v != own) atomicOr(&ctrl->error, kErrNoEdge);
+        succ[c] = pos[u == own ? v : u];
+        return;
+    }
     const uint32_t lu = labels[pos[u]], lv = labels[pos[v]];
     if (lu != (uint32_t)c && lv != (uint32_t)c) atomicOr(&ctrl->error, kErrNoEdge);
     succ[c] = (lu == (uint32_t)c) ? lv : lu;
@@ -1850,8 +1859,8 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     if (round > 0)
         k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
                                                b.ctrl);
-    k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.succ, b.ctrl, n,
-                                              cloud_of != nullptr);
+    k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.orig, b.succ, b.ctrl, n,
+                                              cloud_of != nullptr, round == 0);
     const int mp_blocks = (int)std::min<unsigned>(grid_for(n), kPartBlocks);
     k_merge_parent<<<mp_blocks, 256, 0, st>>>(b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud,
                                               reinterpret_cast<uint2*>(b.bpart), b.ctrl, n);
