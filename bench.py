@@ -43,8 +43,8 @@ TRAFFIC_SOURCES = ("traverse.h", "emst_common.h", "emst_kernels.h")
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 MEASURED_TRAFFIC = {
     # (workload, variant, source hash): (FETCH_SIZE KiB, WRITE_SIZE KiB, TCC hit fraction, profile)
-    ("clustered3d_2m", 13, "b71efd74f8dce137"):
-        (80808.0, 17174.2, 0.902, "profiles/k_traverse_fast_clustered3d_2m.md"),
+    ("clustered3d_2m", 13, "385214691b93f069"):
+        (81059.9, 17169.5, 0.889, "profiles/k_traverse_fast_clustered3d_2m.md"),
 }
 
 
