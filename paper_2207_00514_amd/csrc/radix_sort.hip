@@ -120,6 +120,21 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
     const int64_t first_tile = (int64_t)blockIdx.x * tiles_per_block;
     const int64_t num_tiles = (n + kRsTile - 1) / kRsTile;
     const int64_t last_tile = min(num_tiles, first_tile + tiles_per_block);
+    // the next tile's items are loaded while the current one is ranked and
+    // scattered
+    uint64_t nkey[kRsItems];
+    uint32_t nval[kRsItems];
+    auto load_tile = [&](int64_t tile) {
+        const int64_t tb = tile * kRsTile;
+#pragma unroll
+        for (int s = 0; s < kRsItems; ++s) {
+            const int64_t idx = tb + (int64_t)s * kRsThreads + t;
+            const bool in = tile < last_tile && idx < n;
+            nkey[s] = in ? kin[idx] : 0ull;
+            nval[s] = in ? vin[idx] : 0u;
+        }
+    };
+    load_tile(first_tile);
     for (int64_t tile = first_tile; tile < last_tile; ++tile) {
         for (int k = t; k < kRsItems * kRsWaves * 256; k += kRsThreads) (&cnt[0][0][0])[k] = 0;
         __syncthreads();
@@ -132,10 +147,11 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
         for (int s = 0; s < kRsItems; ++s) {
             const int64_t idx = tb + (int64_t)s * kRsThreads + t;
             ok[s] = idx < n;
-            key[s] = ok[s] ? kin[idx] : 0ull;
-            val[s] = ok[s] ? vin[idx] : 0u;
+            key[s] = nkey[s];
+            val[s] = nval[s];
             dig[s] = (uint32_t)(key[s] >> shift) & 255u;
         }
+        load_tile(tile + 1);
 #pragma unroll
         for (int s = 0; s < kRsItems; ++s) {
             uint64_t peers = __ballot(ok[s]);
