@@ -746,10 +746,11 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
         const int x = q * 256 + tid;
         const int64_t k = base + x;
         v[q] = kInfBits;
-        if (k < n) {
+        const uint32_t lab = s_lab[run_lds(x + 1)];
+        const uint32_t llab = s_lab[run_lds(x)], rlab = s_lab[run_lds(x + 2)];
+        // only a position next to another component reads coordinates
+        if (k < n && (llab != lab || rlab != lab)) {
             const int64_t kl = k > 0 ? k - 1 : k, kr = k + 1 < n ? k + 1 : k;
-            const uint32_t lab = s_lab[run_lds(x + 1)];
-            const uint32_t llab = s_lab[run_lds(x)], rlab = s_lab[run_lds(x + 2)];
             uint32_t cl = 0u, lcl = 0u, rcl = 0u;
             if (cloud_of) {
                 cl = cloud_of[k];
