@@ -323,13 +323,29 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         set_child_ref<DIM>(&recs[parent], side, self_ref);
         if (leaf) leaf_parent[i] = (parent << 1) | (uint32_t)side;
         else node_parent[self] = (parent << 1) | (uint32_t)side;
-        const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
-        const uint64_t other = atomicExch((unsigned long long*)&exch[parent], (unsigned long long)mine);
-        if (other == ~0ull) return;
-        const int64_t oend = (int64_t)(other >> 32);
-        if (left_child) r = oend;
-        else l = oend;
-        h = max(h, (uint32_t)(other & 0xFFFFFFFFu)) + 1u;
+        // Two sibling leaves: node k holds leaves k and k+1 exactly when
+        // leaf k is a left child and leaf k+1 a right child.  Both leaf
+        // threads see this from the split bits of adjacent pairs (which
+        // always differ), so the left one continues and the right one stops
+        // with no exchange.
+        bool pair = false;
+        if (leaf) {
+            if (left_child) pair = (i + 1 == n - 1) || split_bit(codes, i + 1) > split_bit(codes, i);
+            else pair = (i - 1 == 0) || split_bit(codes, i - 1) < split_bit(codes, i - 2);
+            if (pair && !left_child) return;
+        }
+        if (pair) {
+            r = i + 1;
+            h = 1u;
+        } else {
+            const uint64_t mine = ((uint64_t)(left_child ? l : r) << 32) | h;
+            const uint64_t other = atomicExch((unsigned long long*)&exch[parent], (unsigned long long)mine);
+            if (other == ~0ull) return;
+            const int64_t oend = (int64_t)(other >> 32);
+            if (left_child) r = oend;
+            else l = oend;
+            h = max(h, (uint32_t)(other & 0xFFFFFFFFu)) + 1u;
+        }
         self = parent;
         self_ref = parent;
         leaf = false;
