@@ -361,10 +361,13 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
     }
 }
 
-// A leaf's box is its point, stored in its parent's record.
+// A leaf's box is its point, stored in its parent's record.  The left leaf
+// of two sibling leaves (a node of height 1) also stores their union in
+// that node's parent's record, so the level fit starts at height 2.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ spts,
-                                                    const uint32_t* __restrict__ leaf_parent, int64_t n,
+                                                    const uint32_t* __restrict__ leaf_parent,
+                                                    const uint32_t* __restrict__ node_parent, int64_t n,
                                                     Rec<DIM>* recs) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -373,6 +376,18 @@ __global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ sp
     for (int k = 0; k < DIM; ++k) p[k] = spts[i * DIM + k];
     const uint32_t link = leaf_parent[i];
     set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), p, p);
+    if ((link & 1u) == 0u && i + 1 < n && leaf_parent[i + 1] == (link | 1u)) {
+        const uint32_t up = node_parent[link >> 1];
+        if (up == kNone) return;
+        float lo[DIM], hi[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const float q = spts[(i + 1) * DIM + k];
+            lo[k] = fminf(p[k], q);
+            hi[k] = fmaxf(p[k], q);
+        }
+        set_child_box<DIM>(&recs[up >> 1], (int)(up & 1u), lo, hi);
+    }
 }
 
 // Nodes grouped by height: keys = height, values = node id, for one stable
@@ -1992,7 +2007,7 @@ template <int DIM>
 int build_hierarchy(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hipStream_t st) {
     k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, b.orig, n, b.recs, b.leaf_parent, b.node_parent, b.exch, b.rlo,
                                               b.rhi, b.height, b.ctrl);
-    k_fit_leaves<DIM><<<grid_for(n), 256, 0, st>>>(b.spts, b.leaf_parent, n, b.recs);
+    k_fit_leaves<DIM><<<grid_for(n), 256, 0, st>>>(b.spts, b.leaf_parent, b.node_parent, n, b.recs);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
 }
@@ -2021,7 +2036,8 @@ int fit_levels(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, ui
     uint32_t* starts = b.hist;  // the sort's histogram is free again
     k_level_starts<<<grid_for(m), 256, 0, st>>>(skeys, m, starts);
     const unsigned fgrid = std::min<unsigned>(grid_for(m), 1024);
-    for (uint32_t h = 1; h < H; ++h)
+    // height 1 (two leaves) was fitted with the leaves
+    for (uint32_t h = 2; h < H; ++h)
         k_fit_level<DIM><<<fgrid, 256, 0, st>>>(ids, starts, h, b.node_parent, b.recs);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
