@@ -714,7 +714,7 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
     for (int x = tid; x < kRunTile + 2; x += 256) {
         int64_t p = base + x - 1;
         p = p < 0 ? 0 : (p >= n ? n - 1 : p);
-        s_lab[run_lds(x)] = labels[p];
+        s_lab[run_lds(x)] = FIRST ? (uint32_t)p : labels[p];  // first round: a point's label is its position
     }
     __syncthreads();
     if (!FIRST) {
