@@ -176,12 +176,40 @@ struct MortonParams {
     double qmax;
 };
 
+// Quantisation of the scene box [lo, hi] to `bits` bits per axis.  Host and
+// device evaluate the same IEEE double operations, so a kernel that derives
+// the parameters from the control block gets the ones the host derives from
+// its mirror.
+__host__ __device__ inline MortonParams morton_params(const float* lo, const float* hi, int dim, int bits) {
+    MortonParams mp;
+    mp.qmax = (double)((1ull << bits) - 1ull);
+    for (int k = 0; k < 3; ++k) {
+        mp.lo[k] = k < dim ? (double)lo[k] : 0.0;
+        const double ext = k < dim ? (double)hi[k] - (double)lo[k] : 0.0;
+        mp.scale[k] = ext > 0.0 ? mp.qmax / ext : 0.0;
+    }
+    return mp;
+}
+
+__host__ __device__ inline MortonParams morton_params_of(const Ctrl& c, int dim) {
+    float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < dim; ++k) {
+        lo[k] = ord_dec(c.bb_min[k]);
+        hi[k] = ord_dec(c.bb_max[k]);
+    }
+    return morton_params(lo, hi, dim, dim == 3 ? 21 : 32);
+}
+
 // Z-curve code of every point: 21 bits per coordinate in 3D (63-bit code),
 // 32 bits per coordinate in 2D (64-bit code).  The quantisation only shapes
-// the tree; the EMST does not depend on it.
+// the tree; the EMST does not depend on it.  With `box` set, the parameters
+// come from the scene box in that control block instead of `mp`, so the
+// codes need no host read-back of the box.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, int64_t n, MortonParams mp,
-                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                const Ctrl* __restrict__ box, uint64_t* __restrict__ keys,
+                                                uint32_t* __restrict__ vals) {
+    if (box) mp = morton_params_of(*box, DIM);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t q[DIM];
 #pragma unroll
@@ -1734,17 +1762,6 @@ bool extent_ok(const float* lo, const float* hi, int dim) {
     return isfinite((float)s);
 }
 
-MortonParams morton_params(const float* lo, const float* hi, int dim, int bits) {
-    MortonParams mp;
-    mp.qmax = (double)((1ull << bits) - 1ull);
-    for (int k = 0; k < 3; ++k) {
-        mp.lo[k] = k < dim ? (double)lo[k] : 0.0;
-        const double ext = k < dim ? (double)hi[k] - (double)lo[k] : 0.0;
-        mp.scale[k] = ext > 0.0 ? mp.qmax / ext : 0.0;
-    }
-    return mp;
-}
-
 // The record labels of arbitrary labels (no bounds).
 hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_part, uint32_t* run_carry, const uint32_t* rlo,
                             const uint32_t* rhi, uint2* lab2, int64_t n, Ctrl* ctrl, hipStream_t st) {
@@ -2079,7 +2096,7 @@ void finish_stats(emst_ctx* ctx, emst_stats& S) {
 // core distances of k_pts (k_pts = 1 gives zero cores, hence the EMST);
 // core_out (nullable) receives the squared core distances in input order;
 // core_only stops after them.
-enum JobPhase { kPhBox, kPhTree, kPhRank, kPhFit, kPhRound, kPhFinal, kPhDone };
+enum JobPhase { kPhTree, kPhRank, kPhFit, kPhRound, kPhFinal, kPhDone };
 
 struct Job {
     int dim = 3;
@@ -2094,7 +2111,7 @@ struct Job {
     bool core_only = false;
     Ctrl* h = nullptr;     // pinned host mirror of this job's control block
     bool prof = false;     // record the context's phase and traversal events
-    int phase = kPhBox;
+    int phase = kPhTree;
     int round = 0;
     int64_t ncomp = 0;
     bool ranks = false;
@@ -2148,13 +2165,14 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
     Bufs<DIM> b = carve<DIM>(j.ws, L);
     hipEvent_t* E = ctx->ev;  // E[0..3] phases, E[8 + 2r], E[9 + 2r] traversal of round r
     switch (j.phase) {
-    case kPhBox:  // validation + scene box
+    case kPhTree: {  // validation + scene box, Morton codes, sort, hierarchy
         if (j.prof) HIP_TRY(hipEventRecord(E[0], st));
         k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
         HIP_TRY(launch_bbox<DIM>(j.pts, n, b.bpart, b.ctrl, st));
-        break;
-    case kPhTree: {  // Morton codes, sort, hierarchy
-        k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(j.pts, n, j.mp, b.k0, b.v0);
+        // The codes take the box from the control block.  A cloud that fails
+        // validation (read back after this phase) still yields codes of some
+        // box: any codes make a valid hierarchy, and the job stops there.
+        k_morton<DIM><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(j.pts, n, j.mp, b.ctrl, b.k0, b.v0);
         const int shifts[8] = {0, 8, 16, 24, 32, 40, 48, 56};
         HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, 8, &j.codes_in1));
         const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
@@ -2241,20 +2259,19 @@ int job_advance(emst_ctx* ctx, Job& j) {
     const Ctrl* h = j.h;
     const int64_t n = j.n;
     switch (j.phase) {
-    case kPhBox: {
-        if (h->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
-        float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        for (int k = 0; k < DIM; ++k) {
-            lo[k] = ord_dec(h->bb_min[k]);
-            hi[k] = ord_dec(h->bb_max[k]);
-        }
-        if (!extent_ok(lo, hi, DIM)) return fail(ctx, EMST_ERANGE, "squared extent of the cloud overflows float32");
-        j.mp = morton_params(lo, hi, DIM, DIM == 3 ? 21 : 32);
-        j.phase = kPhTree;
-        return EMST_OK;
-    }
     case kPhTree:
     case kPhRank:
+        if (j.phase == kPhTree) {
+            if (h->nonfinite) return fail(ctx, EMST_ENONFINITE, "non-finite coordinate");
+            float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            for (int k = 0; k < DIM; ++k) {
+                lo[k] = ord_dec(h->bb_min[k]);
+                hi[k] = ord_dec(h->bb_max[k]);
+            }
+            if (!extent_ok(lo, hi, DIM))
+                return fail(ctx, EMST_ERANGE, "squared extent of the cloud overflows float32");
+            j.mp = morton_params_of(*h, DIM);  // the parameters k_morton derived on the device
+        }
         if (int rc = check_hierarchy(ctx, h, n)) return rc;
         if (j.phase == kPhTree && (int64_t)h->dup_codes * 64 > n) {
             j.ranks = true;
@@ -2961,7 +2978,7 @@ extern "C" int emst_test_tree_boxes(emst_ctx* ctx, const float* d_points, int64_
     float lo[3], hi[3];
     for (int k = 0; k < 3; ++k) { lo[k] = ord_dec(ctx->h_ctrl->bb_min[k]); hi[k] = ord_dec(ctx->h_ctrl->bb_max[k]); }
     const MortonParams mp = morton_params(lo, hi, 3, 21);
-    k_morton<3><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(d_points, n, mp, b.k0, b.v0);
+    k_morton<3><<<std::min<unsigned>(grid_for(n), 1024), 256, 0, st>>>(d_points, n, mp, nullptr, b.k0, b.v0);
     int shifts[8];
     for (int q = 0; q < 8; ++q) shifts[q] = 8 * q;
     int in1 = 0;
