@@ -206,8 +206,10 @@ void emst_solver_destroy(emst_solver *solver);
 int emst_solver_admit(emst_solver *solver, const float *d_points, int64_t n, int32_t dim, int64_t tag,
                       void *stream, int32_t *slot);
 
-/* One phase for every running request, one wait on `stream`.  *n_finished
- * (nullable) = requests that finished or failed in this step. */
+/* One phase for every running request; returns when all of them are done.
+ * The requests run on a few streams of the solver (default priority),
+ * after the work already queued on `stream`.  *n_finished (nullable) =
+ * requests that finished or failed in this step. */
 int emst_solver_step(emst_solver *solver, void *stream, int32_t *n_finished);
 
 /* *state: 0 free, 1 running, 2 finished, < 0 failed with that status;

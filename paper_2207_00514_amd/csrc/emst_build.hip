@@ -2614,6 +2614,11 @@ extern "C" int emst_build_mreach(emst_ctx* ctx, const float* d_points, int64_t n
 // running request by one phase (its tree, then one Boruvka round per step,
 // then its edge order) with one wait for all of them, so a request admitted
 // between two steps starts at the next one while the others keep going.
+// The requests of a step are spread over a few streams of the solver, so
+// the kernels of small requests, which fill a fraction of the GPU each,
+// run side by side.
+
+constexpr int kSolverStreams = 4;
 
 struct SolverSlot {
     int state = 0;          // 0 free, 1 running, 2 done, < 0: failed with that status
@@ -2631,6 +2636,8 @@ struct emst_solver {
     size_t budget = 0;
     std::vector<SolverSlot> slots;
     Ctrl* h = nullptr;      // pinned mirrors, one per slot
+    hipStream_t lane[kSolverStreams] = {};
+    hipEvent_t fork = nullptr;  // orders the lanes after the caller's stream
 };
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -2640,6 +2647,8 @@ extern "C" size_t emst_solver_slot_bytes(int64_t n, int dim) {
     const size_t m = (size_t)(n > 1 ? n - 1 : 0);
     return a256((size_t)n * dim * 4) + emst_workspace_bytes(n > 1 ? n : 2, dim) + a256(m * 8) + 2 * a256(m * 4);
 }
+
+extern "C" void emst_solver_destroy(emst_solver* sv);
 
 extern "C" int emst_solver_create(emst_ctx* ctx, void* d_budget, size_t budget_bytes, int32_t max_slots,
                                   emst_solver** out) {
@@ -2652,10 +2661,14 @@ extern "C" int emst_solver_create(emst_ctx* ctx, void* d_budget, size_t budget_b
     sv->base = (char*)d_budget;
     sv->budget = budget_bytes;
     sv->slots.resize(max_slots);
-    if (hipSetDevice(ctx->device) != hipSuccess ||
-        hipHostMalloc((void**)&sv->h, sizeof(Ctrl) * (size_t)max_slots, hipHostMallocDefault) != hipSuccess) {
-        delete sv;
-        return fail(ctx, EMST_EHIP, "hipHostMalloc failed");
+    bool ok = hipSetDevice(ctx->device) == hipSuccess &&
+              hipHostMalloc((void**)&sv->h, sizeof(Ctrl) * (size_t)max_slots, hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&sv->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < kSolverStreams; ++k)
+        ok = hipStreamCreateWithFlags(&sv->lane[k], hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        emst_solver_destroy(sv);
+        return fail(ctx, EMST_EHIP, "solver set-up failed");
     }
     *out = sv;
     return EMST_OK;
@@ -2663,6 +2676,12 @@ extern "C" int emst_solver_create(emst_ctx* ctx, void* d_budget, size_t budget_b
 
 extern "C" void emst_solver_destroy(emst_solver* sv) {
     if (!sv) return;
+    for (hipStream_t& l : sv->lane)
+        if (l) {
+            (void)hipStreamSynchronize(l);
+            (void)hipStreamDestroy(l);
+        }
+    if (sv->fork) (void)hipEventDestroy(sv->fork);
     if (sv->h) (void)hipHostFree(sv->h);
     delete sv;
 }
@@ -2728,12 +2747,17 @@ extern "C" int emst_solver_step(emst_solver* sv, void* stream, int32_t* n_finish
     if (n_finished) *n_finished = 0;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // the lanes start after what the caller's stream holds (admitted points)
+    HIP_TRY(hipEventRecord(sv->fork, st));
+    for (hipStream_t l : sv->lane) HIP_TRY(hipStreamWaitEvent(l, sv->fork, 0));
     std::vector<int> go;
+    int next_lane = 0;
     for (int s = 0; s < (int)sv->slots.size(); ++s) {
         SolverSlot& q = sv->slots[s];
         if (q.state != 1) continue;
         if (q.job.prof) q.job.prof = false;
-        const int rc = q.dim == 3 ? job_enqueue<3>(ctx, q.job, st) : job_enqueue<2>(ctx, q.job, st);
+        hipStream_t l = sv->lane[next_lane++ % kSolverStreams];
+        const int rc = q.dim == 3 ? job_enqueue<3>(ctx, q.job, l) : job_enqueue<2>(ctx, q.job, l);
         if (rc) {
             q.state = rc;
             q.err = ctx->err;
@@ -2741,7 +2765,11 @@ extern "C" int emst_solver_step(emst_solver* sv, void* stream, int32_t* n_finish
             go.push_back(s);
         }
     }
-    const hipError_t w = hipStreamSynchronize(st);
+    hipError_t w = hipSuccess;
+    for (hipStream_t l : sv->lane) {
+        const hipError_t e = hipStreamSynchronize(l);
+        if (w == hipSuccess) w = e;
+    }
     if (w != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(w));
     int done = 0;
     for (int s : go) {
