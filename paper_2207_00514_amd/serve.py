@@ -52,7 +52,7 @@ class Server:
     """`budget_bytes` is the device memory all workers together may use for
     inputs, outputs and workspaces; each worker gets an equal share."""
 
-    def __init__(self, workers: int = 2, budget_bytes: int = 8 << 30, max_batch: int = 256,
+    def __init__(self, workers: int = 4, budget_bytes: int = 8 << 30, max_batch: int = 256,
                  device: int = 0):
         import torch
         self.device = device
