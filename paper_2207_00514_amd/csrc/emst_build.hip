@@ -1036,16 +1036,29 @@ __global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ ca
     if (key == compkey[c]) atomicMin(&compmax[c], max(oi, j));
 }
 
+// The components of a round, as a list: k_merge_parent leaves the roots it
+// finds (the components of the next round) in its workgroup's segment of
+// `out`, `cap` entries from cap * blockIdx.x on, and their number in
+// cnt_out[blockIdx.x].  From the second round on the merge kernels run with
+// that many workgroups and visit the entries of `in` (the list of the round
+// before) instead of testing labels[c] == c at every position.  Order inside
+// a segment does not matter: every component's work is independent.
+struct RootList {
+    const uint32_t* in;
+    const uint32_t* cnt_in;
+    uint32_t* out;
+    uint32_t* cnt_out;
+    int64_t cap;
+};
+
 // Merge, step 1: successor component of every component (the component at
 // the other end of its shortest outgoing edge).
-__global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__ labels,
-                                                    const uint32_t* __restrict__ pos,
-                                                    const uint64_t* __restrict__ compkey,
-                                                    const uint32_t* __restrict__ compmax,
-                                                    const uint32_t* __restrict__ orig, uint32_t* succ,
-                                                    Ctrl* ctrl, int64_t n, bool allow_isolated, bool first) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n || ctrl->done || labels[c] != (uint32_t)c) return;
+__device__ __forceinline__ void merge_succ_one(int64_t c, const uint32_t* __restrict__ labels,
+                                               const uint32_t* __restrict__ pos,
+                                               const uint64_t* __restrict__ compkey,
+                                               const uint32_t* __restrict__ compmax,
+                                               const uint32_t* __restrict__ orig, uint32_t* succ, Ctrl* ctrl,
+                                               bool allow_isolated, bool first) {
     const uint64_t key = compkey[c];
     const uint32_t v = compmax[c];
     if (key == kKeyMax || v == kNone) {
@@ -1068,28 +1081,59 @@ __global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__
     succ[c] = (lu == (uint32_t)c) ? lv : lu;
 }
 
+// First round: one thread per position.  Later rounds: the root list.
+__global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__ labels,
+                                                    const uint32_t* __restrict__ pos,
+                                                    const uint64_t* __restrict__ compkey,
+                                                    const uint32_t* __restrict__ compmax,
+                                                    const uint32_t* __restrict__ orig, uint32_t* succ,
+                                                    Ctrl* ctrl, int64_t n, bool allow_isolated, bool first,
+                                                    RootList rl) {
+    if (ctrl->done) return;
+    if (first) {
+        const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (c < n && labels[c] == (uint32_t)c)
+            merge_succ_one(c, labels, pos, compkey, compmax, orig, succ, ctrl, allow_isolated, true);
+        return;
+    }
+    const uint32_t* seg = rl.in + rl.cap * blockIdx.x;
+    const int64_t cnt = rl.cnt_in[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
+        merge_succ_one(seg[i], labels, pos, compkey, compmax, orig, succ, ctrl, allow_isolated, false);
+}
+
 // Merge, step 2: the chains of successors end in a mutual pair (Section 2);
 // the smaller label of that pair becomes the root of the merged component
 // ("Merging components together").  Every other component emits its edge,
 // so a mutual pair contributes its shared edge once.  Roots reset their
 // per-component state for the next round.
+// With `first` the workgroups stride over every position (the segment of
+// workgroup b then has room for every position it visits); otherwise each
+// visits its segment of the root list.
 __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict__ labels,
                                                       const uint32_t* __restrict__ succ, uint32_t* par,
                                                       uint64_t* compkey, uint32_t* compmax, uint32_t* ub,
                                                       uint4* __restrict__ eud, uint2* __restrict__ part,
-                                                      const Ctrl* ctrl, int64_t n) {
+                                                      const Ctrl* ctrl, int64_t n, bool first, RootList rl) {
     if (ctrl->done) return;
     __shared__ uint32_t s_cnt[2];
     if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
     __syncthreads();
-    uint32_t roots = 0, emitted = 0;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        if (labels[c] != (uint32_t)c) continue;
+    uint32_t emitted = 0;
+    const uint32_t* seg_in = rl.in + rl.cap * blockIdx.x;
+    uint32_t* seg_out = rl.out + rl.cap * blockIdx.x;
+    const int64_t cnt = first ? 0 : rl.cnt_in[blockIdx.x];
+    const int64_t i0 = first ? (int64_t)blockIdx.x * blockDim.x + threadIdx.x : (int64_t)threadIdx.x;
+    const int64_t step = first ? (int64_t)gridDim.x * blockDim.x : (int64_t)blockDim.x;
+    const int64_t end = first ? n : cnt;
+    for (int64_t i = i0; i < end; i += step) {
+        const int64_t c = first ? i : (int64_t)seg_in[i];
+        if (first && labels[c] != (uint32_t)c) continue;
         const uint32_t s = succ[c];
         const bool root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
         par[c] = root ? (uint32_t)c : s;
         if (root) {
-            ++roots;
+            seg_out[atomicAdd(&s_cnt[0], 1u)] = (uint32_t)c;
             ub[c] = kInfBits;
             compkey[c] = kKeyMax;
             compmax[c] = kNone;
@@ -1102,27 +1146,20 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
             eud[c] = make_uint4((uint32_t)(key & 0xFFFFFFFFu), compmax[c], (uint32_t)(key >> 32), 0u);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        roots += __shfl_xor(roots, off);
-        emitted += __shfl_xor(emitted, off);
-    }
-    if (lane_id() == 0) {
-        if (roots) atomicAdd(&s_cnt[0], roots);
-        if (emitted) atomicAdd(&s_cnt[1], emitted);
-    }
+    for (int off = 32; off > 0; off >>= 1) emitted += __shfl_xor(emitted, off);
+    if (lane_id() == 0 && emitted) atomicAdd(&s_cnt[1], emitted);
     __syncthreads();
     // (new roots, emitted edges) of this workgroup; k_relabel adds them up
-    if (threadIdx.x == 0) part[blockIdx.x] = make_uint2(s_cnt[0], s_cnt[1]);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = make_uint2(s_cnt[0], s_cnt[1]);
+        rl.cnt_out[blockIdx.x] = s_cnt[0];
+    }
 }
 
 // Merge, step 3: pointer jumping towards the roots.  Concurrent updates only
 // ever replace a pointer by one of its ancestors, so any interleaving is
 // safe; the loop is capped and the relabel step finishes any remaining hops.
-__global__ __launch_bounds__(256) void k_merge_jump(const uint32_t* __restrict__ labels, uint32_t* par,
-                                                    int64_t n, int steps, const Ctrl* ctrl) {
-    if (ctrl->done) return;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n || labels[c] != (uint32_t)c) return;
+__device__ __forceinline__ void merge_jump_one(int64_t c, uint32_t* par, int steps) {
     uint32_t p = load_relaxed(&par[c]);
     for (int it = 0; it < steps; ++it) {
         const uint32_t pp = load_relaxed(&par[p]);
@@ -1130,6 +1167,22 @@ __global__ __launch_bounds__(256) void k_merge_jump(const uint32_t* __restrict__
         __hip_atomic_store(&par[c], pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         p = pp;
     }
+}
+
+// First round: one thread per position.  Later rounds: the root list of the
+// round (the components that k_merge_parent has just linked).
+__global__ __launch_bounds__(256) void k_merge_jump(const uint32_t* __restrict__ labels, uint32_t* par,
+                                                    int64_t n, int steps, const Ctrl* ctrl, bool first,
+                                                    RootList rl) {
+    if (ctrl->done) return;
+    if (first) {
+        const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (c < n && labels[c] == (uint32_t)c) merge_jump_one(c, par, steps);
+        return;
+    }
+    const uint32_t* seg = rl.in + rl.cap * blockIdx.x;
+    const int64_t cnt = rl.cnt_in[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) merge_jump_one(seg[i], par, steps);
 }
 
 // Merge, step 4: every point takes its component's root as its new label
@@ -1535,6 +1588,14 @@ struct BatchLayout {
 
 static BatchLayout make_batch_layout(int64_t n, int64_t clouds);
 
+// Root lists of the merge kernels: one segment per k_merge_parent
+// workgroup, with room for every position that workgroup strides over.
+static int root_list_blocks(int64_t n) { return (int)std::min<unsigned>(grid_for(n), kPartBlocks); }
+static int64_t root_list_cap(int64_t n) {
+    const int64_t stride = (int64_t)root_list_blocks(n) * 256;
+    return (n + stride - 1) / stride * 256;
+}
+
 static Layout make_layout(int64_t n, int dim) {
     Layout L;
     size_t o = 0;
@@ -1546,8 +1607,10 @@ static Layout make_layout(int64_t n, int dim) {
     const size_t N = (size_t)(n > 0 ? n : 1), M = (size_t)(n > 1 ? n - 1 : 1);
     L.ctrl = take(sizeof(Ctrl));
     L.bpart = take(32 * (size_t)kPartBlocks);
-    L.k0 = take(8 * N);
-    L.k1 = take(8 * N);
+    // the key buffers also hold the root lists during the rounds
+    const size_t keys = std::max<size_t>(8 * N, 4 * (size_t)root_list_blocks(n) * (size_t)root_list_cap(n));
+    L.k0 = take(keys);
+    L.k1 = take(keys);
     L.v0 = take(4 * N);
     L.v1 = take(4 * N);
     L.hist = take(4 * radix_hist_elems());
@@ -1908,13 +1971,25 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     if (round > 0)
         k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
                                                b.ctrl);
-    k_merge_succ<<<grid_for(n), 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.orig, b.succ, b.ctrl, n,
-                                              cloud_of != nullptr, round == 0);
-    const int mp_blocks = (int)std::min<unsigned>(grid_for(n), kPartBlocks);
+    // root lists: segments in the Morton key buffers (free during the
+    // rounds), counts behind k_merge_parent's partials in bpart
+    const int mp_blocks = root_list_blocks(n);
+    const bool first = round == 0;
+    RootList rl;
+    uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(b.k0), reinterpret_cast<uint32_t*>(b.k1)};
+    uint32_t* counts = b.bpart + 4 * kPartBlocks;
+    rl.in = lists[round & 1];
+    rl.cnt_in = counts + kPartBlocks * (round & 1);
+    rl.out = lists[(round + 1) & 1];
+    rl.cnt_out = counts + kPartBlocks * ((round + 1) & 1);
+    rl.cap = root_list_cap(n);
+    const unsigned merge_grid = first ? grid_for(n) : (unsigned)mp_blocks;
+    k_merge_succ<<<merge_grid, 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.orig, b.succ, b.ctrl, n,
+                                             cloud_of != nullptr, first, rl);
     k_merge_parent<<<mp_blocks, 256, 0, st>>>(b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud,
-                                              reinterpret_cast<uint2*>(b.bpart), b.ctrl, n);
+                                              reinterpret_cast<uint2*>(b.bpart), b.ctrl, n, first, rl);
     HIP_TRY(hipGetLastError());
-    k_merge_jump<<<grid_for(n), 256, 0, st>>>(b.labels, b.par, n, 1024, b.ctrl);
+    k_merge_jump<<<merge_grid, 256, 0, st>>>(b.labels, b.par, n, 1024, b.ctrl, first, rl);
     k_relabel<<<nt, 256, 0, st>>>(b.labels, b.par, n, 4096, b.run_part, reinterpret_cast<const uint2*>(b.bpart),
                                   mp_blocks, b.ctrl, target);
     HIP_TRY(hipGetLastError());
