@@ -604,6 +604,29 @@ __device__ __forceinline__ void block_max_min256(uint32_t& mx, uint32_t& mn, uin
     mn = min(min(s_w[4], s_w[5]), min(s_w[6], s_w[7]));
 }
 
+// Sum of (a, b) over the 256 threads of the workgroup; s_w holds 8 words.
+__device__ __forceinline__ void block_sum2_256(uint32_t& a, uint32_t& b, uint32_t* s_w) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += (uint32_t)__shfl_xor(a, off);
+        b += (uint32_t)__shfl_xor(b, off);
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        s_w[w] = a;
+        s_w[4 + w] = b;
+    }
+    __syncthreads();
+    a = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    b = s_w[4] + s_w[5] + s_w[6] + s_w[7];
+}
+
+// Up to this many tiles, a kernel that needs a scan over the per-tile
+// partials of the kernel before computes its own entry from all of them
+// (at most 2 x 1024 words from L2 per workgroup) instead of waiting for a
+// one-workgroup scan kernel, which saves that launch.
+constexpr int kFoldTiles = 1024;
+
 // Exclusive max-scan in thread order over the 256 threads (0 for thread 0).
 __device__ __forceinline__ uint32_t block_excl_max256(uint32_t x, uint32_t* s_w4) {
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -730,7 +753,7 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
                                                     const float* __restrict__ spts,
                                                     const uint32_t* __restrict__ cloud_of,
                                                     const float* __restrict__ core_s, int64_t n, uint32_t* ub,
-                                                    Ctrl* ctrl) {
+                                                    Ctrl* ctrl, const uint32_t* __restrict__ fold_part, int nt) {
     if (ctrl->done) return;
     __shared__ uint32_t s_lab[kRunLds];               // labels of positions base-1 .. base+kRunTile
     __shared__ uint32_t s_rs[FIRST ? 1 : kRunLds];    // start of the run containing each position
@@ -743,6 +766,21 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
         int64_t p = base + x - 1;
         p = p < 0 ? 0 : (p >= n ? n - 1 : p);
         s_lab[run_lds(x)] = FIRST ? (uint32_t)p : labels[p];  // first round: a point's label is its position
+    }
+    // the tile carries: last run start before the tile, first run end after
+    // it (from k_tile_carries, or with fold_part from the tile partials)
+    uint32_t carry_l = 0u, carry_r = kNone;
+    if (!FIRST) {
+        if (fold_part) {
+            for (int t = tid; t < nt; t += 256) {
+                if (t < (int)blockIdx.x) carry_l = max(carry_l, fold_part[2 * t]);
+                if (t > (int)blockIdx.x) carry_r = min(carry_r, fold_part[2 * t + 1]);
+            }
+            block_max_min256(carry_l, carry_r, s_w);  // (its barrier also covers s_lab)
+        } else {
+            carry_l = carry[2 * blockIdx.x];
+            carry_r = carry[2 * blockIdx.x + 1];
+        }
     }
     __syncthreads();
     if (!FIRST) {
@@ -759,8 +797,8 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
                 if (p == n - 1 || s_lab[run_lds(x + 2)] != l) agg_t = min(agg_t, (uint32_t)p);
             }
         }
-        uint32_t cur = max(block_excl_max256(agg_h, s_w), carry[2 * blockIdx.x]);
-        const uint32_t cr = min(block_excl_min256_rev(agg_t, s_w + 4), carry[2 * blockIdx.x + 1]);
+        uint32_t cur = max(block_excl_max256(agg_h, s_w), carry_l);
+        const uint32_t cr = min(block_excl_min256_rev(agg_t, s_w + 4), carry_r);
 #pragma unroll
         for (int j = 0; j < kRunPer; ++j) {
             const int x = x0 + j;
@@ -779,7 +817,6 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
         __syncthreads();
     }
     // record labels; record k has the children [rlo[k], k] and [k+1, rhi[k]]
-    const uint32_t carry_r = FIRST ? kNone : carry[2 * blockIdx.x + 1];
 #pragma unroll
     for (int q = 0; q < kRunPer; ++q) {
         const int x = q * 256 + tid;
@@ -986,12 +1023,30 @@ __global__ __launch_bounds__(1024) void k_qlist_scan(const uint32_t* __restrict_
     if (threadIdx.x == 0) ctrl->qcount = run;
 }
 
-// qlist[qoff[t] + k] = the k-th flagged position of tile t, in order.
+// qlist[qoff[t] + k] = the k-th flagged position of tile t, in order.  With
+// fold_cnt, a workgroup sums the tile counts before its own tile itself
+// (qoff unused), and workgroup 0 stores the total in ctrl->qcount.
 __global__ __launch_bounds__(256) void k_qlist_write(const uint8_t* __restrict__ qflag,
                                                      const uint32_t* __restrict__ qoff, int64_t n,
-                                                     uint32_t* __restrict__ qlist, const Ctrl* ctrl) {
+                                                     uint32_t* __restrict__ qlist, Ctrl* ctrl,
+                                                     const uint32_t* __restrict__ fold_cnt, int nt) {
     if (ctrl->done) return;
-    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_w[8];
+    uint32_t off;
+    if (fold_cnt) {
+        uint32_t before = 0u, total = 0u;
+        for (int t = threadIdx.x; t < nt; t += 256) {
+            const uint32_t c = fold_cnt[t];
+            total += c;
+            if (t < (int)blockIdx.x) before += c;
+        }
+        block_sum2_256(before, total, s_w);
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->qcount = total;
+        off = before;
+        __syncthreads();  // s_w is reused below
+    } else {
+        off = qoff[blockIdx.x];
+    }
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
     const int64_t x0 = base + (int64_t)threadIdx.x * kRunPer;  // this thread's kRunPer consecutive positions
     uint32_t f[kRunPer];
@@ -1011,7 +1066,7 @@ __global__ __launch_bounds__(256) void k_qlist_write(const uint8_t* __restrict__
     }
     if (lane == 63) s_w[w] = inc;
     __syncthreads();
-    uint32_t at = qoff[blockIdx.x] + inc - cnt;
+    uint32_t at = off + inc - cnt;
     for (int k = 0; k < w; ++k) at += s_w[k];
 #pragma unroll
     for (int j = 0; j < kRunPer; ++j)
@@ -1832,7 +1887,7 @@ hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_part, uint32_t
     k_run_partials<<<nb, 256, 0, st>>>(labels, n, run_part);
     k_tile_carries<<<1, 1024, 0, st>>>(run_part, nb, run_carry, ctrl);
     k_round_prep<3, false, false><<<nb, 256, 0, st>>>(labels, run_carry, rlo, rhi, lab2, nullptr, nullptr, nullptr,
-                                                      n, nullptr, ctrl);
+                                                      n, nullptr, ctrl, nullptr, nb);
     return hipGetLastError();
 }
 
@@ -1946,13 +2001,15 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     // record labels and bounds; the run partials of round r > 0 come from
     // the relabel kernel of round r - 1
     const int nt = run_tiles(n);
+    const bool fold = nt <= kFoldTiles;  // scans folded into their consumers
     if (round == 0) {
         k_round_prep<DIM, true, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
-                                                          cloud_of, ta.core_s, n, b.ub, b.ctrl);
+                                                          cloud_of, ta.core_s, n, b.ub, b.ctrl, nullptr, nt);
     } else {
-        k_tile_carries<<<1, 1024, 0, st>>>(b.run_part, nt, b.run_carry, b.ctrl);
+        if (!fold) k_tile_carries<<<1, 1024, 0, st>>>(b.run_part, nt, b.run_carry, b.ctrl);
         k_round_prep<DIM, false, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
-                                                           cloud_of, ta.core_s, n, b.ub, b.ctrl);
+                                                           cloud_of, ta.core_s, n, b.ub, b.ctrl,
+                                                           fold ? b.run_part : nullptr, nt);
     }
     ta.first = round == 0;
     // variant 13: only the points whose last result no longer holds search
@@ -1960,8 +2017,8 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     if (uses_qlist(variant, round, n)) {
         k_reuse_mark<<<nt, 256, 0, st>>>(b.labels, b.ub, b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag,
                                          b.qcnt, n, b.ctrl);
-        k_qlist_scan<<<1, 1024, 0, st>>>(b.qcnt, nt, b.qoff, b.ctrl);
-        k_qlist_write<<<nt, 256, 0, st>>>(b.qflag, b.qoff, n, b.qlist, b.ctrl);
+        if (!fold) k_qlist_scan<<<1, 1024, 0, st>>>(b.qcnt, nt, b.qoff, b.ctrl);
+        k_qlist_write<<<nt, 256, 0, st>>>(b.qflag, b.qoff, n, b.qlist, b.ctrl, fold ? b.qcnt : nullptr, nt);
         HIP_TRY(hipGetLastError());
         ta.qlist = b.qlist;
     }
