@@ -883,7 +883,12 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
         // sequence falls back to the global atomic.
         uint32_t* h_lab = s_rs;
         uint32_t* h_val = s_re;
-        __syncthreads();
+        bool some = false;
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) some |= v[q] != kInfBits;
+        // a tile without a component boundary (most tiles of late rounds)
+        // has no bound to give
+        if (!__syncthreads_or(some)) return;
         for (int e = tid; e < kBoundHash; e += 256) {
             h_lab[e] = kNone;
             h_val[e] = kInfBits;
@@ -893,7 +898,8 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
         for (int q = 0; q < kRunPer; ++q) {
             const int x = q * 256 + tid;
             const int64_t k = base + x;
-            if (base + q * 256 < n) {  // uniform over the workgroup
+            // uniform over the workgroup; a wave without a bound skips its scan
+            if (base + q * 256 < n && __ballot(v[q] != kInfBits) != 0ull) {
                 const uint32_t lab = k < n ? s_lab[run_lds(x + 1)] : kNone;
                 bool run_end;
                 const uint32_t m = wave_seg_min<uint32_t>(lab, v[q], &run_end);
@@ -1178,17 +1184,36 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
     const uint32_t* seg_in = rl.in + rl.cap * blockIdx.x;
     uint32_t* seg_out = rl.out + rl.cap * blockIdx.x;
     const int64_t cnt = first ? 0 : rl.cnt_in[blockIdx.x];
-    const int64_t i0 = first ? (int64_t)blockIdx.x * blockDim.x + threadIdx.x : (int64_t)threadIdx.x;
+    // the lanes of a wave take consecutive entries, so the loop is uniform
+    // per wave, and a wave appends its roots in lane order (segments stay
+    // runs of ascending positions)
+    const int lane = lane_id();
+    const int64_t w0 = (first ? (int64_t)blockIdx.x * blockDim.x + threadIdx.x : (int64_t)threadIdx.x) - lane;
     const int64_t step = first ? (int64_t)gridDim.x * blockDim.x : (int64_t)blockDim.x;
     const int64_t end = first ? n : cnt;
-    for (int64_t i = i0; i < end; i += step) {
-        const int64_t c = first ? i : (int64_t)seg_in[i];
-        if (first && labels[c] != (uint32_t)c) continue;
-        const uint32_t s = succ[c];
-        const bool root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
-        par[c] = root ? (uint32_t)c : s;
+    for (int64_t w = w0; w < end; w += step) {
+        const int64_t i = w + lane;
+        int64_t c = 0;
+        bool comp = i < end;
+        if (comp) {
+            c = first ? i : (int64_t)seg_in[i];
+            comp = !first || labels[c] == (uint32_t)c;
+        }
+        bool root = false;
+        if (comp) {
+            const uint32_t s = succ[c];
+            root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
+            par[c] = root ? (uint32_t)c : s;
+        }
+        const uint64_t rm = __ballot(root);
+        if (rm) {
+            uint32_t at = 0u;
+            if (lane == 0) at = atomicAdd(&s_cnt[0], (uint32_t)__popcll(rm));
+            at = (uint32_t)__shfl((int)at, 0);
+            if (root) seg_out[at + (uint32_t)__popcll(rm & ((1ull << lane) - 1ull))] = (uint32_t)c;
+        }
+        if (!comp) continue;
         if (root) {
-            seg_out[atomicAdd(&s_cnt[0], 1u)] = (uint32_t)c;
             ub[c] = kInfBits;
             compkey[c] = kKeyMax;
             compmax[c] = kNone;
