@@ -298,6 +298,18 @@ def test_query_list_threshold(ctx):
                 assert all(x == n for x in q)
 
 
+def test_scan_fold_threshold(ctx):
+    """Up to 1024 tiles of 2048 positions the round kernels compute the
+    tile carries and list offsets themselves, above it one-workgroup scan
+    kernels do; the merge kernels' root-list segments grow from 1024 to
+    1280 entries across the same sizes.  Both sides, variant 13."""
+    for n in (1024 * 2048, 1024 * 2048 + 1):
+        pts = W.clustered3d(n, seed=33)
+        print(f"scan fold n={n}", flush=True)
+        ref = oracle.kdboruvka(pts, threads=16)
+        assert_same(run(ctx, pts, 13), ref, f"n={n}")
+
+
 def test_clustered3d_2m(ctx):
     pts = W.clustered3d()
     ref = oracle.kdboruvka(pts, threads=16)
