@@ -1081,20 +1081,54 @@ __global__ __launch_bounds__(256) void k_qlist_write(const uint8_t* __restrict__
 
 // Stage B of the component minimum: among the points whose candidate matches
 // the component's (D bits, min index) key, the smallest max index wins, so
-// the component edge is the minimum under (D, min, max).
+// the component edge is the minimum under (D, min, max).  PER consecutive
+// points per thread: 4 (16-byte loads; the arrays are 256-byte aligned)
+// once components span many points, 1 in the round after the first, where
+// they are small and a thread's component-key loads mostly miss.
+template <int PER>
 __global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ cand_d,
                                                  const uint32_t* __restrict__ cand_j,
                                                  const uint32_t* __restrict__ labels,
                                                  const uint32_t* __restrict__ orig,
                                                  const uint64_t* __restrict__ compkey, uint32_t* compmax,
                                                  int64_t n, const Ctrl* ctrl) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || ctrl->done) return;
-    const uint32_t j = cand_j[i];
-    if (j == kNone) return;  // no candidate
-    const uint32_t cd = cand_d[i], oi = orig[i], c = labels[i];
-    const uint64_t key = ((uint64_t)cd << 32) | (uint64_t)min(oi, j);
-    if (key == compkey[c]) atomicMin(&compmax[c], max(oi, j));
+    const int64_t i0 = PER * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 >= n || ctrl->done) return;
+    uint32_t j[PER], cd[PER], oi[PER], c[PER];
+    if (PER == 4 && i0 + 3 < n) {
+        const uint4 J = *reinterpret_cast<const uint4*>(cand_j + i0);
+        if ((J.x & J.y & J.z & J.w) == kNone) return;  // none has a candidate
+        const uint4 D = *reinterpret_cast<const uint4*>(cand_d + i0);
+        const uint4 O = *reinterpret_cast<const uint4*>(orig + i0);
+        const uint4 L = *reinterpret_cast<const uint4*>(labels + i0);
+        const uint32_t jv[4] = {J.x, J.y, J.z, J.w}, dv[4] = {D.x, D.y, D.z, D.w};
+        const uint32_t ov[4] = {O.x, O.y, O.z, O.w}, lv[4] = {L.x, L.y, L.z, L.w};
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            j[k] = jv[k];
+            cd[k] = dv[k];
+            oi[k] = ov[k];
+            c[k] = lv[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = i0 + k;
+            j[k] = i < n ? cand_j[i] : kNone;
+            cd[k] = j[k] != kNone ? cand_d[i] : 0u;
+            oi[k] = j[k] != kNone ? orig[i] : 0u;
+            c[k] = j[k] != kNone ? labels[i] : 0u;
+        }
+    }
+    uint64_t ck[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) ck[k] = j[k] != kNone ? compkey[c[k]] : 0ull;  // loads in flight together
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (j[k] == kNone) continue;  // no candidate
+        const uint64_t key = ((uint64_t)cd[k] << 32) | (uint64_t)min(oi[k], j[k]);
+        if (key == ck[k]) atomicMin(&compmax[c[k]], max(oi[k], j[k]));
+    }
 }
 
 // The components of a round, as a list: k_merge_parent leaves the roots it
@@ -2050,9 +2084,12 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
     HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
     if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
-    if (round > 0)
-        k_resolve<<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
-                                               b.ctrl);
+    if (round == 1)
+        k_resolve<1><<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
+                                                  b.ctrl);
+    else if (round > 1)
+        k_resolve<4><<<grid_for((n + 3) / 4), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey,
+                                                            b.compmax, n, b.ctrl);
     // root lists: segments in the Morton key buffers (free during the
     // rounds), counts behind k_merge_parent's partials in bpart
     const int mp_blocks = root_list_blocks(n);
