@@ -2044,10 +2044,11 @@ int read_ctrl(emst_ctx* ctx, Ctrl* ctrl, hipStream_t st) {
 // cloud is finished) becomes a root.
 // Variant 13 searches from a query list from the third round on (the
 // second keeps nothing: in the first round every point joins its nearest
-// neighbour's component).  Below kQlistMinN points the list's three extra
+// neighbour's component).  Below kQlistMinN points the list's extra
 // launches per round cost more than the idle lanes they save, and the
-// points skip inside the traversal instead.
-constexpr int64_t kQlistMinN = (int64_t)1 << 18;
+// points skip inside the traversal instead (measured crossover between
+// 5e5 and 1e6 points).
+constexpr int64_t kQlistMinN = (int64_t)3 << 18;
 static inline bool uses_qlist(int variant, int round, int64_t n) {
     return variant == 13 && round >= 2 && n >= kQlistMinN;
 }

@@ -282,9 +282,9 @@ def test_uniform2d_10k(ctx):
 
 def test_query_list_threshold(ctx):
     """Variant 13 compacts the searching points into a query list from
-    2^18 points on and skips inside the traversal below: both sides of the
+    3 * 2^18 points on and skips inside the traversal below: both sides of the
     threshold, 2D and 3D, with integer coordinates (many equal lengths)."""
-    for n in (262_143, 262_144):
+    for n in (786_431, 786_432):
         for pts in (W.clustered3d(n, seed=31), np.floor(W.uniform2d(n, seed=32) * 2000.0).astype(np.float32)):
             print(f"query list n={n} dim={pts.shape[1]}", flush=True)
             ref = oracle.kdboruvka(pts, threads=16)
@@ -292,7 +292,7 @@ def test_query_list_threshold(ctx):
             st = ctx.stats()
             q = st["queries_round"]
             assert all(x == n for x in q[:2])
-            if n >= 262_144:
+            if n >= 786_432:
                 assert any(x < n for x in q[2:])  # a list ran
             else:
                 assert all(x == n for x in q)
