@@ -338,18 +338,27 @@ def check_spanning_tree(n: int, edges) -> None:
 def check_cycle_property(points, mst: MST, core2=None) -> None:
     """Every non-tree pair's key exceeds the largest key on its tree path
     (the cycle property that characterises the unique MST under K; with
-    core2, under the key of M)."""
+    core2, under the key of M).  The edge set must also be a spanning tree
+    (check_spanning_tree) and its d2 must be the weights of its own edges:
+    the path keys come from the points, not from the tree."""
     pts = _points(points)
     n = pts.shape[0]
-    if n < 3:
+    check_spanning_tree(n, mst.edges)
+    if n < 2:
         return
     W = pair_d2_matrix(pts)
     if core2 is not None:
         c = np.asarray(core2, dtype=np.float32)
         W = np.maximum(np.maximum(W, c[:, None]), c[None, :]).astype(np.float32)
     D = W.view(np.uint32).astype(np.int64)
+    e = np.asarray(mst.edges).reshape(-1, 2)
+    # the tree's own weights must be the weights of its edges: the keys below
+    # are taken from the points, never from the tree
+    claimed = np.asarray(mst.d2, dtype=np.float32).view(np.uint32).astype(np.int64)
+    assert np.array_equal(claimed, D[e[:, 0], e[:, 1]]), "tree weights differ from the weights of its edges"
     adj = [[] for _ in range(n)]
-    for (u, v), d in zip(mst.edges.tolist(), mst.d2.view(np.uint32).tolist()):
+    for u, v in e.tolist():
+        d = int(D[u, v])
         adj[u].append((v, d))
         adj[v].append((u, d))
     B = np.int64(n + 1)
@@ -365,6 +374,7 @@ def check_cycle_property(points, mst: MST, core2=None) -> None:
                     k = (int(d) * B + min(x, y)) * B + max(x, y)
                     mx[y] = max(int(mx[x]), k)
                     stack.append(y)
+        assert (mx != -1).all(), f"vertex {int(np.argmax(mx == -1))} is not reachable from {s}"
         ys = np.arange(s + 1, n)
         keys = (D[s, ys] * B + s) * B + ys
         assert (keys >= mx[ys]).all(), f"cycle property violated from vertex {s}"
