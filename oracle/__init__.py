@@ -8,7 +8,9 @@ Contents
 --------
 * ``prim``          dense O(n^2) Prim under the key K (C, ``emst_oracle.c``)
 * ``kdboruvka``     Boruvka over a kd-tree, serial or OpenMP (C)
-* ``sqdist``        the float32 squared distance D for one pair (C)
+* ``sqdist``        the float32 squared distance D for one pair (C);
+                    ``sqdist_pairs`` for many, ``weights`` the reported
+                    weight sqrtf(D)
 * ``kruskal_bruteforce``  all n(n-1)/2 keys sorted, then union-find (numpy)
 * ``nearest_other_bruteforce``  per-point nearest neighbour in another
                     component under (D, j) (numpy), the per-point step of
@@ -67,6 +69,10 @@ def lib():
         i64p = ctypes.POINTER(ctypes.c_int64)
         L.oracle_sqdist.argtypes = [f32p, f32p, ctypes.c_int]
         L.oracle_sqdist.restype = ctypes.c_float
+        L.oracle_sqdist_pairs.argtypes = [f32p, f32p, ctypes.c_int64, ctypes.c_int, f32p]
+        L.oracle_sqdist_pairs.restype = None
+        L.oracle_weights.argtypes = [f32p, ctypes.c_int64, f32p]
+        L.oracle_weights.restype = None
         L.oracle_prim.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i32p, f32p]
         L.oracle_prim.restype = ctypes.c_int
         L.oracle_kdboruvka.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i32p, f32p,
@@ -103,6 +109,25 @@ def sqdist(a, b) -> np.float32:
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
     b = np.ascontiguousarray(np.asarray(b, dtype=np.float32))
     return np.float32(lib().oracle_sqdist(_p(a, ctypes.c_float), _p(b, ctypes.c_float), a.shape[0]))
+
+
+def sqdist_pairs(a, b) -> np.ndarray:
+    """D of every pair of rows: a, b [m, dim] float32 -> [m] float32."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float32))
+    assert a.shape == b.shape and a.ndim == 2
+    out = np.empty(a.shape[0], np.float32)
+    lib().oracle_sqdist_pairs(_p(a, ctypes.c_float), _p(b, ctypes.c_float), a.shape[0], a.shape[1],
+                              _p(out, ctypes.c_float))
+    return out
+
+
+def weights(d2) -> np.ndarray:
+    """The reported edge weights: sqrtf(d2), correctly rounded."""
+    d = np.ascontiguousarray(np.asarray(d2, dtype=np.float32).reshape(-1))
+    out = np.empty_like(d)
+    lib().oracle_weights(_p(d, ctypes.c_float), d.shape[0], _p(out, ctypes.c_float))
+    return out
 
 
 class MST:

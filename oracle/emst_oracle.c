@@ -25,7 +25,8 @@
  *   weights sqrtf(D).
  *
  * Functions:
- *   oracle_sqdist       D for one pair
+ *   oracle_sqdist       D for one pair (oracle_sqdist_pairs: for many)
+ *   oracle_weights      the reported weight sqrtf(D), correctly rounded
  *   oracle_prim         dense O(n^2) Prim (Section 2, Prim's algorithm)
  *   oracle_kdboruvka    Boruvka (Algorithm 1) over a kd-tree nearest
  *                       other-component search, with subtree skipping
@@ -91,6 +92,21 @@ float oracle_sqdist(const float *a, const float *b, int dim) {
     float s = sqdist(a, b, dim);
     fp_leave(csr);
     return s;
+}
+
+/* D of m pairs: out[i] = D(a + i*dim, b + i*dim). */
+void oracle_sqdist_pairs(const float *a, const float *b, int64_t m, int dim, float *out) {
+    unsigned int csr = fp_enter();
+    for (int64_t i = 0; i < m; ++i) out[i] = sqdist(a + i * dim, b + i * dim, dim);
+    fp_leave(csr);
+}
+
+/* The reported weight of an edge: w[i] = sqrtf(d2[i]), IEEE correctly
+ * rounded. */
+void oracle_weights(const float *d2, int64_t m, float *w) {
+    unsigned int csr = fp_enter();
+    for (int64_t i = 0; i < m; ++i) w[i] = sqrtf(d2[i]);
+    fp_leave(csr);
 }
 
 /* ------------------------------------------------------------------------ */
