@@ -256,6 +256,9 @@ typedef struct emst_stats {
     int64_t queries_round[64];      /* points the traversal searched in each
                                        round: n, or the length of the round's
                                        query list (variant 13, third round on) */
+    int64_t records_touched_round[64];  /* counting only: distinct node
+                                       records the traversal loaded in each
+                                       round */
 } emst_stats;
 
 /* Time every phase with HIP events (adds synchronisation; off by default). */
@@ -267,39 +270,29 @@ int emst_set_counting(emst_ctx *ctx, int on);
 
 /* Traversal launch shape.  All compute the same result:
  *   0  one lane per query, top-down from the root, stack in private memory
- *   1  wavefront-cooperative: the 64 Morton-ordered queries of a wave walk
- *      the union of their paths with one node load per wave
- *   2  one lane per query, walking up from the query's own leaf and stopping
- *      at the first ancestor whose Morton cell holds the search ball
- *   3, 4  as 0 and 2 on persistent waves that refill finished lanes
  *   5  as 0 with a branch-free inner loop and a 16-deep LDS stack
- *   6  as 2 with the loop of 5
  *   7  as 5 with an 8-deep LDS stack
  *   8  as 5 with a 4-deep LDS stack
- *   9  as 6 with an 8-deep LDS stack
  *  10  as 7, but each wave of 64 queries starts below the root, at the
  *      lowest ancestor of its leaves whose Morton cell holds every lane's
  *      search ball
  *  11  as 10 with the component bound shared while the round runs (every
  *      improved candidate lowers it with an atomicMin, every node visit
  *      re-reads it)
- *  12  as 10 with two pending nodes per lane: both records are loaded
- *      together, the two nearest admissible internal children of the four
- *      become the next pair, the others are deferred
  *  13  as 10, and a point keeps last round's result where it still holds:
  *      its candidate if that is still outside its component, or "nothing"
  *      if it found nothing within a radius at least the new one (default)
  * -1 (the default) takes the variant from the context's autotune table
  * (emst_set_autotune) for the call's mode, dimension and size, else 13.
- * Batches (emst_build_batched) run 0, 5, 7, 8 or 13 (with the start of 7)
- * as chosen and 7 for any other value.
- * Returns EMST_EINVAL outside [-1, 13]. */
+ * Batches (emst_build_batched) run 0, 5, 8 or 13 (with the start of 7) as
+ * chosen and 7 for 10 and 11.
+ * Returns EMST_EINVAL for any other value. */
 int emst_set_traversal(emst_ctx *ctx, int variant);
 
 /* Traversal-shape table (the autotuner's output), a JSON document
  *
  *   {"entries": [{"mode": "single" | "batched", "dim": 2 | 3,
- *                 "n_min": <points>, "variant": <0..13>}, ...]}
+ *                 "n_min": <points>, "variant": <0, 5, 7, 8, 10, 11 or 13>}, ...]}
  *
  * (other keys are ignored).  A call in auto mode (emst_set_traversal -1)
  * with n points uses the entry of its mode and dimension with the largest

@@ -55,6 +55,52 @@ int emst_test_tree_boxes(emst_ctx *ctx, const float *d_points, int64_t n, int32_
 int emst_test_radix_sort(emst_ctx *ctx, uint64_t *d_keys, uint32_t *d_vals, int64_t n,
                          void *d_workspace, size_t ws_bytes, void *stream);
 
+/*
+ * One Boruvka round of emst_build from a given partition (Section 3,
+ * Figure 3): label propagation and component bounds (Optimizations 1 and
+ * 2), the nearest-other-component traversal with stage A (Algorithm 2),
+ * stage B of the tie-break, and the merge ("Merging components together"),
+ * on the tree emst_build builds for d_points [n][dim].
+ *
+ *  d_comp     [n] int32: the component of every point (input order), values
+ *             in [0, n), at least two distinct ones.
+ *  round      which round's kernels run, 1 .. 63 (1: the second round; from
+ *             2 on, variant 13 searches from a query list at 3 * 2^18 points
+ *             and more).  No earlier result is reused: every point searches.
+ *  variant    traversal variant, as emst_set_traversal takes it (not -1).
+ * Outputs per point, input order (device memory, [n] each):
+ *  d_bound    the bound of the point's component after the bound pass
+ *  d_cand_d, d_cand_j   the point's candidate: the (D, j)-nearest point
+ *             outside its component within the bound, or (+inf, -1)
+ *  d_comp_d2, d_comp_u, d_comp_v   its component's edge after stages A and
+ *             B: the minimum under (D, min, max), u < v original indices
+ *  d_comp_out the component after the merge: the original index of one
+ *             point of it, the same for all of its points
+ * *ncomp_out (host) receives the number of components after the round.
+ */
+int emst_test_round(emst_ctx *ctx, const float *d_points, int64_t n, int dim, const int32_t *d_comp,
+                    int32_t round, int32_t variant, float *d_bound, float *d_cand_d, int32_t *d_cand_j,
+                    float *d_comp_d2, int32_t *d_comp_u, int32_t *d_comp_v, int32_t *d_comp_out,
+                    int64_t *ncomp_out, void *d_workspace, size_t ws_bytes, void *stream);
+
+/*
+ * The distance and weight functions of the kernels on m pairs of points
+ * (a_i, b_i), d_a and d_b [m][dim] float32 (dim 2 or 3):
+ *   d_sq[i]   D(a_i, b_i) as the bound pass evaluates it
+ *   d_box[i]  the box distance from a_i to the one-point box [b_i, b_i],
+ *             as the traversal evaluates D at a leaf
+ *   d_w[i]    the reported weight of an edge of squared length d_sq[i]
+ */
+int emst_test_distances(emst_ctx *ctx, const float *d_a, const float *d_b, int64_t m, int dim, float *d_sq,
+                        float *d_box, float *d_w, void *stream);
+
+/*
+ * The weight function on float32 bit patterns: d_w[k] = weight of the
+ * squared length whose bits are first + k, for k in [0, count);
+ * first + count <= 2^32.
+ */
+int emst_test_weights(emst_ctx *ctx, uint32_t first, int64_t count, float *d_w, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

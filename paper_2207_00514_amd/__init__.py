@@ -36,6 +36,7 @@ EXPORTS = [
     "emst_core_distances", "emst_build_mreach", "emst_set_autotune", "emst_get_autotune",
     "emst_solver_slot_bytes", "emst_solver_create", "emst_solver_destroy", "emst_solver_admit",
     "emst_solver_step", "emst_solver_poll", "emst_solver_take",
+    "emst_test_round", "emst_test_distances", "emst_test_weights",
 ]
 
 
@@ -57,7 +58,7 @@ class Stats(ctypes.Structure):
         ("leaf_tests", ctypes.c_int64), ("child_tests_round", ctypes.c_int64 * 64),
         ("leaf_tests_round", ctypes.c_int64 * 64), ("dist_evals", ctypes.c_int64),
         ("traversal_variant", ctypes.c_int32), ("rank_codes", ctypes.c_int32),
-        ("queries_round", ctypes.c_int64 * 64),
+        ("queries_round", ctypes.c_int64 * 64), ("records_touched_round", ctypes.c_int64 * 64),
     ]
 
     def as_dict(self) -> dict:
@@ -72,6 +73,7 @@ class Stats(ctypes.Structure):
             leaf_tests_round=list(self.leaf_tests_round[:r]), dist_evals=self.dist_evals,
             traversal_variant=self.traversal_variant, rank_codes=self.rank_codes,
             queries_round=list(self.queries_round[:r]),
+            records_touched_round=list(self.records_touched_round[:r]),
         )
 
 
@@ -136,6 +138,13 @@ def lib():
         L.emst_test_tree_boxes.restype = i32
         L.emst_test_radix_sort.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         L.emst_test_radix_sort.restype = i32
+        L.emst_test_round.argtypes = [vp, vp, i64, i32, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
+                                      vp, vp, ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
+        L.emst_test_round.restype = i32
+        L.emst_test_distances.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, vp]
+        L.emst_test_distances.restype = i32
+        L.emst_test_weights.argtypes = [vp, ctypes.c_uint32, i64, vp, vp]
+        L.emst_test_weights.restype = i32
         _lib = L
     return _lib
 
@@ -264,6 +273,51 @@ class Context:
         self._check(lib().emst_test_radix_sort(
             self._h, ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), int(n),
             ws, wsb, _stream_handle(stream)))
+
+    def test_round(self, points, comp, round_: int = 1, variant: int = 13, stream=None):
+        """One Boruvka round from the partition `comp` (int32 [n], input
+        order); returns a dict of per-point tensors (bound, cand_d, cand_j,
+        comp_d2, comp_u, comp_v, comp_out) and ncomp -- see
+        include/emst_test.h."""
+        import torch
+        points = self._check_points(points)
+        n, dim = points.shape
+        dev = points.device
+        f = lambda: torch.empty(n, dtype=torch.float32, device=dev)  # noqa: E731
+        i = lambda: torch.empty(n, dtype=torch.int32, device=dev)  # noqa: E731
+        out = dict(bound=f(), cand_d=f(), cand_j=i(), comp_d2=f(), comp_u=i(), comp_v=i(), comp_out=i())
+        comp = comp.to(device=dev, dtype=torch.int32).contiguous()
+        nc = ctypes.c_int64(0)
+        ws, wsb = self._ws_ptr(n, dim)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(lib().emst_test_round(
+            self._h, P(points), int(n), int(dim), P(comp), int(round_), int(variant), P(out["bound"]),
+            P(out["cand_d"]), P(out["cand_j"]), P(out["comp_d2"]), P(out["comp_u"]), P(out["comp_v"]),
+            P(out["comp_out"]), ctypes.byref(nc), ws, wsb, _stream_handle(stream)))
+        out["ncomp"] = nc.value
+        return out
+
+    def test_distances(self, a, b, stream=None):
+        """(D, box distance to the one-point box, weight) of the kernels for
+        every pair of rows of a and b ([m, dim] float32)."""
+        import torch
+        a, b = self._check_points(a), self._check_points(b)
+        m, dim = a.shape
+        sq, box, w = (torch.empty(m, dtype=torch.float32, device=a.device) for _ in range(3))
+        P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(lib().emst_test_distances(self._h, P(a), P(b), int(m), int(dim), P(sq), P(box), P(w),
+                                              _stream_handle(stream)))
+        return sq, box, w
+
+    def test_weights(self, first: int, count: int, out=None, stream=None):
+        """The kernels' weight function on the float32 bit patterns first ..
+        first + count - 1."""
+        import torch
+        if out is None:
+            out = torch.empty(count, dtype=torch.float32, device=f"cuda:{self.device}")
+        self._check(lib().emst_test_weights(self._h, ctypes.c_uint32(int(first)), int(count),
+                                            ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
 
     def build(self, points, out=None, want_d2: bool = True, stream=None):
         """EMST of points [n, dim] (float32, on this context's device).

@@ -146,7 +146,7 @@ __global__ void k_init_ctrl(Ctrl* ctrl) {
         ctrl->nonfinite = 0; ctrl->root = kNone; ctrl->height = 0;
         ctrl->ncomp_next = 0; ctrl->edge_count = 0; ctrl->error = 0;
         ctrl->key_or = 0ull; ctrl->key_and = ~0ull;
-        ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0; ctrl->trav_next = 0;
+        ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0; ctrl->touched = 0;
         ctrl->long_ties = 0; ctrl->dup_codes = 0; ctrl->done = 0;
     }
 }
@@ -761,7 +761,6 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
     __shared__ uint32_t s_w[8];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
-    if (BOUNDS && blockIdx.x == 0 && tid == 0) ctrl->trav_next = 0ull;
     for (int x = tid; x < kRunTile + 2; x += 256) {
         int64_t p = base + x - 1;
         p = p < 0 ? 0 : (p >= n ? n - 1 : p);
@@ -1492,7 +1491,7 @@ __global__ __launch_bounds__(256) void k_edge_write(const uint4* __restrict__ eu
     const uint4 s = eud[perm[i]];
     const float d = bitsf(s.z);
     reinterpret_cast<int2*>(edges)[i] = make_int2((int32_t)s.x, (int32_t)s.y);
-    w[i] = sqrtf(d);
+    w[i] = edge_weight(d);
     if (d2) d2[i] = d;
 }
 
@@ -1651,6 +1650,18 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
     if (i < n) p[i] = v;
 }
 
+// Counting runs: ctrl->touched += the number of set flags among f[0, m).
+__global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__ f, int64_t m, Ctrl* ctrl) {
+    __shared__ uint32_t s_w[4];
+    uint32_t cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        cnt += f[i] != 0;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&ctrl->touched, (unsigned long long)(s_w[0] + s_w[1] + s_w[2] + s_w[3]));
+}
+
 // The subtree root of a cloud is the internal node whose leaf range is
 // exactly the cloud's range of sorted positions.
 __global__ __launch_bounds__(256) void k_cloud_roots(const uint32_t* __restrict__ rlo, const uint32_t* __restrict__ rhi,
@@ -1682,7 +1693,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint4* __restric
     const float d = bitsf(s.z);
     edges[2 * o] = (int32_t)((int64_t)s.x - ci.off);
     edges[2 * o + 1] = (int32_t)((int64_t)s.y - ci.off);
-    w[o] = sqrtf(d);
+    w[o] = edge_weight(d);
     if (d2) d2[o] = d;
 }
 
@@ -1789,7 +1800,9 @@ static BatchLayout make_batch_layout(int64_t n, int64_t clouds) {
 
 using namespace emst;
 
-constexpr int kMaxVariant = 13;  // traversal variants 0 .. 13
+// traversal variants: 0, 5, 7, 8, 10, 11 and 13 (the default)
+constexpr uint32_t kVariants = (1u << 0) | (1u << 5) | (1u << 7) | (1u << 8) | (1u << 10) | (1u << 11) | (1u << 13);
+static inline bool variant_ok(int v) { return v >= 0 && v < 32 && ((kVariants >> v) & 1u); }
 
 struct emst_ctx {
     int device = 0;
@@ -1841,7 +1854,7 @@ extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_
     emst_ctx* ctx = new (std::nothrow) emst_ctx();
     if (!ctx) return EMST_ENOMEM;
     ctx->device = hip_device;
-    if (autotune_json && !ctx->tune.parse(autotune_json, kMaxVariant, nullptr)) {
+    if (autotune_json && !ctx->tune.parse(autotune_json, kVariants, nullptr)) {
         delete ctx;
         return EMST_EINVAL;
     }
@@ -1891,7 +1904,7 @@ extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
     return EMST_OK;
 }
 extern "C" int emst_set_traversal(emst_ctx* ctx, int variant) {
-    if (!ctx || variant < -1 || variant > kMaxVariant) return EMST_EINVAL;
+    if (!ctx || (variant != -1 && !variant_ok(variant))) return EMST_EINVAL;
     ctx->traversal = variant;
     return EMST_OK;
 }
@@ -1902,7 +1915,7 @@ extern "C" int emst_set_autotune(emst_ctx* ctx, const char* json) {
         ctx->tune.clear();
         return EMST_OK;
     }
-    if (!ctx->tune.parse(json, kMaxVariant, &ctx->err)) return EMST_EINVAL;
+    if (!ctx->tune.parse(json, kVariants, &ctx->err)) return EMST_EINVAL;
     return EMST_OK;
 }
 extern "C" int emst_get_autotune(const emst_ctx* ctx, char* buf, size_t cap, size_t* len) {
@@ -2021,13 +2034,14 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     TraverseArgs<DIM> ta;
     ta.spts = b.spts; ta.labels = b.labels; ta.orig = b.orig; ta.ub = b.ub; ta.recs = b.recs; ta.root = root;
     ta.n = n; ta.cand_d = b.cand_d; ta.cand_j = b.cand_j; ta.compkey = b.compkey; ta.compmax = b.compmax;
-    ta.ctrl = b.ctrl; ta.first = true; ta.leaf_parent = b.leaf_parent; ta.up = b.up;
+    ta.ctrl = b.ctrl; ta.first = true; ta.up = b.up;
     ta.cloud_of = nullptr; ta.cloud_root = nullptr; ta.lab2 = b.lab2;
     ta.wave_lca = reinterpret_cast<const uint32_t*>(b.exch);  // the build's exchange words are free by now
     ta.core_s = nullptr;
     ta.core_o = nullptr;
     ta.pos = b.pos;
     ta.qlist = nullptr;
+    ta.touched = nullptr;
     return ta;
 }
 
@@ -2053,10 +2067,45 @@ static inline bool uses_qlist(int variant, int round, int64_t n) {
     return variant == 13 && round >= 2 && n >= kQlistMinN;
 }
 
+// Test hook support (emst_test_round): the state of a round between stage
+// B and the merge, per point in input order.
+struct RoundCapture {
+    float* bound;       // bound of the point's component
+    float* cand_d;      // the point's candidate D, +inf if none
+    int32_t* cand_j;    // its original index, -1 if none
+    float* comp_d2;     // the component's edge (D, u, v), D = +inf if none
+    int32_t* comp_u;
+    int32_t* comp_v;
+};
+
+__global__ __launch_bounds__(256) void k_test_capture(const uint32_t* __restrict__ labels,
+                                                      const uint32_t* __restrict__ orig,
+                                                      const uint32_t* __restrict__ ub,
+                                                      const uint32_t* __restrict__ cand_d,
+                                                      const uint32_t* __restrict__ cand_j,
+                                                      const uint64_t* __restrict__ compkey,
+                                                      const uint32_t* __restrict__ compmax, int64_t n,
+                                                      RoundCapture cap) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t o = orig[p], c = labels[p];
+    cap.bound[o] = bitsf(ub[c]);
+    const uint32_t j = cand_j[p];
+    cap.cand_d[o] = j == kNone ? INFINITY : bitsf(cand_d[p]);
+    cap.cand_j[o] = j == kNone ? -1 : (int32_t)j;
+    const uint64_t key = compkey[c];
+    const uint32_t v = compmax[c];
+    const bool has = key != kKeyMax && v != kNone;
+    cap.comp_d2[o] = has ? bitsf((uint32_t)(key >> 32)) : INFINITY;
+    cap.comp_u[o] = has ? (int32_t)(uint32_t)key : -1;
+    cap.comp_v[o] = has ? (int32_t)v : -1;
+}
+
 // One Boruvka round, enqueued on st (no host wait).
 template <int DIM>
 int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int round, int height,
-                  int variant, const uint32_t* cloud_of, int64_t target, bool prof, hipStream_t st) {
+                  int variant, const uint32_t* cloud_of, int64_t target, bool prof, hipStream_t st,
+                  const RoundCapture* cap = nullptr) {
     hipEvent_t* E = ctx->ev;
     // record labels and bounds; the run partials of round r > 0 come from
     // the relabel kernel of round r - 1
@@ -2082,15 +2131,27 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
         HIP_TRY(hipGetLastError());
         ta.qlist = b.qlist;
     }
+    // counting runs: the query flags (dead once the list is written) mark
+    // the node records this round's searches load
+    ta.touched = nullptr;
+    const int64_t words = (n - 1 + 3) / 4;
+    if (ctx->counting) {
+        k_fill_u32<<<grid_for(words), 256, 0, st>>>(reinterpret_cast<uint32_t*>(b.qflag), words, 0u);
+        ta.touched = b.qflag;
+    }
     if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
     HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
     if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
+    if (ctx->counting) k_count_flags<<<std::min<unsigned>(grid_for(n - 1), 1024), 256, 0, st>>>(b.qflag, n - 1, b.ctrl);
     if (round == 1)
         k_resolve<1><<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
                                                   b.ctrl);
     else if (round > 1)
         k_resolve<4><<<grid_for((n + 3) / 4), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey,
                                                             b.compmax, n, b.ctrl);
+    if (cap)
+        k_test_capture<<<grid_for(n), 256, 0, st>>>(b.labels, b.orig, b.ub, b.cand_d, b.cand_j, b.compkey,
+                                                    b.compmax, n, *cap);
     // root lists: segments in the Morton key buffers (free during the
     // rounds), counts behind k_merge_parent's partials in bpart
     const int mp_blocks = root_list_blocks(n);
@@ -2129,6 +2190,9 @@ int finish_round(emst_ctx* ctx, const Ctrl* h, int round, int64_t target, int64_
         S.child_tests = it;
         S.leaf_tests = lt;
         S.dist_evals = (int64_t)h->dist_evals;
+        int64_t before = 0;
+        for (int r = 0; r < round; ++r) before += S.records_touched_round[r];
+        S.records_touched_round[round] = (int64_t)h->touched - before;
     }
     const int64_t next = h->ncomp_next;
     if (next >= ncomp || next < target) return fail(ctx, EMST_EINTERNAL, "round made no progress");
@@ -3105,7 +3169,190 @@ __global__ __launch_bounds__(256) void k_test_boxes(const Rec<3>* __restrict__ r
     }
 }
 
+// emst_test_round: the smallest sorted position of every component
+// (rep[c], initialised to kNone) ...
+__global__ __launch_bounds__(256) void k_test_reps(const int32_t* __restrict__ comp,
+                                                   const uint32_t* __restrict__ orig, int64_t n, uint32_t* rep) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) atomicMin(&rep[comp[orig[p]]], (uint32_t)p);
+}
+
+// ... becomes the label of its points, and every component starts the
+// round as k_merge_parent leaves a root (no bound, no key, no edge).  Every
+// point starts with its own index as its last candidate, which lies in its
+// own component, so no earlier result is reused.
+__global__ __launch_bounds__(256) void k_test_labels(const int32_t* __restrict__ comp,
+                                                     const uint32_t* __restrict__ orig,
+                                                     const uint32_t* __restrict__ rep, int64_t n,
+                                                     uint32_t* __restrict__ labels, uint32_t* __restrict__ ub,
+                                                     uint64_t* __restrict__ compkey, uint32_t* __restrict__ compmax,
+                                                     uint32_t* __restrict__ cand_d, uint32_t* __restrict__ cand_j) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t o = orig[p];
+    const uint32_t l = rep[comp[o]];
+    labels[p] = l;
+    cand_j[p] = o;
+    cand_d[p] = 0u;
+    if (l == (uint32_t)p) {
+        ub[p] = kInfBits;
+        compkey[p] = kKeyMax;
+        compmax[p] = kNone;
+    }
+}
+
+// The root list a round starts from: segment b holds, in ascending order,
+// the roots among positions [b * cap, (b + 1) * cap).
+__global__ __launch_bounds__(256) void k_test_root_list(const uint32_t* __restrict__ labels, int64_t n, RootList rl) {
+    __shared__ uint32_t s_w[4];
+    const int64_t lo = (int64_t)blockIdx.x * rl.cap;
+    const int64_t hi = std::min<int64_t>(lo + rl.cap, n);
+    uint32_t* seg = const_cast<uint32_t*>(rl.in) + rl.cap * blockIdx.x;
+    uint32_t at = 0;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    for (int64_t base = lo; base < hi; base += 256) {
+        const int64_t p = base + threadIdx.x;
+        const bool root = p < hi && labels[p] == (uint32_t)p;
+        const uint64_t m = __ballot(root);
+        if (lane == 0) s_w[w] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = at;
+        for (int k = 0; k < w; ++k) before += s_w[k];
+        if (root) seg[before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)p;
+        at += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) const_cast<uint32_t*>(rl.cnt_in)[blockIdx.x] = at;
+}
+
+// The component of every point after the round: the original index of its
+// root point.
+__global__ __launch_bounds__(256) void k_test_comp_out(const uint32_t* __restrict__ labels,
+                                                       const uint32_t* __restrict__ orig, int64_t n,
+                                                       int32_t* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) out[orig[p]] = (int32_t)orig[labels[p]];
+}
+
+template <int DIM>
+int test_round(emst_ctx* ctx, const float* pts, int64_t n, const int32_t* comp, int round, int variant,
+               const RoundCapture& cap, int32_t* comp_out, int64_t* ncomp_out, char* ws, hipStream_t st) {
+    // the tree of emst_build (the phases up to the boxes, without round 0)
+    Job j = make_job(ctx, pts, n, DIM, ws, nullptr, nullptr, nullptr, 0, nullptr, true, ctx->h_ctrl, false);
+    j.variant = variant;
+    if (int rc = job_run<DIM>(ctx, j, st)) return rc;
+    const Layout L = make_layout(n, DIM);
+    Bufs<DIM> b = carve<DIM>(ws, L);
+    TraverseArgs<DIM> ta = job_args<DIM>(j, b);
+    k_fill_u32<<<grid_for(n), 256, 0, st>>>(b.succ, n, kNone);
+    k_test_reps<<<grid_for(n), 256, 0, st>>>(comp, b.orig, n, b.succ);
+    k_test_labels<<<grid_for(n), 256, 0, st>>>(comp, b.orig, b.succ, n, b.labels, b.ub, b.compkey, b.compmax,
+                                               b.cand_d, b.cand_j);
+    k_run_partials<<<run_tiles(n), 256, 0, st>>>(b.labels, n, b.run_part);
+    RootList rl;
+    uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(b.k0), reinterpret_cast<uint32_t*>(b.k1)};
+    uint32_t* counts = b.bpart + 4 * kPartBlocks;
+    rl.in = lists[round & 1];
+    rl.cnt_in = counts + kPartBlocks * (round & 1);
+    rl.out = lists[(round + 1) & 1];
+    rl.cnt_out = counts + kPartBlocks * ((round + 1) & 1);
+    rl.cap = root_list_cap(n);
+    k_test_root_list<<<root_list_blocks(n), 256, 0, st>>>(b.labels, n, rl);
+    HIP_TRY(hipGetLastError());
+    if (int rc = enqueue_round<DIM>(ctx, b, ta, n, round, j.height, variant, nullptr, 1, false, st, &cap)) return rc;
+    k_test_comp_out<<<grid_for(n), 256, 0, st>>>(b.labels, b.orig, n, comp_out);
+    HIP_TRY(hipGetLastError());
+    if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
+    const Ctrl* h = ctx->h_ctrl;
+    if (h->error & kErrStack) return fail(ctx, EMST_EINTERNAL, "traversal stack overflow");
+    if (h->error & kErrJump) return fail(ctx, EMST_EINTERNAL, "component merge did not converge");
+    if (h->error) return fail(ctx, EMST_EINTERNAL, "a component found no outgoing edge");
+    *ncomp_out = (int64_t)h->ncomp_next;
+    return EMST_OK;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_test_distances(const float* __restrict__ a, const float* __restrict__ b,
+                                                        int64_t m, float* __restrict__ sq, float* __restrict__ box,
+                                                        float* __restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    float p[DIM], q[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        p[k] = a[i * DIM + k];
+        q[k] = b[i * DIM + k];
+    }
+    const float d = sqdist<DIM>(p, q);
+    sq[i] = d;
+    box[i] = boxdist<DIM>(p, q, q);
+    w[i] = edge_weight(d);
+}
+
+__global__ __launch_bounds__(256) void k_test_weights(uint32_t first, int64_t count, float* __restrict__ w) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) w[k] = edge_weight(bitsf(first + (uint32_t)k));
+}
+
 }  // namespace emst
+
+extern "C" int emst_test_distances(emst_ctx* ctx, const float* d_a, const float* d_b, int64_t m, int dim,
+                                   float* d_sq, float* d_box, float* d_w, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (m < 0 || (dim != 2 && dim != 3)) return fail(ctx, EMST_EINVAL, "bad m or dim");
+    if (m == 0) return EMST_OK;
+    if (!d_a || !d_b || !d_sq || !d_box || !d_w) return fail(ctx, EMST_EINVAL, "null pointer");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const unsigned grid = (unsigned)((m + 255) / 256);
+    if (dim == 3) k_test_distances<3><<<grid, 256, 0, st>>>(d_a, d_b, m, d_sq, d_box, d_w);
+    else k_test_distances<2><<<grid, 256, 0, st>>>(d_a, d_b, m, d_sq, d_box, d_w);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return EMST_OK;
+}
+
+extern "C" int emst_test_weights(emst_ctx* ctx, uint32_t first, int64_t count, float* d_w, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (count < 0 || (uint64_t)first + (uint64_t)count > (1ull << 32)) return fail(ctx, EMST_EINVAL, "bad range");
+    if (count == 0) return EMST_OK;
+    if (!d_w) return fail(ctx, EMST_EINVAL, "null pointer");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_test_weights<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(first, count, d_w);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return EMST_OK;
+}
+
+extern "C" int emst_test_round(emst_ctx* ctx, const float* d_points, int64_t n, int dim, const int32_t* d_comp,
+                               int32_t round, int32_t variant, float* d_bound, float* d_cand_d, int32_t* d_cand_j,
+                               float* d_comp_d2, int32_t* d_comp_u, int32_t* d_comp_v, int32_t* d_comp_out,
+                               int64_t* ncomp_out, void* d_workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 2 || n > 0x7FFFFFFFll || (dim != 2 && dim != 3)) return fail(ctx, EMST_EINVAL, "bad n or dim");
+    if (round < 1 || round > 63) return fail(ctx, EMST_EINVAL, "round must be in [1, 63]");
+    if (!variant_ok(variant)) return fail(ctx, EMST_EINVAL, "unknown traversal variant");
+    if (!d_points || !d_comp || !d_bound || !d_cand_d || !d_cand_j || !d_comp_d2 || !d_comp_u || !d_comp_v ||
+        !d_comp_out || !ncomp_out || !d_workspace)
+        return fail(ctx, EMST_EINVAL, "null pointer");
+    if (((uintptr_t)d_workspace & 255u) != 0) return fail(ctx, EMST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < emst_workspace_bytes(n, dim)) return fail(ctx, EMST_ENOMEM, "workspace too small");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const bool counting = ctx->counting;
+    ctx->counting = false;
+    RoundCapture cap{d_bound, d_cand_d, d_cand_j, d_comp_d2, d_comp_u, d_comp_v};
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int rc = dim == 3 ? test_round<3>(ctx, d_points, n, d_comp, round, variant, cap, d_comp_out, ncomp_out,
+                                            (char*)d_workspace, st)
+                            : test_round<2>(ctx, d_points, n, d_comp, round, variant, cap, d_comp_out, ncomp_out,
+                                            (char*)d_workspace, st);
+    ctx->counting = counting;
+    return rc;
+}
 
 extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes, int64_t n,
                                          const uint32_t* d_leaf_labels, int32_t* d_left, int32_t* d_right,

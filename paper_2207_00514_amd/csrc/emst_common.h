@@ -128,6 +128,11 @@ __device__ __forceinline__ float boxdist(const float* p, const float* lo, const 
     return s;
 }
 
+// The reported weight of an edge of squared length d2: its square root,
+// correctly rounded (the library is built with correctly rounded float32
+// square roots).
+__device__ __forceinline__ float edge_weight(float d2) { return sqrtf(d2); }
+
 // ---------------------------------------------------------------------------
 // atomics with explicit scope / ordering
 

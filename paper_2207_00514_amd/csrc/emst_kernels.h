@@ -21,7 +21,7 @@ struct Ctrl {
     unsigned long long internal_tests;
     unsigned long long leaf_tests;
     unsigned long long dist_evals;
-    unsigned long long trav_next;   // next query handed out by the persistent traversal
+    unsigned long long touched;     // counting runs: node records the traversals loaded, each once per round
     uint32_t long_ties;      // the edge order met a run of equal keys too long to fix in place
     uint32_t dup_codes;      // sorted positions whose Morton code equals the previous one
     uint32_t done;           // the round loop has reached its target: later round kernels return at once

@@ -117,7 +117,7 @@ struct Reader {
 
 }  // namespace
 
-bool TuneTable::parse(const char* json, int max_variant, std::string* err) {
+bool TuneTable::parse(const char* json, uint32_t valid_variants, std::string* err) {
     Reader r{json, {}};
     std::vector<TuneEntry> out;
     auto fail = [&](const std::string& why) {
@@ -171,7 +171,7 @@ bool TuneTable::parse(const char* json, int max_variant, std::string* err) {
                             ++r.p;
                         }
                         if (e.batched < 0 || (e.dim != 2 && e.dim != 3) || e.n_min < 0 || e.variant < 0 ||
-                            e.variant > max_variant)
+                            e.variant > 31 || !((valid_variants >> e.variant) & 1u))
                             return fail("every entry needs mode, dim in {2, 3}, n_min >= 0 and a valid variant");
                         out.push_back(e);
                         r.ws();

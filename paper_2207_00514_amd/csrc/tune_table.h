@@ -23,9 +23,10 @@ public:
     // Replace the table by the entries of a JSON document
     //   {"entries": [{"mode": "single"|"batched", "dim": 2|3,
     //                 "n_min": <int >= 0>, "variant": <int>}, ...]}
-    // (other keys are ignored).  Returns false, leaving the table as it
-    // was, on malformed input or out-of-range values; `err` says why.
-    bool parse(const char* json, int max_variant, std::string* err);
+    // (other keys are ignored).  A variant v is valid if bit v of
+    // `valid_variants` is set.  Returns false, leaving the table as it was,
+    // on malformed input or out-of-range values; `err` says why.
+    bool parse(const char* json, uint32_t valid_variants, std::string* err);
     void clear() { entries_.clear(); }
     // The variant of the entry with the largest n_min <= n for (batched,
     // dim), or `fallback` if there is none.

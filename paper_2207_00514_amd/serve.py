@@ -145,6 +145,65 @@ class Server:
                     r.done = t_done
 
 
+class FifoServer:
+    """The one-request-per-launch baseline: one worker thread solves the
+    queued requests one at a time, oldest first, each with its own
+    ``emst_build`` on one stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = device
+        self._ctx = Context(device)
+        self._stream = torch.cuda.Stream(device=device)
+        self._queue: collections.deque = collections.deque()
+        self._cv = threading.Condition()
+        self._closed = False
+        self._thread: Optional[threading.Thread] = None
+        self._served = 0
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request) -> None:
+        with self._cv:
+            req.arrival = self.now() if req.arrival == 0.0 else req.arrival
+            self._queue.append(req)
+            self._cv.notify()
+
+    def start(self) -> None:
+        self._thread = threading.Thread(target=self._run, daemon=True)
+        self._thread.start()
+
+    def close(self) -> None:
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        if self._thread:
+            self._thread.join()
+
+    def _run(self) -> None:
+        import torch
+        while True:
+            with self._cv:
+                while not self._queue and not self._closed:
+                    self._cv.wait()
+                if not self._queue and self._closed:
+                    return
+                r = self._queue.popleft()
+            r.start, r.batch = self.now(), self._served
+            self._served += 1
+            try:
+                with torch.cuda.stream(self._stream):
+                    pts = torch.from_numpy(r.points).to(f"cuda:{self.device}")
+                    e, w, d = self._ctx.build(pts, stream=self._stream)
+                    r.edges, r.weights, r.d2 = e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()
+                self._stream.synchronize()
+            except Exception as exc:  # a failing request fails alone
+                r.error = str(exc)
+            r.done = self.now()
+
+
 class SolverServer:
     """Round-granular continuous batching on the native solver
     (``emst_solver_*``): one driver thread admits every queued request that

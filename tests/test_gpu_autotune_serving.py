@@ -31,6 +31,12 @@ def same_tree(a, b):
             and np.array_equal(a[2].view(np.uint32), b[2].view(np.uint32)))
 
 
+def oracle_tree(pts):
+    """(edges, weights, d2) of the CPU oracle for one cloud."""
+    ref = oracle.emst(np.ascontiguousarray(pts, np.float32), threads=16)
+    return ref.edges, ref.w, ref.d2
+
+
 def test_autotune_table_round_trip_and_results():
     import paper_2207_00514_amd as emst
     from paper_2207_00514_amd import autotune
@@ -86,6 +92,7 @@ def test_autotune_bad_tables():
     for bad in ("{", '{"entries": [{"mode": "x", "dim": 3, "n_min": 0, "variant": 7}]}',
                 '{"entries": [{"mode": "single", "dim": 4, "n_min": 0, "variant": 7}]}',
                 '{"entries": [{"mode": "single", "dim": 3, "n_min": 0, "variant": 99}]}',
+                '{"entries": [{"mode": "single", "dim": 3, "n_min": 0, "variant": 12}]}',
                 '{"entries": []} trailing'):
         with pytest.raises(emst.EmstError) as ei:
             ctx.set_autotune(bad)
@@ -97,10 +104,24 @@ def test_autotune_bad_tables():
     assert json.loads(ctx.get_autotune()) == {"entries": []}
 
 
+def test_only_the_offered_traversal_shapes_are_accepted():
+    import paper_2207_00514_amd as emst
+    ctx = emst.Context(0)
+    for v in (-1, 0, 5, 7, 8, 10, 11, 13):
+        ctx.set_traversal(v)
+    for v in (-2, 1, 2, 3, 4, 6, 9, 12, 14, 31, 32):
+        with pytest.raises(emst.EmstError) as ei:
+            ctx.set_traversal(v)
+        assert ei.value.name == "EMST_EINVAL"
+
+
 def test_serving_results_equal_alone_and_in_the_mix():
     import paper_2207_00514_amd as emst
     from paper_2207_00514_amd import serve
     sizes = np.clip(W.request_sizes(48, seed=51), 500, 40_000).astype(int)
+    # one request above the query-list threshold (3 * 2^18 points), so a
+    # batch holding it runs the list rounds
+    sizes[20] = 900_000
     reqs = [serve.Request(rid=i, points=W.request_cloud(int(n), seed=1000 + i)) for i, n in enumerate(sizes)]
     rng = np.random.default_rng(52)
     arrivals = np.cumsum(rng.exponential(0.002, len(reqs))).tolist()
@@ -110,11 +131,10 @@ def test_serving_results_equal_alone_and_in_the_mix():
     assert len({r.batch for r in reqs}) < len(reqs), "no request was batched with another"
     alone = emst.Context(0)
     for r in reqs:
+        print(f"request {r.rid} n={len(r.points)}", flush=True)
         solo = host(alone.build(dev(r.points)))
         assert same_tree((r.edges, r.weights, r.d2), solo), f"request {r.rid}"
-    for r in reqs[:4]:
-        ref = oracle.emst(r.points, threads=8)
-        assert np.array_equal(r.edges, ref.edges)
+        assert same_tree((r.edges, r.weights, r.d2), oracle_tree(r.points)), f"request {r.rid} vs oracle"
 
 
 def test_serving_rejects_a_request_over_its_share():
@@ -144,10 +164,12 @@ def test_solver_round_granular_admission_equals_alone():
     import paper_2207_00514_amd as emst
     ctx = emst.Context(0)
     alone = emst.Context(0)
-    solver = emst.Solver(ctx, 256 << 20, max_slots=16)
+    solver = emst.Solver(ctx, 512 << 20, max_slots=16)
     clouds = [W.small_random(n, d, 70 + i, k) for i, (n, d, k) in enumerate(
         [(3000, 3, "uniform"), (20000, 2, "uniform"), (1, 3, "uniform"), (0, 2, "uniform"),
          (5000, 3, "dup"), (40000, 3, "outlier"), (2, 2, "int"), (12000, 3, "int")])]
+    # a request above the query-list threshold (3 * 2^18 points) joins too
+    clouds.append(W.clustered3d(800_000, seed=79))
     first = [solver.admit(dev(c), tag=i) for i, c in enumerate(clouds[:4])]
     assert None not in first
     solver.step()
@@ -164,6 +186,7 @@ def test_solver_round_granular_admission_equals_alone():
             assert got[0].shape == (0, 2)
             continue
         assert same_tree(got, host(alone.build(dev(c)))), f"cloud {i}"
+        assert same_tree(got, oracle_tree(c)), f"cloud {i} vs oracle"
     solver.close()
 
 
@@ -211,3 +234,4 @@ def test_solver_server_results_equal_alone():
     alone = emst.Context(0)
     for r in reqs:
         assert same_tree((r.edges, r.weights, r.d2), host(alone.build(dev(r.points)))), f"request {r.rid}"
+        assert same_tree((r.edges, r.weights, r.d2), oracle_tree(r.points)), f"request {r.rid} vs oracle"
