@@ -264,6 +264,13 @@ typedef struct emst_stats {
 /* Time every phase with HIP events (adds synchronisation; off by default). */
 int emst_set_profiling(emst_ctx *ctx, int on);
 
+/* Batches (emst_build_batched): run the rounds from the third on as replays
+ * of a captured graph of two rounds, with one control-block read-back per
+ * replay instead of one per round (off by default; profiling and counting
+ * runs never use it).  The context keeps the last few instantiated graphs,
+ * keyed by workspace, sizes and traversal shape.  Same results either way. */
+int emst_set_graphs(emst_ctx *ctx, int on);
+
 /* Use the instrumented traversal that counts child-box tests and leaf
  * distance evaluations (same result, slower; off by default). */
 int emst_set_counting(emst_ctx *ctx, int on);

@@ -36,7 +36,7 @@ EXPORTS = [
     "emst_core_distances", "emst_build_mreach", "emst_set_autotune", "emst_get_autotune",
     "emst_solver_slot_bytes", "emst_solver_create", "emst_solver_destroy", "emst_solver_admit",
     "emst_solver_step", "emst_solver_poll", "emst_solver_take",
-    "emst_test_round", "emst_test_distances", "emst_test_weights",
+    "emst_test_round", "emst_test_distances", "emst_test_weights", "emst_set_graphs",
 ]
 
 
@@ -103,7 +103,7 @@ def lib():
         L.emst_build_mreach.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, vp]
         L.emst_build_mreach.restype = i32
         L.emst_build.restype = i32
-        for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal"):
+        for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_set_graphs"):
             getattr(L, f).argtypes = [vp, i32]
             getattr(L, f).restype = i32
         L.emst_set_autotune.argtypes = [vp, ctypes.c_char_p]
@@ -196,6 +196,10 @@ class Context:
 
     def set_profiling(self, on: bool = True):
         self._check(lib().emst_set_profiling(self._h, int(bool(on))))
+
+    def set_graphs(self, on: bool = True):
+        """Batches: replay captured pairs of rounds (see emst_set_graphs)."""
+        self._check(lib().emst_set_graphs(self._h, int(bool(on))))
 
     def set_counting(self, on: bool = True):
         self._check(lib().emst_set_counting(self._h, int(bool(on))))

@@ -147,7 +147,7 @@ __global__ void k_init_ctrl(Ctrl* ctrl) {
         ctrl->ncomp_next = 0; ctrl->edge_count = 0; ctrl->error = 0;
         ctrl->key_or = 0ull; ctrl->key_and = ~0ull;
         ctrl->internal_tests = 0; ctrl->leaf_tests = 0; ctrl->dist_evals = 0; ctrl->touched = 0;
-        ctrl->long_ties = 0; ctrl->dup_codes = 0; ctrl->done = 0;
+        ctrl->long_ties = 0; ctrl->dup_codes = 0; ctrl->done = 0; ctrl->rounds_run = 0;
     }
 }
 
@@ -761,6 +761,15 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
     __shared__ uint32_t s_w[8];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
+    // the leaf ranges of the tile's records, loaded before the label scans
+    // so that their latency overlaps the scans
+    uint32_t rl[kRunPer], rh[kRunPer];
+#pragma unroll
+    for (int q = 0; q < kRunPer; ++q) {
+        const int64_t k = base + q * 256 + tid;
+        rl[q] = k < n - 1 ? rlo[k] : 0u;
+        rh[q] = k < n - 1 ? rhi[k] : 0u;
+    }
     for (int x = tid; x < kRunTile + 2; x += 256) {
         int64_t p = base + x - 1;
         p = p < 0 ? 0 : (p >= n ? n - 1 : p);
@@ -821,7 +830,7 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
         const int x = q * 256 + tid;
         const int64_t k = base + x;
         if (k < n - 1) {
-            const uint32_t lo = rlo[k], hi = rhi[k];
+            const uint32_t lo = rl[q], hi = rh[q];
             bool left, right;
             if (FIRST) {
                 left = lo == (uint32_t)k;
@@ -1336,6 +1345,7 @@ __global__ __launch_bounds__(256) void k_relabel(uint32_t* labels, const uint32_
             e = s_w[4] + s_w[5] + s_w[6] + s_w[7];
             ctrl->ncomp_next = r;
             ctrl->edge_count += e;
+            ctrl->rounds_run += 1u;
             // the loop ends here (or stops on an error)
             if ((int64_t)r <= target || ctrl->error) ctrl->done = 1u;
         }
@@ -1818,6 +1828,21 @@ struct emst_ctx {
     hipEvent_t sev[2] = {nullptr, nullptr};  // completion of the control copies of two rounds in flight
     void* h_stage = nullptr;       // pinned host staging for per-cloud tables
     size_t h_stage_bytes = 0;
+    // captured round pairs of batches (emst_set_graphs): a few instantiated
+    // graphs, keyed by everything their launches bake in
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;
+    struct GraphEntry {
+        const void* ws;
+        int64_t n, target;
+        int variant, height;
+        const void* cloud_of;
+        uint32_t root;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    std::vector<GraphEntry> gcache;
+    uint64_t gclock = 0;
 };
 
 // Pinned host memory of at least `bytes` (host memory only; the library
@@ -1878,6 +1903,8 @@ extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_
 
 extern "C" void emst_destroy(emst_ctx* ctx) {
     if (!ctx) return;
+    for (auto& g : ctx->gcache) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     for (auto& e : ctx->sev)
         if (e) (void)hipEventDestroy(e);
@@ -1896,6 +1923,11 @@ extern "C" size_t emst_workspace_bytes(int64_t n, int dim) {
 extern "C" int emst_set_profiling(emst_ctx* ctx, int on) {
     if (!ctx) return EMST_EINVAL;
     ctx->profiling = on != 0;
+    return EMST_OK;
+}
+extern "C" int emst_set_graphs(emst_ctx* ctx, int on) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->graphs = on != 0;
     return EMST_OK;
 }
 extern "C" int emst_set_counting(emst_ctx* ctx, int on) {
@@ -2201,27 +2233,156 @@ int finish_round(emst_ctx* ctx, const Ctrl* h, int round, int64_t target, int64_
 }
 
 // Boruvka rounds until the component count reaches `target` (the number of
-// non-empty clouds of a batch).
+// non-empty clouds of a batch).  As for one cloud (job_rounds), round r + 1
+// is queued before round r is read back, while the shrink of the last
+// round predicts that round r leaves components beyond the target; a round
+// queued past the end finds `done` raised and returns at once.
+// A graph of two consecutive rounds (an even one and the next) from the
+// third round on: those rounds launch the same kernels with the same
+// arguments, so one graph serves every pair.  Instantiated graphs are kept
+// per context (at most kGraphCache, least recently used replaced).
+constexpr int kGraphCache = 4;
+template <int DIM>
+int round_pair_graph(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int64_t target, int height,
+                     int variant, const uint32_t* cloud_of, hipGraphExec_t* out) {
+    ++ctx->gclock;
+    for (auto& g : ctx->gcache)
+        if (g.ws == (const void*)b.ctrl && g.n == n && g.target == target && g.variant == variant &&
+            g.height == height && g.cloud_of == (const void*)cloud_of && g.root == ta.root) {
+            g.used = ctx->gclock;
+            *out = g.exec;
+            return EMST_OK;
+        }
+    if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_round<DIM>(ctx, b, ta, n, 2, height, variant, cloud_of, target, false, ctx->cap_stream);
+    if (rc == EMST_OK)
+        rc = enqueue_round<DIM>(ctx, b, ta, n, 3, height, variant, cloud_of, target, false, ctx->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ec != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(ei));
+    if ((int)ctx->gcache.size() >= kGraphCache) {
+        auto old = std::min_element(ctx->gcache.begin(), ctx->gcache.end(),
+                                    [](const emst_ctx::GraphEntry& x, const emst_ctx::GraphEntry& y) {
+                                        return x.used < y.used;
+                                    });
+        (void)hipGraphExecDestroy(old->exec);
+        ctx->gcache.erase(old);
+    }
+    ctx->gcache.push_back({(const void*)b.ctrl, n, target, variant, height, (const void*)cloud_of, ta.root, exec,
+                           ctx->gclock});
+    *out = exec;
+    return EMST_OK;
+}
+
+// Rounds 2, 3, ... as replays of the captured pair, the next replay queued
+// before the last one is read back while more rounds are predicted.  A
+// replay past the end returns at once (`done`).  Per-round statistics are
+// kept only at pair boundaries; the round count comes from the device.
+template <int DIM>
+int graph_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int64_t target, int height,
+                 int variant, const uint32_t* cloud_of, emst_stats& S, int64_t ncomp, hipStream_t st) {
+    hipGraphExec_t exec = nullptr;
+    if (int rc = round_pair_graph<DIM>(ctx, b, ta, n, target, height, variant, cloud_of, &exec)) return rc;
+    Ctrl* mirror[2] = {ctx->h_ctrl, ctx->h_ctrl + 1};
+    auto launch = [&](int k) -> int {
+        HIP_TRY(hipGraphLaunch(exec, st));
+        HIP_TRY(hipMemcpyAsync(mirror[k & 1], b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(ctx->sev[k & 1], st));
+        return EMST_OK;
+    };
+    if (int rc = launch(0)) return rc;
+    int queued = 0;
+    int64_t prev = 0;
+    for (int k = 0; 2 + 2 * k < 64; ++k) {
+        // components after this pair, predicted from the last one's shrink
+        const bool more = prev == 0 || (double)ncomp * (double)ncomp >= 2.0 * (double)prev * (double)target;
+        if (queued == k && more) {
+            if (int rc = launch(k + 1)) return rc;
+            queued = k + 1;
+        }
+        HIP_TRY(hipEventSynchronize(ctx->sev[k & 1]));
+        const Ctrl* h = mirror[k & 1];
+        S.components[2 + 2 * k] = ncomp;
+        prev = ncomp;
+        if (int rc = finish_round(ctx, h, 2 + 2 * k, target, ncomp, S)) {
+            (void)hipStreamSynchronize(st);
+            return rc;
+        }
+        if (ncomp <= target) {
+            HIP_TRY(hipStreamSynchronize(st));
+            *ctx->h_ctrl = *h;
+            S.rounds = (int32_t)h->rounds_run;
+            S.traversal_launches = S.rounds;
+            S.traversal_variant = variant;
+            return EMST_OK;
+        }
+        if (queued == k) {
+            if (int rc = launch(k + 1)) return rc;
+            queued = k + 1;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    return fail(ctx, EMST_EINTERNAL, "too many rounds");
+}
+
 template <int DIM>
 int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, int64_t target, int height,
                int variant, const uint32_t* cloud_of, emst_stats& S, hipStream_t st) {
     const bool prof = ctx->profiling && ctx->ev_ok;
-    int64_t ncomp = n;
-    int round = 0;
-    while (ncomp > target) {
+    // with graphs, rounds from the third on run as replays of a captured
+    // pair, each followed by one read-back
+    const bool graphs = ctx->graphs && !prof && !ctx->counting;
+    Ctrl* mirror[2] = {ctx->h_ctrl, ctx->h_ctrl + 1};
+    auto queue = [&](int r) -> int {
+        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, r, height, variant, cloud_of, target, prof, st)) return rc;
+        HIP_TRY(hipMemcpyAsync(mirror[r & 1], b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(ctx->sev[r & 1], st));
+        return EMST_OK;
+    };
+    int64_t ncomp = n, prev = 0;
+    int queued = -1;
+    for (int round = 0;; ++round) {
         if (round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
+        if (graphs && round == 2) return graph_rounds<DIM>(ctx, b, ta, n, target, height, variant, cloud_of, S,
+                                                           ncomp, st);
+        if (queued < round) {
+            if (int rc = queue(round)) return rc;
+            queued = round;
+        }
+        // components entering round + 1, predicted from the last shrink
+        const bool more = prev == 0 || (double)ncomp * (double)ncomp >= 2.0 * (double)prev * (double)target;
+        if (more && round + 1 < 64 && !(graphs && round + 1 == 2)) {
+            if (int rc = queue(round + 1)) return rc;
+            queued = round + 1;
+        }
+        HIP_TRY(hipEventSynchronize(ctx->sev[round & 1]));
+        const Ctrl* h = mirror[round & 1];
         S.components[round] = ncomp;
-        if (int rc = enqueue_round<DIM>(ctx, b, ta, n, round, height, variant, cloud_of, target, prof, st))
+        S.queries_round[round] = uses_qlist(variant, round, n) ? (int64_t)h->qcount : n;
+        prev = ncomp;
+        if (int rc = finish_round(ctx, h, round, target, ncomp, S)) {
+            (void)hipStreamSynchronize(st);
             return rc;
-        if (int rc = read_ctrl(ctx, b.ctrl, st)) return rc;
-        S.queries_round[round] = uses_qlist(variant, round, n) ? (int64_t)ctx->h_ctrl->qcount : n;
-        if (int rc = finish_round(ctx, ctx->h_ctrl, round, target, ncomp, S)) return rc;
-        ++round;
+        }
+        if (ncomp <= target) {
+            // a round queued beyond the last returned at once; wait for it
+            HIP_TRY(hipStreamSynchronize(st));
+            *ctx->h_ctrl = *h;
+            S.rounds = round + 1;
+            S.traversal_launches = round + 1;
+            S.traversal_variant = variant;
+            return EMST_OK;
+        }
     }
-    S.rounds = round;
-    S.traversal_launches = round;
-    S.traversal_variant = variant;
-    return EMST_OK;
 }
 
 // Canonical edge order over the n component slots (the slots of the final

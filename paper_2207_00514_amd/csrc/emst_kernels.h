@@ -26,7 +26,8 @@ struct Ctrl {
     uint32_t dup_codes;      // sorted positions whose Morton code equals the previous one
     uint32_t done;           // the round loop has reached its target: later round kernels return at once
     uint32_t qcount;         // length of this round's query list
-    uint32_t pad[2];
+    uint32_t rounds_run;     // rounds that ran before the loop reached its target
+    uint32_t pad;
 };
 
 constexpr uint32_t kErrStack = 1u;

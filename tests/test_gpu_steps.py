@@ -113,10 +113,34 @@ def partitions(pts, seed):
             yield f"boruvka{r}", p
 
 
-def check_round(pts, comp, got, shared_bound=False):
+_BRUTE = {}
+
+
+def brute(pts, comp, key=None):
+    """D bits of all pairs and the (D, j)-nearest outside point of every
+    point, cached per case."""
+    if key is not None and key in _BRUTE:
+        return _BRUTE[key]
+    D = bits(oracle.pair_d2_matrix(pts))
+    d2, j = oracle.nearest_other_bruteforce(pts, comp)
+    if key is not None:
+        _BRUTE[key] = (D, d2, j)
+    return D, d2, j
+
+
+_PARTS = {}
+
+
+def cached_partitions(pts, seed, key):
+    if key not in _PARTS:
+        _PARTS[key] = [(name, np.asarray(c)) for name, c in partitions(pts, seed) if len(np.unique(c)) >= 2]
+    return _PARTS[key]
+
+
+def check_round(pts, comp, got, shared_bound=False, key=None):
     n = len(pts)
     comp = np.asarray(comp)
-    D = bits(oracle.pair_d2_matrix(pts))
+    D, d2, j = brute(pts, comp, key)
     same = comp[:, None] == comp[None, :]
     out_min = np.where(same, BIG, D).min(axis=1)          # per point: shortest D leaving its component
     bound = bits(host(got["bound"]))
@@ -132,7 +156,6 @@ def check_round(pts, comp, got, shared_bound=False):
         leaving = np.where(same[m], BIG, D[m])
         assert (leaving == b[0]).any(), f"component {c}: bound is not the length of a leaving pair"
     # candidate: the (D, j)-nearest outside point, if within the bound
-    d2, j = oracle.nearest_other_bruteforce(pts, comp)
     cj = host(got["cand_j"])
     cd = bits(host(got["cand_d"]))
     if not shared_bound:
@@ -174,14 +197,12 @@ CASES = [(n, dim, seed) for n, dim, seed in ((3, 2, 1), (64, 3, 2), (257, 2, 3),
 def test_one_round_steps(ctx, n, dim, seed, variant):
     kinds = ("uniform", "int", "dup", "outlier")
     pts = W.small_random(n, dim, seed, kinds[seed % 4])
-    for name, comp in partitions(pts, seed):
-        if len(np.unique(comp)) < 2:
-            continue
+    for name, comp in cached_partitions(pts, seed, (n, dim, seed)):
         for rnd in (1, 2):
             print(f"case n={n} dim={dim} seed={seed} variant={variant} partition={name} round={rnd}", flush=True)
             got = ctx.test_round(dev(pts), torch.from_numpy(comp.astype(np.int32)), rnd, variant)
             torch.cuda.synchronize()
-            check_round(pts, comp, got, shared_bound=variant == 11)
+            check_round(pts, comp, got, shared_bound=variant == 11, key=(n, dim, seed, name))
 
 
 def test_one_round_steps_on_ties(ctx):
