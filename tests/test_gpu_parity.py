@@ -356,6 +356,37 @@ def test_batched_equals_solo(ctx):
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), f"cloud {c}"
 
 
+def test_batched_graph_replays_equal_eager(ctx):
+    """Rounds from the third on replayed from a captured graph (one per
+    context, reused across calls): several calls in a row, with eager work of
+    another context and synchronisations between them, each equal to the
+    eager batched result, then a second shape (a new capture)."""
+    import paper_2207_00514_amd as emst
+    g = emst.Context(0)
+    g.set_graphs(True)
+    other = emst.Context(0)
+    for shape in range(2):
+        clouds = W.batched_clouds(n_clouds=48 if shape == 0 else 12, seed=81 + shape, lo=2000, hi=60_000)
+        ctx.set_traversal(-1)
+        ref = run_batched(ctx, clouds)
+        for rep in range(4):
+            print(f"graph replay shape={shape} rep={rep}", flush=True)
+            got = run_batched(g, clouds)
+            for c, (a, b) in enumerate(zip(got, ref)):
+                for x, y in zip(a, b):
+                    assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), f"shape {shape} rep {rep} cloud {c}"
+            assert g.stats()["rounds"] == ctx.stats()["rounds"]
+            pts = W.small_random(3000, 3, 90 + rep)
+            assert_same(run(other, pts), oracle.prim(pts), "eager work between replays")
+    # a batch large enough for the query-list rounds
+    clouds = W.batched_clouds(n_clouds=20, seed=83, lo=40_000, hi=80_000)
+    ref = run_batched(ctx, clouds)
+    for rep in range(2):
+        got = run_batched(g, clouds)
+        for c, (a, b) in enumerate(zip(got, ref)):
+            assert all(np.array_equal(x.view(np.uint8), y.view(np.uint8)) for x, y in zip(a, b)), f"cloud {c}"
+
+
 def test_batched_errors(ctx):
     import paper_2207_00514_amd as emst
     clouds = [W.small_random(100, 3, 1), W.small_random(50, 2, 2)]
