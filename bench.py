@@ -376,12 +376,13 @@ def batched_leg(args) -> dict:
     # autotune the traversal shape on this batch (untimed; every candidate
     # gives the same trees), then time the automatic choice
     ms = {}
-    for v in autotune.BATCHED_CANDIDATES:
-        ctx.set_traversal(v)
-        ms[v] = 1e3 * autotune._median_seconds(lambda: ctx.build_batched_flat(flat, sizes, dims), 2)
+    for shape in autotune.BATCHED_CANDIDATES:
+        autotune._set_shape(ctx, shape)
+        ms[shape] = 1e3 * autotune._median_seconds(lambda: ctx.build_batched_flat(flat, sizes, dims), 2)
     best = min(ms, key=ms.get)
-    ctx.set_autotune(autotune.table_json([{"mode": "batched", "dim": 3, "n_min": 0, "variant": int(best)}]))
-    ctx.set_traversal(-1)
+    ctx.set_autotune(autotune.table_json([{"mode": "batched", "dim": 3, "n_min": 0, "variant": int(best[0]),
+                                           "lds_depth": int(best[1])}]))
+    autotune._set_shape(ctx, (-1, 0))
     steps = max(args.steps, 3)
     for _ in range(max(args.warmup, 1)):
         ctx.build_batched_flat(flat, sizes, dims)
@@ -410,8 +411,8 @@ def batched_leg(args) -> dict:
                                  "ms": round(t_solo * 1e3, 3)},
         "speedup": round(t_solo / t_batched, 2),
         "equals_solo": bool(same),
-        "autotuned_variant": int(best),
-        "autotune_ms": {str(k): round(v, 3) for k, v in ms.items()},
+        "autotuned_shape": {"variant": int(best[0]), "lds_depth": int(best[1])},
+        "autotune_ms": {autotune._label(k): round(v, 3) for k, v in ms.items()},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -259,6 +259,9 @@ typedef struct emst_stats {
     int64_t records_touched_round[64];  /* counting only: distinct node
                                        records the traversal loaded in each
                                        round */
+    int32_t traversal_lds_depth;    /* LDS stack ring entries per lane of
+                                       variant 13 (0 for other variants) */
+    int32_t pad_;
 } emst_stats;
 
 /* Time every phase with HIP events (adds synchronisation; off by default). */
@@ -296,14 +299,22 @@ int emst_set_counting(emst_ctx *ctx, int on);
  * Returns EMST_EINVAL for any other value. */
 int emst_set_traversal(emst_ctx *ctx, int variant);
 
+/* LDS stack ring of variant 13: entries per lane kept in LDS (4, 8 or 16;
+ * deeper entries spill to private memory).  Deeper rings spill less but
+ * hold fewer waves per CU.  0 (the default) takes the depth from the
+ * autotune table entry of the call, else 8.  EMST_EINVAL for any other
+ * value.  Every depth gives the same result. */
+int emst_set_lds_depth(emst_ctx *ctx, int depth);
+
 /* Traversal-shape table (the autotuner's output), a JSON document
  *
  *   {"entries": [{"mode": "single" | "batched", "dim": 2 | 3,
- *                 "n_min": <points>, "variant": <0, 5, 7, 8, 10, 11 or 13>}, ...]}
+ *                 "n_min": <points>, "variant": <0, 5, 7, 8, 10, 11 or 13>,
+ *                 "lds_depth": <4, 8 or 16; optional, default 8>}, ...]}
  *
- * (other keys are ignored).  A call in auto mode (emst_set_traversal -1)
- * with n points uses the entry of its mode and dimension with the largest
- * n_min <= n.  NULL clears the table.  EMST_EINVAL on a malformed table,
+ * (other keys are ignored).  A call in auto mode (emst_set_traversal -1,
+ * emst_set_lds_depth 0) with n points uses the entry of its mode and
+ * dimension with the largest n_min <= n.  NULL clears the table.  EMST_EINVAL on a malformed table,
  * which then stays as it was.  Every variant gives the same result. */
 int emst_set_autotune(emst_ctx *ctx, const char *json);
 

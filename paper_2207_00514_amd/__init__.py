@@ -36,7 +36,8 @@ EXPORTS = [
     "emst_core_distances", "emst_build_mreach", "emst_set_autotune", "emst_get_autotune",
     "emst_solver_slot_bytes", "emst_solver_create", "emst_solver_destroy", "emst_solver_admit",
     "emst_solver_step", "emst_solver_poll", "emst_solver_take",
-    "emst_test_round", "emst_test_distances", "emst_test_weights", "emst_set_graphs",
+    "emst_test_round", "emst_test_distances", "emst_test_weights",
+    "emst_set_graphs", "emst_set_lds_depth",
 ]
 
 
@@ -59,6 +60,7 @@ class Stats(ctypes.Structure):
         ("leaf_tests_round", ctypes.c_int64 * 64), ("dist_evals", ctypes.c_int64),
         ("traversal_variant", ctypes.c_int32), ("rank_codes", ctypes.c_int32),
         ("queries_round", ctypes.c_int64 * 64), ("records_touched_round", ctypes.c_int64 * 64),
+        ("traversal_lds_depth", ctypes.c_int32), ("pad_", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -74,6 +76,7 @@ class Stats(ctypes.Structure):
             traversal_variant=self.traversal_variant, rank_codes=self.rank_codes,
             queries_round=list(self.queries_round[:r]),
             records_touched_round=list(self.records_touched_round[:r]),
+            traversal_lds_depth=self.traversal_lds_depth,
         )
 
 
@@ -103,7 +106,8 @@ def lib():
         L.emst_build_mreach.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, vp]
         L.emst_build_mreach.restype = i32
         L.emst_build.restype = i32
-        for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_set_graphs"):
+        for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_set_graphs",
+                  "emst_set_lds_depth"):
             getattr(L, f).argtypes = [vp, i32]
             getattr(L, f).restype = i32
         L.emst_set_autotune.argtypes = [vp, ctypes.c_char_p]
@@ -196,6 +200,11 @@ class Context:
 
     def set_profiling(self, on: bool = True):
         self._check(lib().emst_set_profiling(self._h, int(bool(on))))
+
+    def set_lds_depth(self, depth: int):
+        """LDS stack ring entries per lane of variant 13 (4, 8, 16; 0 = the
+        autotune table's choice, else 8)."""
+        self._check(lib().emst_set_lds_depth(self._h, int(depth)))
 
     def set_graphs(self, on: bool = True):
         """Batches: replay captured pairs of rounds (see emst_set_graphs)."""

@@ -1,8 +1,9 @@
 """Autotuner for the traversal shape.
 
-Every traversal variant computes the same tree; they differ only in speed,
-and the fastest depends on the cloud's size, dimension and on whether it
-runs alone or in a batch.  ``autotune`` times the candidate variants on
+Every traversal shape -- the variant and, for the default variant 13, the
+depth of its LDS stack ring -- computes the same tree; they differ only in
+speed, and the fastest depends on the cloud's size, dimension and on whether
+it runs alone or in a batch.  ``autotune`` times the candidate shapes on
 synthetic clouds of the workload recipes (or on the caller's own batch),
 keeps the fastest per size bucket and installs the result as the context's
 traversal-shape table (``emst_set_autotune``); calls left on the automatic
@@ -21,8 +22,22 @@ import numpy as np
 
 from . import workloads as W
 
-SINGLE_CANDIDATES = (5, 7, 8, 10, 11, 13)
-BATCHED_CANDIDATES = (0, 5, 7, 8, 13)
+# (traversal variant, LDS stack ring depth of variant 13): the two axes of
+# the traversal shape (the fixed-depth variants 5, 7, 8 have rings of 16, 8
+# and 4 entries of their own)
+SINGLE_CANDIDATES = ((5, 8), (7, 8), (8, 8), (10, 8), (11, 8), (13, 4), (13, 8), (13, 16))
+BATCHED_CANDIDATES = ((0, 8), (5, 8), (7, 8), (8, 8), (13, 4), (13, 8), (13, 16))
+
+
+def _label(shape) -> str:
+    v, d = shape
+    return f"{v}" if v != 13 else f"{v}/{d}"
+
+
+def _set_shape(ctx, shape) -> None:
+    v, d = shape
+    ctx.set_traversal(v)
+    ctx.set_lds_depth(d)
 
 
 def _median_seconds(fn, repeats: int) -> float:
@@ -48,7 +63,7 @@ def _bucket_starts(sizes: Sequence[int]) -> List[int]:
 
 
 def tune_single(ctx, sizes: Sequence[int] = (10_000, 100_000, 1_000_000, 4_000_000),
-                dims: Iterable[int] = (2, 3), candidates: Sequence[int] = SINGLE_CANDIDATES,
+                dims: Iterable[int] = (2, 3), candidates: Sequence[tuple] = SINGLE_CANDIDATES,
                 repeats: int = 3) -> List[Dict]:
     """One entry per (dim, size bucket): the fastest candidate on a cloud of
     that size (3D: the clustered recipe; 2D: the uniform one)."""
@@ -65,28 +80,29 @@ def tune_single(ctx, sizes: Sequence[int] = (10_000, 100_000, 1_000_000, 4_000_0
                 out[0] = ctx.build(pts, out=out[0])
 
             ms = {}
-            for v in candidates:
-                ctx.set_traversal(v)
-                ms[v] = 1e3 * _median_seconds(run, repeats)
+            for shape in candidates:
+                _set_shape(ctx, shape)
+                ms[shape] = 1e3 * _median_seconds(run, repeats)
             best = min(ms, key=ms.get)
-            entries.append({"mode": "single", "dim": int(dim), "n_min": int(n_min), "variant": int(best),
-                            "tuned_on": int(n), "ms": {str(k): round(t, 4) for k, t in ms.items()}})
-    ctx.set_traversal(-1)
+            entries.append({"mode": "single", "dim": int(dim), "n_min": int(n_min), "variant": int(best[0]),
+                            "lds_depth": int(best[1]), "tuned_on": int(n),
+                            "ms": {_label(k): round(t, 4) for k, t in ms.items()}})
+    _set_shape(ctx, (-1, 0))
     return entries
 
 
-def tune_batched(ctx, clouds, candidates: Sequence[int] = BATCHED_CANDIDATES, repeats: int = 3) -> List[Dict]:
+def tune_batched(ctx, clouds, candidates: Sequence[tuple] = BATCHED_CANDIDATES, repeats: int = 3) -> List[Dict]:
     """One entry for batches: the fastest candidate on the caller's clouds
     (a list of device tensors, as ``Context.build_batched`` takes them)."""
     ms = {}
-    for v in candidates:
-        ctx.set_traversal(v)
-        ms[v] = 1e3 * _median_seconds(lambda: ctx.build_batched(clouds), repeats)
-    ctx.set_traversal(-1)
+    for shape in candidates:
+        _set_shape(ctx, shape)
+        ms[shape] = 1e3 * _median_seconds(lambda: ctx.build_batched(clouds), repeats)
+    _set_shape(ctx, (-1, 0))
     best = min(ms, key=ms.get)
     total = int(sum(int(c.shape[0]) for c in clouds))
-    return [{"mode": "batched", "dim": 3, "n_min": 0, "variant": int(best), "tuned_on": total,
-             "ms": {str(k): round(t, 4) for k, t in ms.items()}}]
+    return [{"mode": "batched", "dim": 3, "n_min": 0, "variant": int(best[0]), "lds_depth": int(best[1]),
+             "tuned_on": total, "ms": {_label(k): round(t, 4) for k, t in ms.items()}}]
 
 
 def table_json(entries: List[Dict]) -> str:
@@ -103,5 +119,5 @@ def autotune(ctx, single_sizes: Optional[Sequence[int]] = (10_000, 100_000, 1_00
         entries += tune_batched(ctx, batched_clouds, repeats=repeats)
     text = table_json(entries)
     ctx.set_autotune(text)
-    ctx.set_traversal(-1)
+    _set_shape(ctx, (-1, 0))
     return text

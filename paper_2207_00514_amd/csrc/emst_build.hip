@@ -1820,6 +1820,7 @@ struct emst_ctx {
     bool profiling = false;
     bool counting = false;
     int traversal = -1;            // -1: the autotune table, else the built-in choice
+    int lds_depth = 0;             // 0: the autotune table, else 4, 8 or 16 (variant 13)
     TuneTable tune;
     emst_stats stats;
     Ctrl* h_ctrl = nullptr;        // pinned host mirror of the control block
@@ -1838,6 +1839,7 @@ struct emst_ctx {
         int variant, height;
         const void* cloud_of;
         uint32_t root;
+        int lds_depth;
         hipGraphExec_t exec;
         uint64_t used;
     };
@@ -1869,6 +1871,15 @@ static void* stage(emst_ctx* ctx, size_t bytes) {
 static int fail(emst_ctx* ctx, int code, const char* msg) {
     if (ctx) ctx->err = msg;
     return code;
+}
+
+// The traversal shape of a call: the context's explicit choices, else the
+// autotune table's entry for (mode, dim, n), else variant 13 with an 8-deep
+// LDS ring.
+static void pick_shape(const emst_ctx* ctx, int batched, int dim, int64_t n, int* variant, int* depth) {
+    const TuneEntry* e = ctx->tune.pick(batched, dim, n);
+    *variant = ctx->traversal >= 0 ? ctx->traversal : (e ? e->variant : 13);
+    *depth = ctx->lds_depth > 0 ? ctx->lds_depth : (e ? e->lds_depth : 8);
 }
 
 extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_json) {
@@ -1923,6 +1934,11 @@ extern "C" size_t emst_workspace_bytes(int64_t n, int dim) {
 extern "C" int emst_set_profiling(emst_ctx* ctx, int on) {
     if (!ctx) return EMST_EINVAL;
     ctx->profiling = on != 0;
+    return EMST_OK;
+}
+extern "C" int emst_set_lds_depth(emst_ctx* ctx, int depth) {
+    if (!ctx || (depth != 0 && depth != 4 && depth != 8 && depth != 16)) return EMST_EINVAL;
+    ctx->lds_depth = depth;
     return EMST_OK;
 }
 extern "C" int emst_set_graphs(emst_ctx* ctx, int on) {
@@ -2074,6 +2090,7 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     ta.pos = b.pos;
     ta.qlist = nullptr;
     ta.touched = nullptr;
+    ta.lds_depth = 8;
     return ta;
 }
 
@@ -2248,7 +2265,8 @@ int round_pair_graph(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t
     ++ctx->gclock;
     for (auto& g : ctx->gcache)
         if (g.ws == (const void*)b.ctrl && g.n == n && g.target == target && g.variant == variant &&
-            g.height == height && g.cloud_of == (const void*)cloud_of && g.root == ta.root) {
+            g.height == height && g.cloud_of == (const void*)cloud_of && g.root == ta.root &&
+            g.lds_depth == ta.lds_depth) {
             g.used = ctx->gclock;
             *out = g.exec;
             return EMST_OK;
@@ -2277,8 +2295,8 @@ int round_pair_graph(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t
         (void)hipGraphExecDestroy(old->exec);
         ctx->gcache.erase(old);
     }
-    ctx->gcache.push_back({(const void*)b.ctrl, n, target, variant, height, (const void*)cloud_of, ta.root, exec,
-                           ctx->gclock});
+    ctx->gcache.push_back({(const void*)b.ctrl, n, target, variant, height, (const void*)cloud_of, ta.root,
+                           ta.lds_depth, exec, ctx->gclock});
     *out = exec;
     return EMST_OK;
 }
@@ -2537,6 +2555,7 @@ struct Job {
     bool ranks = false;
     int full = 0;
     int variant = 10;
+    int lds_depth = 8;
     uint32_t root = 0;     // of the finished hierarchy
     int height = 0;
     int codes_in1 = 0;     // which key buffer holds the sorted codes
@@ -2560,7 +2579,7 @@ static Job make_job(emst_ctx* ctx, const float* pts, int64_t n, int dim, char* w
     j.h = h;
     j.prof = prof;
     j.ncomp = n;
-    j.variant = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(0, dim, n, 13);
+    pick_shape(ctx, 0, dim, n, &j.variant, &j.lds_depth);
     memset(&j.S, 0, sizeof(j.S));
     j.S.n = n;
     j.S.dim = dim;
@@ -2570,6 +2589,7 @@ static Job make_job(emst_ctx* ctx, const float* pts, int64_t n, int dim, char* w
 template <int DIM>
 static TraverseArgs<DIM> job_args(const Job& j, const Bufs<DIM>& b) {
     TraverseArgs<DIM> ta = traverse_args<DIM>(b, j.n, j.root);
+    ta.lds_depth = j.lds_depth;
     if (j.k_pts >= 2) {
         ta.core_s = b.core_s;
         ta.core_o = b.core_o;
@@ -2717,6 +2737,7 @@ int job_advance(emst_ctx* ctx, Job& j) {
             j.S.rounds = j.round;
             j.S.traversal_launches = j.round;
             j.S.traversal_variant = j.variant;
+            j.S.traversal_lds_depth = j.variant == 13 ? j.lds_depth : 0;
             if (h->edge_count != (uint32_t)(n - 1)) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
             j.phase = kPhFinal;
         }
@@ -2921,8 +2942,11 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     ta.cloud_root = d_croot;
     // variants 1-4 start every lane at one root and 6, 9-12 need the Morton
     // cells of one cloud: a batch runs them as 7 (and 13 with the start of 7)
-    const int t = ctx->traversal >= 0 ? ctx->traversal : ctx->tune.pick(1, 3, n, 13);
+    int t = 13, depth = 8;
+    pick_shape(ctx, 1, 3, n, &t, &depth);
     const int variant = (t == 0 || t == 5 || t == 8 || t == 13) ? t : 7;
+    ta.lds_depth = depth;
+    S.traversal_lds_depth = variant == 13 ? depth : 0;
     if (int rc = run_rounds<3>(ctx, b, ta, n, nonempty, S.tree_height, variant, cloud_sorted, S, st)) return rc;
     if ((int64_t)ctx->h_ctrl->edge_count != eoff) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
     if (prof) HIP_TRY(hipEventRecord(E[2], st));

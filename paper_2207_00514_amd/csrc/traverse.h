@@ -55,6 +55,9 @@ struct TraverseArgs {
     const uint32_t* qlist;
     // counting runs: one flag per node record, set when a search loads it
     uint8_t* touched;
+    // launch shape (host side): LDS stack ring entries per lane of variant
+    // 13 (4, 8 or 16)
+    int lds_depth;
 };
 
 // Where a top-down search of query i starts.
@@ -602,11 +605,27 @@ hipError_t launch_traverse_s(const TraverseArgs<DIM>& a, int variant, bool count
         EMST_FAST(8, true, false, true);
     } else if (variant == 13 && a.cloud_of) {
         // batches: the start of variant 7 (each cloud's root) with the reuse
-        if (a.qlist) EMST_FAST(8, false, false, false, true, true);
-        else EMST_FAST(8, false, false, false, true, false);
+        if (a.lds_depth == 4) {
+            if (a.qlist) EMST_FAST(4, false, false, false, true, true);
+            else EMST_FAST(4, false, false, false, true, false);
+        } else if (a.lds_depth == 16) {
+            if (a.qlist) EMST_FAST(16, false, false, false, true, true);
+            else EMST_FAST(16, false, false, false, true, false);
+        } else {
+            if (a.qlist) EMST_FAST(8, false, false, false, true, true);
+            else EMST_FAST(8, false, false, false, true, false);
+        }
     } else if (variant == 13) {
-        if (a.qlist) EMST_FAST(8, true, false, false, true, true);
-        else EMST_FAST(8, true, false, false, true, false);
+        if (a.lds_depth == 4) {
+            if (a.qlist) EMST_FAST(4, true, false, false, true, true);
+            else EMST_FAST(4, true, false, false, true, false);
+        } else if (a.lds_depth == 16) {
+            if (a.qlist) EMST_FAST(16, true, false, false, true, true);
+            else EMST_FAST(16, true, false, false, true, false);
+        } else {
+            if (a.qlist) EMST_FAST(8, true, false, false, true, true);
+            else EMST_FAST(8, true, false, false, true, false);
+        }
     } else {
         if (count) k_traverse_lane<DIM, STACK, true><<<grid, 256, 0, st>>>(a);
         else k_traverse_lane<DIM, STACK, false><<<grid, 256, 0, st>>>(a);

@@ -137,7 +137,7 @@ bool TuneTable::parse(const char* json, uint32_t valid_variants, std::string* er
                     ++r.p;
                 } else {
                     for (;;) {
-                        TuneEntry e{-1, -1, -1, -1};
+                        TuneEntry e{-1, -1, -1, -1, 8};
                         if (!r.expect('{')) return fail(r.err);
                         r.ws();
                         if (*r.p != '}') {
@@ -150,12 +150,13 @@ bool TuneTable::parse(const char* json, uint32_t valid_variants, std::string* er
                                     if (m == "single") e.batched = 0;
                                     else if (m == "batched") e.batched = 1;
                                     else return fail("mode must be \"single\" or \"batched\"");
-                                } else if (k == "dim" || k == "n_min" || k == "variant") {
+                                } else if (k == "dim" || k == "n_min" || k == "variant" || k == "lds_depth") {
                                     int64_t v;
                                     if (!r.integer(&v)) return fail(r.err);
                                     if (k == "dim") e.dim = (int)v;
                                     else if (k == "n_min") e.n_min = v;
-                                    else e.variant = (int)v;
+                                    else if (k == "variant") e.variant = (int)v;
+                                    else e.lds_depth = (v == 4 || v == 8 || v == 16) ? (int)v : -1;
                                 } else if (!r.skip()) {
                                     return fail(r.err);
                                 }
@@ -171,8 +172,9 @@ bool TuneTable::parse(const char* json, uint32_t valid_variants, std::string* er
                             ++r.p;
                         }
                         if (e.batched < 0 || (e.dim != 2 && e.dim != 3) || e.n_min < 0 || e.variant < 0 ||
-                            e.variant > 31 || !((valid_variants >> e.variant) & 1u))
-                            return fail("every entry needs mode, dim in {2, 3}, n_min >= 0 and a valid variant");
+                            e.variant > 31 || !((valid_variants >> e.variant) & 1u) || e.lds_depth < 0)
+                            return fail("every entry needs mode, dim in {2, 3}, n_min >= 0, a valid variant "
+                                        "and lds_depth 4, 8 or 16 if given");
                         out.push_back(e);
                         r.ws();
                         if (*r.p == ',') {
@@ -203,14 +205,10 @@ bool TuneTable::parse(const char* json, uint32_t valid_variants, std::string* er
     return true;
 }
 
-int TuneTable::pick(int batched, int dim, int64_t n, int fallback) const {
-    int best = fallback;
-    int64_t best_min = -1;
+const TuneEntry* TuneTable::pick(int batched, int dim, int64_t n) const {
+    const TuneEntry* best = nullptr;
     for (const TuneEntry& e : entries_)
-        if (e.batched == batched && e.dim == dim && e.n_min <= n && e.n_min > best_min) {
-            best = e.variant;
-            best_min = e.n_min;
-        }
+        if (e.batched == batched && e.dim == dim && e.n_min <= n && (!best || e.n_min > best->n_min)) best = &e;
     return best;
 }
 
@@ -219,8 +217,9 @@ std::string TuneTable::dump() const {
     char buf[160];
     for (size_t i = 0; i < entries_.size(); ++i) {
         const TuneEntry& e = entries_[i];
-        snprintf(buf, sizeof(buf), "%s{\"mode\": \"%s\", \"dim\": %d, \"n_min\": %lld, \"variant\": %d}",
-                 i ? ", " : "", e.batched ? "batched" : "single", e.dim, (long long)e.n_min, e.variant);
+        snprintf(buf, sizeof(buf),
+                 "%s{\"mode\": \"%s\", \"dim\": %d, \"n_min\": %lld, \"variant\": %d, \"lds_depth\": %d}",
+                 i ? ", " : "", e.batched ? "batched" : "single", e.dim, (long long)e.n_min, e.variant, e.lds_depth);
         s += buf;
     }
     s += "]}";

@@ -44,15 +44,16 @@ def test_autotune_table_round_trip_and_results():
     text = autotune.autotune(ctx, single_sizes=(3000, 30000), dims=(3,), repeats=1)
     table = json.loads(text)["entries"]
     assert [e["n_min"] for e in table] == [0, int((3000 * 30000) ** 0.5)]
-    assert all(e["variant"] in autotune.SINGLE_CANDIDATES for e in table)
+    assert all((e["variant"], e["lds_depth"]) in autotune.SINGLE_CANDIDATES for e in table)
     back = json.loads(ctx.get_autotune())["entries"]
-    assert [(e["mode"], e["dim"], e["n_min"], e["variant"]) for e in back] == \
-        [(e["mode"], e["dim"], e["n_min"], e["variant"]) for e in table]
+    key = lambda e: (e["mode"], e["dim"], e["n_min"], e["variant"], e["lds_depth"])  # noqa: E731
+    assert [key(e) for e in back] == [key(e) for e in table]
     for n in (3000, 30000):
         pts = W.clustered3d(n)
         got = host(ctx.build(dev(pts)))
-        want = table[0]["variant"] if n < table[1]["n_min"] else table[1]["variant"]
-        assert ctx.stats()["traversal_variant"] == want
+        e = table[0] if n < table[1]["n_min"] else table[1]
+        assert ctx.stats()["traversal_variant"] == e["variant"]
+        assert ctx.stats()["traversal_lds_depth"] == (e["lds_depth"] if e["variant"] == 13 else 0)
         ref = oracle.emst(pts, threads=8)
         assert np.array_equal(got[0], ref.edges) and np.array_equal(got[2].view(np.uint32), ref.d2.view(np.uint32))
     # the saved table configures a new context
@@ -82,6 +83,42 @@ def test_autotune_lookup_by_mode_dim_and_size():
     ctx.set_traversal(10)
     host(ctx.build(dev(W.clustered3d(6000))))
     assert ctx.stats()["traversal_variant"] == 10
+
+
+def test_lds_depth_axis():
+    """The LDS ring depth of variant 13 (table key lds_depth, or
+    emst_set_lds_depth): every depth gives the oracle's tree, alone and in a
+    batch, and the table's depth applies by size."""
+    import paper_2207_00514_amd as emst
+    table = {"entries": [
+        {"mode": "single", "dim": 3, "n_min": 0, "variant": 13, "lds_depth": 4},
+        {"mode": "single", "dim": 3, "n_min": 5000, "variant": 13, "lds_depth": 16},
+        {"mode": "batched", "dim": 3, "n_min": 0, "variant": 13, "lds_depth": 16}]}
+    ctx = emst.Context(0, autotune_json=json.dumps(table))
+    for pts, want in ((W.clustered3d(1000, seed=5), 4), (W.clustered3d(60_000, seed=6), 16)):
+        got = host(ctx.build(dev(pts)))
+        assert ctx.stats()["traversal_lds_depth"] == want
+        ref = oracle.emst(pts, threads=8)
+        assert np.array_equal(got[0], ref.edges) and np.array_equal(got[2].view(np.uint32), ref.d2.view(np.uint32))
+    pts = W.clustered3d(900_000, seed=7)  # query-list rounds
+    ref = oracle.emst(pts, threads=16)
+    for d in (4, 8, 16):
+        ctx.set_lds_depth(d)
+        got = host(ctx.build(dev(pts)))
+        assert ctx.stats()["traversal_lds_depth"] == d
+        assert np.array_equal(got[0], ref.edges), f"depth {d}"
+    ctx.set_lds_depth(0)
+    clouds = W.batched_clouds(n_clouds=8, seed=42, lo=500, hi=20_000)
+    res = ctx.build_batched([dev(c) for c in clouds])
+    torch.cuda.synchronize()
+    assert ctx.stats()["traversal_lds_depth"] == 16
+    for c, r in zip(clouds, res):
+        assert np.array_equal(r[0].cpu().numpy(), oracle.emst(c, threads=8).edges)
+    for bad in (1, 2, 3, 5, 32, -1):
+        with pytest.raises(emst.EmstError):
+            ctx.set_lds_depth(bad)
+    with pytest.raises(emst.EmstError):
+        ctx.set_autotune('{"entries": [{"mode": "single", "dim": 3, "n_min": 0, "variant": 13, "lds_depth": 6}]}')
 
 
 def test_autotune_bad_tables():
