@@ -56,6 +56,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <xmmintrin.h>
@@ -375,9 +376,15 @@ static int kdboruvka_impl(const float *pts, int64_t n, int dim, const float *cor
 #else
     (void)nthreads;
 #endif
+    /* ORACLE_PROGRESS set: one line per round on stderr (long runs) */
+    const int progress = getenv("ORACLE_PROGRESS") != NULL;
     int64_t n_edges = 0, n_comp = n, round = 0;
     while (n_comp > 1) {
         if (comps_out && round < 64) comps_out[round] = n_comp;
+        if (progress) {
+            fprintf(stderr, "oracle: kd-Boruvka round %lld, %lld components\n", (long long)round, (long long)n_comp);
+            fflush(stderr);
+        }
         /* (i) component of every point, fixed for the round */
         for (int64_t i = 0; i < n; ++i) lab[i] = (uint32_t)uf_find(par, i);
         /* (ii) component of every node: children were created after their
