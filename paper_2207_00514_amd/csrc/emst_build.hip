@@ -2366,6 +2366,12 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
         HIP_TRY(hipEventRecord(ctx->sev[r & 1], st));
         return EMST_OK;
     };
+    if (n <= target) {  // every cloud is a single point: no round at all
+        S.rounds = 0;
+        S.traversal_launches = 0;
+        S.traversal_variant = variant;
+        return EMST_OK;
+    }
     int64_t ncomp = n, prev = 0;
     int queued = -1;
     for (int round = 0;; ++round) {
