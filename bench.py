@@ -158,7 +158,8 @@ def main() -> int:
                 "config": {"workload": "batched512", "clouds": res["clouds"], "points": res["points"], "seed": 4},
                 "batched": res}
         print(json.dumps(line), flush=True)
-        return 0 if res["equals_solo"] and res.get("oracle_sample_parity", True) else 1
+        ok = res["equals_solo"] and res.get("oracle_sample_parity", True) and res["captured_rounds"]["equal_results"]
+        return 0 if ok else 1
     if args.workload == "serving":
         res = serving_leg(args)
         b9 = res["0.9"]["batched"]
@@ -308,7 +309,8 @@ def bench_single(args) -> int:
     ok = True
     if "batched" in legs:
         line["batched"] = batched_leg(args)
-        ok = ok and line["batched"]["equals_solo"] and line["batched"].get("oracle_sample_parity", True)
+        ok = (ok and line["batched"]["equals_solo"] and line["batched"].get("oracle_sample_parity", True)
+              and line["batched"]["captured_rounds"]["equal_results"])
     if "serving" in legs:
         line["serving"] = serving_leg(args)
         ok = ok and line["serving"]["results_equal"]
@@ -392,6 +394,21 @@ def batched_leg(args) -> dict:
         out = ctx.build_batched_flat(flat, sizes, dims)
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / steps
+    # A/B: the rounds from the third on as replays of a captured graph of two
+    # rounds (emst_set_graphs), same inputs and shape
+    ctx.set_graphs(True)
+    for _ in range(max(args.warmup, 1)):
+        ctx.build_batched_flat(flat, sizes, dims)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gout = ctx.build_batched_flat(flat, sizes, dims)
+    torch.cuda.synchronize()
+    t_graphs = (time.perf_counter() - t0) / steps
+    ctx.set_graphs(False)
+    graphs_same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+                      for a, b in zip(out, gout))
+    del gout
     ctx1 = emst.Context(0)
     ctx1.workspace(max(sizes), 3)
     for c in per[:8]:
@@ -411,6 +428,8 @@ def batched_leg(args) -> dict:
                                  "ms": round(t_solo * 1e3, 3)},
         "speedup": round(t_solo / t_batched, 2),
         "equals_solo": bool(same),
+        "captured_rounds": {"ms": round(t_graphs * 1e3, 3), "eager_ms": round(t_batched * 1e3, 3),
+                            "equal_results": bool(graphs_same)},
         "autotuned_shape": {"variant": int(best[0]), "lds_depth": int(best[1])},
         "autotune_ms": {autotune._label(k): round(v, 3) for k, v in ms.items()},
     }
