@@ -97,6 +97,31 @@ int emst_build(emst_ctx *ctx, const float *d_points, int64_t n, int dim,
                int32_t *d_edges, float *d_weights, float *d_d2,
                void *d_workspace, size_t ws_bytes, void *stream);
 
+/*
+ * emst_build_noalloc -- emst_build for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  It takes no workspace: its scratch space is a
+ * static device array of EMST_NOALLOC_WORKSPACE_BYTES that every device the
+ * library runs on holds until the process ends; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).
+ *
+ *  d_points, n, dim, d_edges, d_weights, d_d2, stream   as for emst_build;
+ *  the result is bit-identical to emst_build's.
+ *
+ * Limit: emst_workspace_bytes(n, dim) <= EMST_NOALLOC_WORKSPACE_BYTES
+ * (about 280,000 points in 3D, 300,000 in 2D); larger n gives EMST_ENOMEM
+ * with a message naming the sizes, and nothing is written.  Every call on
+ * one device shares that device's array and leaves its contents behind
+ * (the kernels initialise everything they read), so calls that overlap on
+ * one device -- from two host threads, or on two streams without an order
+ * between them -- race and must not be issued.  Other errors as for
+ * emst_build; EMST_EHIP also if the array's device address could not be
+ * obtained when the context was created.
+ */
+#define EMST_NOALLOC_WORKSPACE_BYTES (64u << 20)
+int emst_build_noalloc(emst_ctx *ctx, const float *d_points, int64_t n, int dim,
+                       int32_t *d_edges, float *d_weights, float *d_d2, void *stream);
+
 /* Exact workspace bytes emst_build_batched needs for `total_points` points
  * in `n_clouds` clouds (0 for invalid arguments). */
 size_t emst_workspace_bytes_batched(int64_t total_points, int32_t n_clouds);

@@ -37,7 +37,7 @@ EXPORTS = [
     "emst_solver_slot_bytes", "emst_solver_create", "emst_solver_destroy", "emst_solver_admit",
     "emst_solver_step", "emst_solver_poll", "emst_solver_take",
     "emst_test_round", "emst_test_distances", "emst_test_weights",
-    "emst_set_graphs", "emst_set_lds_depth",
+    "emst_set_graphs", "emst_set_lds_depth", "emst_build_noalloc",
 ]
 
 
@@ -106,6 +106,8 @@ def lib():
         L.emst_build_mreach.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, vp]
         L.emst_build_mreach.restype = i32
         L.emst_build.restype = i32
+        L.emst_build_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp]
+        L.emst_build_noalloc.restype = i32
         for f in ("emst_set_profiling", "emst_set_counting", "emst_set_traversal", "emst_set_graphs",
                   "emst_set_lds_depth"):
             getattr(L, f).argtypes = [vp, i32]
@@ -151,6 +153,10 @@ def lib():
         L.emst_test_weights.restype = i32
         _lib = L
     return _lib
+
+
+# emst_build_noalloc's static workspace (EMST_NOALLOC_WORKSPACE_BYTES)
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 
 def workspace_bytes(n: int, dim: int) -> int:
@@ -362,6 +368,33 @@ class Context:
         self._check(rc)
         return edges, weights, d2
 
+    def build_noalloc(self, points, out=None, want_d2: bool = True, stream=None):
+        """emst_build_noalloc: as build(), with the library's static device
+        workspace instead of a caller workspace (no device allocation in the
+        call; at most NOALLOC_WORKSPACE_BYTES of workspace, so a few hundred
+        thousand points).  `out` = (edges, weights, d2 or None) preallocated
+        by the caller; without it the outputs are allocated here, before the
+        call."""
+        import torch
+        if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
+            raise TypeError("points must be a CUDA (HIP) torch tensor")
+        if points.dtype != torch.float32 or points.dim() != 2:
+            raise TypeError("points must be float32 [n, dim]")
+        points = points.contiguous()
+        n, dim = points.shape
+        m = max(n - 1, 0)
+        if out is None:
+            edges = torch.empty((m, 2), dtype=torch.int32, device=points.device)
+            weights = torch.empty(m, dtype=torch.float32, device=points.device)
+            d2 = torch.empty(m, dtype=torch.float32, device=points.device) if want_d2 else None
+        else:
+            edges, weights, d2 = out
+        rc = lib().emst_build_noalloc(self._h, ctypes.c_void_p(points.data_ptr()), int(n), int(dim),
+                                      ctypes.c_void_p(edges.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
+                                      ctypes.c_void_p(d2.data_ptr() if d2 is not None else 0),
+                                      _stream_handle(stream))
+        self._check(rc)
+        return edges, weights, d2
 
     @staticmethod
     def _check_points(points):

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1814,8 +1815,39 @@ using namespace emst;
 constexpr uint32_t kVariants = (1u << 0) | (1u << 5) | (1u << 7) | (1u << 8) | (1u << 10) | (1u << 11) | (1u << 13);
 static inline bool variant_ok(int v) { return v >= 0 && v < 32 && ((kVariants >> v) & 1u); }
 
+// Device memory of the allocation-free entry point (emst_build_noalloc):
+// its workspace is this array, which every device the library runs on holds
+// from the code object's load until the process ends.  Host code never
+// passes its name to a kernel: it takes the device address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) unsigned char scratch[EMST_NOALLOC_WORKSPACE_BYTES];
+
+// The address of `scratch` on each device, looked up once per device with
+// that device current.
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+static hipError_t scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();  // leave no sticky error for the next launch check
+            return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 struct emst_ctx {
     int device = 0;
+    void* scratch = nullptr;       // this device's `scratch` (null if the lookup failed)
+    std::string scratch_err;
     std::string err;
     bool profiling = false;
     bool counting = false;
@@ -1908,6 +1940,10 @@ extern "C" int emst_create(emst_ctx** out, int hip_device, const char* autotune_
     ctx->ev_ok = true;
     for (auto& e : ctx->ev)
         if (hipEventCreate(&e) != hipSuccess) ctx->ev_ok = false;
+    // the allocation-free entry point's workspace on this device (the
+    // device is current); a failed lookup only disables that entry point
+    if (const hipError_t e = scratch_address(hip_device, &ctx->scratch); e != hipSuccess)
+        ctx->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
     *out = ctx;
     return EMST_OK;
 }
@@ -2994,6 +3030,28 @@ extern "C" int emst_build(emst_ctx* ctx, const float* d_points, int64_t n, int d
     return build_impl<2>(ctx, d_points, n, d_edges, d_weights, d_d2, (char*)d_workspace, st);
 }
 
+
+extern "C" int emst_build_noalloc(emst_ctx* ctx, const float* d_points, int64_t n, int dim, int32_t* d_edges,
+                                  float* d_weights, float* d_d2, void* stream) {
+    if (!ctx) return EMST_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > 0x7FFFFFFFll) return fail(ctx, EMST_EINVAL, "n out of range");
+    if (dim != 2 && dim != 3) return fail(ctx, EMST_EINVAL, "dim must be 2 or 3");
+    const size_t need = emst_workspace_bytes(n, dim);
+    if (need > (size_t)EMST_NOALLOC_WORKSPACE_BYTES) {
+        ctx->err = "emst_build_noalloc: " + std::to_string(n) + " points need " + std::to_string(need) +
+                   " workspace bytes, more than the " + std::to_string((size_t)EMST_NOALLOC_WORKSPACE_BYTES) +
+                   " of the static workspace";
+        return EMST_ENOMEM;
+    }
+    if (n >= 2 && !ctx->scratch) {
+        ctx->err = "emst_build_noalloc: static workspace unavailable (" + ctx->scratch_err + ")";
+        return EMST_EHIP;
+    }
+    const int rc = emst_build(ctx, d_points, n, dim, d_edges, d_weights, d_d2, ctx->scratch,
+                              (size_t)EMST_NOALLOC_WORKSPACE_BYTES, stream);
+    return rc;
+}
 
 static int check_single(emst_ctx* ctx, const float* d_points, int64_t n, int dim, void* d_workspace,
                         size_t ws_bytes) {

@@ -85,3 +85,18 @@ def test_stats_struct_matches_the_header(tmp_path):
     out = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert out[0] == ctypes.sizeof(emst.Stats)
     assert out[1:] == [getattr(emst.Stats, f).offset for f in fields]
+
+
+def test_noalloc_limit_matches_the_header():
+    """The binding's copy of EMST_NOALLOC_WORKSPACE_BYTES equals the header's,
+    and the entry point rejects a missing context before any device work."""
+    text = open(os.path.join(ROOT, "include", "emst.h")).read()
+    m = re.search(r"#define EMST_NOALLOC_WORKSPACE_BYTES \((\d+)u << (\d+)\)", text)
+    assert m, "EMST_NOALLOC_WORKSPACE_BYTES not found"
+    assert emst.NOALLOC_WORKSPACE_BYTES == int(m.group(1)) << int(m.group(2))
+    L = emst.lib()
+    assert L.emst_build_noalloc(None, None, 10, 3, None, None, None, None) == -1
+    # the documented capacity: about 280,000 3D and 300,000 2D points
+    wb = emst.workspace_bytes
+    assert wb(270_000, 3) <= emst.NOALLOC_WORKSPACE_BYTES < wb(290_000, 3)
+    assert wb(290_000, 2) <= emst.NOALLOC_WORKSPACE_BYTES < wb(320_000, 2)
