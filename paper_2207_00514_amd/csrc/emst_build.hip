@@ -746,6 +746,22 @@ __global__ __launch_bounds__(1024) void k_tile_carries(const uint32_t* __restric
 // position writes its own bound.  Later the positions of a run of equal
 // labels within a wave combine first and one lane per run lowers the
 // component's bound.
+// Kept candidates (traversal variant 13, from the third round on): a point
+// whose last candidate still lies outside its component keeps it (see
+// k_traverse_fast, REUSE).  k_round_prep flags such points in `kept` and
+// offers their candidates to stage A of their component, so that the
+// component key holds a real outgoing edge of the component, hence a bound
+// on its shortest one, before the query list is made and the traversal
+// runs.  kept = null: no offers.
+struct KeepArgs {
+    const uint32_t* cand_d;
+    const uint32_t* cand_j;
+    const uint32_t* pos;
+    const uint32_t* orig;
+    uint64_t* compkey;
+    uint8_t* kept;
+};
+
 template <int DIM, bool FIRST, bool BOUNDS>
 __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__ labels,
                                                     const uint32_t* __restrict__ carry,
@@ -754,7 +770,8 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
                                                     const float* __restrict__ spts,
                                                     const uint32_t* __restrict__ cloud_of,
                                                     const float* __restrict__ core_s, int64_t n, uint32_t* ub,
-                                                    Ctrl* ctrl, const uint32_t* __restrict__ fold_part, int nt) {
+                                                    Ctrl* ctrl, const uint32_t* __restrict__ fold_part, int nt,
+                                                    KeepArgs keep) {
     if (ctrl->done) return;
     __shared__ uint32_t s_lab[kRunLds];               // labels of positions base-1 .. base+kRunTile
     __shared__ uint32_t s_rs[FIRST ? 1 : kRunLds];    // start of the run containing each position
@@ -842,6 +859,35 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
             }
             lab2[k] = make_uint2(left ? s_lab[run_lds(x + 1)] : kInvalid,
                                  right ? s_lab[run_lds(x + 2)] : kInvalid);
+        }
+    }
+    if (!FIRST && keep.kept) {
+        uint32_t pj[kRunPer], other[kRunPer];
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) {
+            const int64_t k = base + q * 256 + tid;
+            pj[q] = k < n ? keep.cand_j[k] : kNone;
+        }
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) other[q] = pj[q] != kNone ? keep.pos[pj[q]] : 0u;
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) other[q] = pj[q] != kNone ? labels[other[q]] : kNone;
+#pragma unroll
+        for (int q = 0; q < kRunPer; ++q) {
+            const int x = q * 256 + tid;
+            const int64_t k = base + x;
+            const bool valid = k < n;
+            const uint32_t lab = valid ? s_lab[run_lds(x + 1)] : kNone;
+            const bool kp = valid && pj[q] != kNone && other[q] != lab;
+            uint64_t key = kKeyMax;
+            if (kp) key = ((uint64_t)keep.cand_d[k] << 32) | (uint64_t)min(keep.orig[k], pj[q]);
+            if (valid) keep.kept[k] = kp ? 1u : 0u;
+            if (base + q * 256 < n) {  // uniform over the workgroup
+                bool run_end;
+                key = wave_seg_min<uint64_t>(lab, key, &run_end);
+                if (valid && run_end && key != kKeyMax && key < load_relaxed64(&keep.compkey[lab]))
+                    atomicMin((unsigned long long*)&keep.compkey[lab], (unsigned long long)key);
+            }
         }
     }
     if (!BOUNDS) return;
@@ -945,61 +991,61 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
 // REUSE) offers its kept candidate to its component here instead.
 
 // Per tile of kRunTile positions: qflag[i] = 1 for a point that must
-// search, qcnt[t] = their number.  A kept candidate farther than the
-// component's bound cannot be the component's shortest edge (the bound is
-// the length of one of its outgoing edges), so only the others are offered.
+// search, qcnt[t] = their number.  On entry qflag holds the kept flags of
+// k_round_prep, whose offers are complete by now, so the radius of every
+// component is known: its bound, lowered to the shortest kept candidate
+// while components are small (tight_radius).  A
+// point searches unless it keeps its candidate, or its last result shows
+// that nothing outside its component lies within that radius: an absorbed
+// candidate at D = pd (every point now outside was outside then, so none
+// is nearer), or a search that found nothing within R.
 __global__ __launch_bounds__(256) void k_reuse_mark(const uint32_t* __restrict__ labels,
                                                     const uint32_t* __restrict__ ub,
-                                                    const uint32_t* __restrict__ cand_d,
-                                                    const uint32_t* __restrict__ cand_j,
-                                                    const uint32_t* __restrict__ pos,
-                                                    const uint32_t* __restrict__ orig, uint64_t* compkey,
+                                                    const uint64_t* __restrict__ compkey,
+                                                    uint32_t* __restrict__ cand_d, uint32_t* __restrict__ cand_j,
                                                     uint8_t* __restrict__ qflag, uint32_t* __restrict__ qcnt,
                                                     int64_t n, const Ctrl* ctrl) {
     if (ctrl->done) return;
     __shared__ uint32_t s_w[4];
     const int64_t base = (int64_t)blockIdx.x * kRunTile;
-    uint32_t c[kRunPer], pj[kRunPer], pd[kRunPer], other[kRunPer], bound[kRunPer];
-    // all loads of the tile first, one dependent step at a time
+    uint32_t c[kRunPer], pj[kRunPer], pd[kRunPer], kp[kRunPer], radius[kRunPer];
 #pragma unroll
     for (int q = 0; q < kRunPer; ++q) {
         const int64_t i = base + q * 256 + threadIdx.x;
         const bool valid = i < n;
         c[q] = valid ? labels[i] : kNone;
+        kp[q] = valid ? qflag[i] : 1u;
         pj[q] = valid ? cand_j[i] : kNone;
         pd[q] = valid ? cand_d[i] : 0u;
     }
+    const bool tight = tight_radius(ctrl, n);
 #pragma unroll
     for (int q = 0; q < kRunPer; ++q) {
-        other[q] = pj[q] != kNone ? pos[pj[q]] : 0u;
-        bound[q] = c[q] != kNone ? ub[c[q]] : 0u;
+        radius[q] = 0u;
+        if (c[q] != kNone && !kp[q]) {
+            const uint64_t ck = tight ? compkey[c[q]] : kKeyMax;
+            radius[q] = min(ub[c[q]], ck != kKeyMax ? (uint32_t)(ck >> 32) : kInfBits);
+        }
     }
-#pragma unroll
-    for (int q = 0; q < kRunPer; ++q) other[q] = pj[q] != kNone ? labels[other[q]] : kNone;
     uint32_t cnt = 0;
 #pragma unroll
     for (int q = 0; q < kRunPer; ++q) {
         const int64_t i = base + q * 256 + threadIdx.x;
-        const bool valid = i < n;
-        uint64_t key = kKeyMax;
-        if (valid) {
-            bool need;
+        if (i >= n) continue;
+        bool need = false;
+        if (!kp[q]) {
             if (pj[q] != kNone) {
-                const bool keep = other[q] != c[q];
-                if (keep && pd[q] <= bound[q]) key = ((uint64_t)pd[q] << 32) | (uint64_t)min(orig[i], pj[q]);
-                need = !keep;
+                need = pd[q] <= radius[q];
+                if (!need) {  // absorbed beyond the radius
+                    cand_j[i] = kNone;
+                    cand_d[i] = pd[q] - 1u;  // every outside point has D > this
+                }
             } else {
-                need = bound[q] > pd[q];
+                need = radius[q] > pd[q];
             }
-            qflag[i] = need ? 1u : 0u;
-            cnt += need;
         }
-        if (base + q * 256 < n) {  // uniform over the workgroup
-            bool run_end;
-            key = wave_seg_min<uint64_t>(c[q], key, &run_end);
-            if (valid && run_end && key != kKeyMax && key < load_relaxed64(&compkey[c[q]]))
-                atomicMin((unsigned long long*)&compkey[c[q]], (unsigned long long)key);
-        }
+        qflag[i] = need ? 1u : 0u;
+        cnt += need;
     }
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = cnt;
@@ -1424,6 +1470,10 @@ __global__ __launch_bounds__(256) void k_relabel(uint32_t* labels, const uint32_
 // A run longer than kMaxTieRun raises long_ties and the caller redoes the
 // order by the full path: by (u, v), then stably by D.  A batch finally
 // sorts stably by cloud (a run never spans two clouds: u fixes the cloud).
+// (Sorting by D alone, four passes, and ordering runs of equal D by (u, v)
+// was measured and dropped: on the 37M-point cosmology cloud, where many
+// short edges in dense halos share one float32 length, runs of equal D
+// exceed any small bound and the full path then costs 9 ms more.)
 constexpr int kMaxTieRun = 32;
 
 __global__ __launch_bounds__(256) void k_edge_du_keys(const uint4* __restrict__ eud, int64_t m,
@@ -1659,6 +1709,10 @@ __global__ __launch_bounds__(256) void k_batch_sorted_cloud(const uint32_t* __re
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(64) void k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
 // Counting runs: ctrl->touched += the number of set flags among f[0, m).
@@ -2043,7 +2097,7 @@ hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_part, uint32_t
     k_run_partials<<<nb, 256, 0, st>>>(labels, n, run_part);
     k_tile_carries<<<1, 1024, 0, st>>>(run_part, nb, run_carry, ctrl);
     k_round_prep<3, false, false><<<nb, 256, 0, st>>>(labels, run_carry, rlo, rhi, lab2, nullptr, nullptr, nullptr,
-                                                      n, nullptr, ctrl, nullptr, nb);
+                                                      n, nullptr, ctrl, nullptr, nb, KeepArgs{});
     return hipGetLastError();
 }
 
@@ -2126,6 +2180,8 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     ta.pos = b.pos;
     ta.qlist = nullptr;
     ta.touched = nullptr;
+    ta.kept = nullptr;
+    ta.all_absorbed = false;
     ta.lds_depth = 8;
     return ta;
 }
@@ -2196,38 +2252,47 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     // the relabel kernel of round r - 1
     const int nt = run_tiles(n);
     const bool fold = nt <= kFoldTiles;  // scans folded into their consumers
+    // variant 13 from the third round on: kept candidates are offered here
+    // (in round 1 none is kept: every point joined its candidate's
+    // component in round 0)
+    const bool keep = variant == 13 && round >= 2;
+    const KeepArgs ka = keep ? KeepArgs{b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag} : KeepArgs{};
     if (round == 0) {
         k_round_prep<DIM, true, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
-                                                          cloud_of, ta.core_s, n, b.ub, b.ctrl, nullptr, nt);
+                                                          cloud_of, ta.core_s, n, b.ub, b.ctrl, nullptr, nt, ka);
     } else {
         if (!fold) k_tile_carries<<<1, 1024, 0, st>>>(b.run_part, nt, b.run_carry, b.ctrl);
         k_round_prep<DIM, false, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
                                                            cloud_of, ta.core_s, n, b.ub, b.ctrl,
-                                                           fold ? b.run_part : nullptr, nt);
+                                                           fold ? b.run_part : nullptr, nt, ka);
     }
     ta.first = round == 0;
+    ta.all_absorbed = round == 1;
+    ta.kept = keep ? b.qflag : nullptr;
     // variant 13: only the points whose last result no longer holds search
     ta.qlist = nullptr;
     if (uses_qlist(variant, round, n)) {
-        k_reuse_mark<<<nt, 256, 0, st>>>(b.labels, b.ub, b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag,
-                                         b.qcnt, n, b.ctrl);
+        ta.kept = nullptr;
+        k_reuse_mark<<<nt, 256, 0, st>>>(b.labels, b.ub, b.compkey, b.cand_d, b.cand_j, b.qflag, b.qcnt, n,
+                                         b.ctrl);
         if (!fold) k_qlist_scan<<<1, 1024, 0, st>>>(b.qcnt, nt, b.qoff, b.ctrl);
         k_qlist_write<<<nt, 256, 0, st>>>(b.qflag, b.qoff, n, b.qlist, b.ctrl, fold ? b.qcnt : nullptr, nt);
         HIP_TRY(hipGetLastError());
         ta.qlist = b.qlist;
     }
-    // counting runs: the query flags (dead once the list is written) mark
-    // the node records this round's searches load
+    // counting runs: the node heights (dead after the build) mark the node
+    // records this round's searches load
     ta.touched = nullptr;
-    const int64_t words = (n - 1 + 3) / 4;
+    const int64_t words = (n - 1) / 4;  // whole words only: the tail is cleared by bytes
     if (ctx->counting) {
-        k_fill_u32<<<grid_for(words), 256, 0, st>>>(reinterpret_cast<uint32_t*>(b.qflag), words, 0u);
-        ta.touched = b.qflag;
+        k_fill_u32<<<grid_for(words + 1), 256, 0, st>>>(reinterpret_cast<uint32_t*>(b.height), words, 0u);
+        k_fill_u8<<<1, 64, 0, st>>>(b.height + 4 * words, n - 1 - 4 * words, 0u);
+        ta.touched = b.height;
     }
     if (prof) HIP_TRY(hipEventRecord(E[8 + 2 * round], st));
     HIP_TRY(launch_traverse<DIM>(ta, height, variant, ctx->counting, st));
     if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
-    if (ctx->counting) k_count_flags<<<std::min<unsigned>(grid_for(n - 1), 1024), 256, 0, st>>>(b.qflag, n - 1, b.ctrl);
+    if (ctx->counting) k_count_flags<<<std::min<unsigned>(grid_for(n - 1), 1024), 256, 0, st>>>(b.height, n - 1, b.ctrl);
     if (round == 1)
         k_resolve<1><<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
                                                   b.ctrl);

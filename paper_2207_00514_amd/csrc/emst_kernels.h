@@ -30,6 +30,17 @@ struct Ctrl {
     uint32_t pad;
 };
 
+// Search radius of a round from the second on (traversal variant 13): the
+// component bound, lowered to the shortest candidate already offered to the
+// component while components are small (fewer than kTightSize points on
+// average).  Any radius at least the component's shortest outgoing edge
+// gives the same tree; a point that finds nothing keeps its radius as proof
+// for later rounds, and once components are large their radii grow round by
+// round, so the looser bound keeps such points from searching again every
+// round.  The count of the round's components is the one k_relabel left in
+// the control block.
+constexpr uint64_t kTightSize = 2048;
+
 constexpr uint32_t kErrStack = 1u;
 constexpr uint32_t kErrNoEdge = 2u;
 constexpr uint32_t kErrJump = 4u;
@@ -44,6 +55,10 @@ __host__ __device__ inline float ord_dec(uint32_t u) {
     float f;
     __builtin_memcpy(&f, &b, 4);
     return f;
+}
+
+__device__ __forceinline__ bool tight_radius(const Ctrl* ctrl, int64_t n) {
+    return (uint64_t)ctrl->ncomp_next * kTightSize > (uint64_t)n;
 }
 
 }  // namespace emst

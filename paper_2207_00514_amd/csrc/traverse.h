@@ -55,6 +55,13 @@ struct TraverseArgs {
     const uint32_t* qlist;
     // counting runs: one flag per node record, set when a search loads it
     uint8_t* touched;
+    // variant 13 without a list from the third round on: per point, 1 if
+    // it keeps last round's candidate (already offered to its component by
+    // k_round_prep); null otherwise
+    const uint8_t* kept;
+    // the second round: every point's last candidate (its nearest point)
+    // joined its component in the first round
+    bool all_absorbed;
     // launch shape (host side): LDS stack ring entries per lane of variant
     // 13 (4, 8 or 16)
     int lds_depth;
@@ -95,7 +102,7 @@ __device__ __forceinline__ void flush_counts(Ctrl* ctrl, uint64_t internal, uint
 // kNone either way).
 template <int DIM>
 __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t i, uint32_t c, float best_d,
-                                             uint32_t best_j, uint32_t miss = kNone) {
+                                             uint32_t best_j, uint32_t miss = kNone, bool offer = true) {
     const bool valid = i < a.n;
     const bool found = valid && best_j != kNone;
     uint64_t key = kKeyMax;
@@ -104,7 +111,7 @@ __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t
         const uint32_t db = found ? fbits(best_d) : miss;
         a.cand_d[i] = db;
         a.cand_j[i] = best_j;
-        if (found) key = ((uint64_t)db << 32) | (uint64_t)min(oi, best_j);
+        if (found && offer) key = ((uint64_t)db << 32) | (uint64_t)min(oi, best_j);
         if (a.first) {
             a.compkey[c] = key;
             a.compmax[c] = found ? max(oi, best_j) : kNone;
@@ -260,7 +267,13 @@ __device__ __forceinline__ float widen(float radius) { return sqrtf(radius) * 1.
 // still the nearest in (D, j) order and the point skips the search; if it
 // found nothing within last round's radius R, nothing outside lies within
 // R, and it skips the search whenever the new radius does not exceed R.
-// Such a point stores R in cand_d (with cand_j = kNone).  With LIST the
+// Such a point stores R in cand_d (with cand_j = kNone).  If its candidate,
+// at D = pd, has joined its component, no point now outside is nearer than
+// pd (each was outside before), so when pd exceeds the radius nothing is
+// admissible: the point skips the search and stores the float below pd as
+// its R.  The radius itself is the component bound, lowered to the
+// shortest candidate already offered to the component while components
+// are small (tight_radius).  With LIST the
 // lanes take the points of the query list, which holds exactly the points
 // that must search (k_reuse_mark), so waves run full.  A wave of the list
 // spans more than 64 positions; its climb starts at the start node of the
@@ -288,6 +301,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
     }
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
     uint32_t c = kNone, best_j = kNone, miss = kNone;
+    bool offer = true;  // false: a kept candidate, already offered
     float best_d = INFINITY;
     if (i < a.n) {
         float p[DIM];
@@ -295,16 +309,31 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
         for (int k = 0; k < DIM; ++k) p[k] = a.spts[i * DIM + k];
         c = a.labels[i];
         float radius = bitsf(a.ub[c]);
+        if (REUSE && !a.first && tight_radius(a.ctrl, a.n)) {
+            // the kept candidates are real outgoing edges of C too: the
+            // shortest one offered tightens the radius (k_round_prep offered
+            // them before this launch from the third round on; in the second
+            // round the key holds what searches have offered so far)
+            const uint64_t ck = load_relaxed64(&a.compkey[c]);
+            if (ck != kKeyMax) radius = fminf(radius, bitsf((uint32_t)(ck >> 32)));
+        }
         const float core_p = MREACH ? a.core_s[i] : 0.f;
         bool search = true;
         if (REUSE) {
             miss = fbits(radius);
+            // a listed point searches (k_reuse_mark decided with this radius)
             if (!a.first && !LIST) {
                 const uint32_t pj = a.cand_j[i], pd = a.cand_d[i];
                 if (pj != kNone) {
-                    if (a.labels[a.pos[pj]] != c) {
+                    if (!a.all_absorbed && a.kept[i]) {  // offered by k_round_prep
                         best_d = bitsf(pd);
                         best_j = pj;
+                        search = false;
+                        offer = false;
+                    } else if (pd > miss) {
+                        // absorbed, but nothing outside is nearer than pd,
+                        // which lies beyond the radius
+                        miss = pd - 1u;
                         search = false;
                     }
                 } else if (miss <= pd) {
@@ -427,7 +456,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             if (!found) break;
         }
     }
-    finish_query<DIM>(a, i, c, best_d, best_j, miss);
+    finish_query<DIM>(a, i, c, best_d, best_j, miss, offer);
     flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
 }
 
