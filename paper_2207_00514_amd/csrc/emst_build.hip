@@ -290,15 +290,13 @@ template <int DIM>
 // merges or resets it while it is a root.)
 __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ pts, const uint32_t* __restrict__ perm,
                                                 int64_t n, float* __restrict__ spts, uint32_t* __restrict__ orig,
-                                                uint32_t* __restrict__ pos, uint32_t* __restrict__ labels,
-                                                uint64_t* __restrict__ exch) {
+                                                uint32_t* __restrict__ labels, uint64_t* __restrict__ exch) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t o = perm[i];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) spts[i * DIM + k] = pts[(int64_t)o * DIM + k];
     orig[i] = o;
-    pos[o] = (uint32_t)i;
     labels[i] = (uint32_t)i;
     if (i + 1 < n) exch[i] = ~0ull;
 }
@@ -756,7 +754,7 @@ __global__ __launch_bounds__(1024) void k_tile_carries(const uint32_t* __restric
 struct KeepArgs {
     const uint32_t* cand_d;
     const uint32_t* cand_j;
-    const uint32_t* pos;
+    const uint32_t* cand_p;
     const uint32_t* orig;
     uint64_t* compkey;
     uint8_t* kept;
@@ -771,7 +769,7 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ cloud_of,
                                                     const float* __restrict__ core_s, int64_t n, uint32_t* ub,
                                                     Ctrl* ctrl, const uint32_t* __restrict__ fold_part, int nt,
-                                                    KeepArgs keep) {
+                                                    KeepArgs keep, uint32_t* __restrict__ succ) {
     if (ctrl->done) return;
     __shared__ uint32_t s_lab[kRunLds];               // labels of positions base-1 .. base+kRunTile
     __shared__ uint32_t s_rs[FIRST ? 1 : kRunLds];    // start of the run containing each position
@@ -860,6 +858,9 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
             lab2[k] = make_uint2(left ? s_lab[run_lds(x + 1)] : kInvalid,
                                  right ? s_lab[run_lds(x + 2)] : kInvalid);
         }
+        // a component's successor is itself until stage B finds its edge
+        // (the first round's traversal writes every successor itself)
+        if (!FIRST && succ && k < n && s_lab[run_lds(x + 1)] == (uint32_t)k) succ[k] = (uint32_t)k;
     }
     if (!FIRST && keep.kept) {
         uint32_t pj[kRunPer], other[kRunPer];
@@ -869,7 +870,10 @@ __global__ __launch_bounds__(256) void k_round_prep(const uint32_t* __restrict__
             pj[q] = k < n ? keep.cand_j[k] : kNone;
         }
 #pragma unroll
-        for (int q = 0; q < kRunPer; ++q) other[q] = pj[q] != kNone ? keep.pos[pj[q]] : 0u;
+        for (int q = 0; q < kRunPer; ++q) {
+            const int64_t k = base + q * 256 + tid;
+            other[q] = pj[q] != kNone ? keep.cand_p[k] : 0u;
+        }
 #pragma unroll
         for (int q = 0; q < kRunPer; ++q) other[q] = pj[q] != kNone ? labels[other[q]] : kNone;
 #pragma unroll
@@ -1136,17 +1140,24 @@ __global__ __launch_bounds__(256) void k_qlist_write(const uint8_t* __restrict__
 
 // Stage B of the component minimum: among the points whose candidate matches
 // the component's (D bits, min index) key, the smallest max index wins, so
-// the component edge is the minimum under (D, min, max).  PER consecutive
+// the component edge is the minimum under (D, min, max).  Every matching
+// point also names the component at the other end of that edge, the
+// successor of the merge (Section 3, "Merging components together"): if
+// two points of a component match, their common min index cannot be one
+// of them (the other's candidate lies outside), so it is their common
+// candidate; hence all matching points have the same candidate, and write
+// the same successor, the label at its sorted position.  PER consecutive
 // points per thread: 4 (16-byte loads; the arrays are 256-byte aligned)
 // once components span many points, 1 in the round after the first, where
 // they are small and a thread's component-key loads mostly miss.
 template <int PER>
 __global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ cand_d,
                                                  const uint32_t* __restrict__ cand_j,
+                                                 const uint32_t* __restrict__ cand_p,
                                                  const uint32_t* __restrict__ labels,
                                                  const uint32_t* __restrict__ orig,
                                                  const uint64_t* __restrict__ compkey, uint32_t* compmax,
-                                                 int64_t n, const Ctrl* ctrl) {
+                                                 uint32_t* __restrict__ succ, int64_t n, const Ctrl* ctrl) {
     const int64_t i0 = PER * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (i0 >= n || ctrl->done) return;
     uint32_t j[PER], cd[PER], oi[PER], c[PER];
@@ -1182,7 +1193,10 @@ __global__ __launch_bounds__(256) void k_resolve(const uint32_t* __restrict__ ca
     for (int k = 0; k < PER; ++k) {
         if (j[k] == kNone) continue;  // no candidate
         const uint64_t key = ((uint64_t)cd[k] << 32) | (uint64_t)min(oi[k], j[k]);
-        if (key == ck[k]) atomicMin(&compmax[c[k]], max(oi[k], j[k]));
+        if (key == ck[k]) {
+            atomicMin(&compmax[c[k]], max(oi[k], j[k]));
+            succ[c[k]] = labels[cand_p[i0 + k]];
+        }
     }
 }
 
@@ -1201,58 +1215,8 @@ struct RootList {
     int64_t cap;
 };
 
-// Merge, step 1: successor component of every component (the component at
-// the other end of its shortest outgoing edge).
-__device__ __forceinline__ void merge_succ_one(int64_t c, const uint32_t* __restrict__ labels,
-                                               const uint32_t* __restrict__ pos,
-                                               const uint64_t* __restrict__ compkey,
-                                               const uint32_t* __restrict__ compmax,
-                                               const uint32_t* __restrict__ orig, uint32_t* succ, Ctrl* ctrl,
-                                               bool allow_isolated, bool first) {
-    const uint64_t key = compkey[c];
-    const uint32_t v = compmax[c];
-    if (key == kKeyMax || v == kNone) {
-        // only a component that is a whole cloud of a batch has no edge
-        if (!allow_isolated) atomicOr(&ctrl->error, kErrNoEdge);
-        succ[c] = (uint32_t)c;
-        return;
-    }
-    const uint32_t u = (uint32_t)(key & 0xFFFFFFFFu);
-    if (first) {
-        // first round: component c is the point at position c alone, and a
-        // point's label is its position
-        const uint32_t own = orig[c];
-        if (u != own && v != own) atomicOr(&ctrl->error, kErrNoEdge);
-        succ[c] = pos[u == own ? v : u];
-        return;
-    }
-    const uint32_t lu = labels[pos[u]], lv = labels[pos[v]];
-    if (lu != (uint32_t)c && lv != (uint32_t)c) atomicOr(&ctrl->error, kErrNoEdge);
-    succ[c] = (lu == (uint32_t)c) ? lv : lu;
-}
-
-// First round: one thread per position.  Later rounds: the root list.
-__global__ __launch_bounds__(256) void k_merge_succ(const uint32_t* __restrict__ labels,
-                                                    const uint32_t* __restrict__ pos,
-                                                    const uint64_t* __restrict__ compkey,
-                                                    const uint32_t* __restrict__ compmax,
-                                                    const uint32_t* __restrict__ orig, uint32_t* succ,
-                                                    Ctrl* ctrl, int64_t n, bool allow_isolated, bool first,
-                                                    RootList rl) {
-    if (ctrl->done) return;
-    if (first) {
-        const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (c < n && labels[c] == (uint32_t)c)
-            merge_succ_one(c, labels, pos, compkey, compmax, orig, succ, ctrl, allow_isolated, true);
-        return;
-    }
-    const uint32_t* seg = rl.in + rl.cap * blockIdx.x;
-    const int64_t cnt = rl.cnt_in[blockIdx.x];
-    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
-        merge_succ_one(seg[i], labels, pos, compkey, compmax, orig, succ, ctrl, allow_isolated, false);
-}
-
-// Merge, step 2: the chains of successors end in a mutual pair (Section 2);
+// Merge, step 1 (the successors come from stage B, or in the first round
+// from the traversal): the chains of successors end in a mutual pair (Section 2);
 // the smaller label of that pair becomes the root of the merged component
 // ("Merging components together").  Every other component emits its edge,
 // so a mutual pair contributes its shared edge once.  Roots reset their
@@ -1264,7 +1228,8 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ succ, uint32_t* par,
                                                       uint64_t* compkey, uint32_t* compmax, uint32_t* ub,
                                                       uint4* __restrict__ eud, uint2* __restrict__ part,
-                                                      const Ctrl* ctrl, int64_t n, bool first, RootList rl) {
+                                                      Ctrl* ctrl, int64_t n, bool first, RootList rl,
+                                                      bool allow_isolated) {
     if (ctrl->done) return;
     __shared__ uint32_t s_cnt[2];
     if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
@@ -1291,6 +1256,8 @@ __global__ __launch_bounds__(256) void k_merge_parent(const uint32_t* __restrict
         bool root = false;
         if (comp) {
             const uint32_t s = succ[c];
+            // only a component that is a whole cloud of a batch has no edge
+            if (s == (uint32_t)c && !allow_isolated) atomicOr(&ctrl->error, kErrNoEdge);
             root = (s == (uint32_t)c) || (succ[s] == (uint32_t)c && (uint32_t)c < s);
             par[c] = root ? (uint32_t)c : s;
         }
@@ -1766,7 +1733,7 @@ __global__ __launch_bounds__(256) void k_batch_edge_write(const uint4* __restric
 // workspace layout
 
 struct Layout {
-    size_t ctrl, bpart, k0, k1, v0, v1, hist, spts, orig, pos, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_part, run_carry, qcnt, qoff, qflag, qlist, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, core_s, core_o, total;
+    size_t ctrl, bpart, k0, k1, v0, v1, hist, spts, orig, cand_p, recs, lab2, height, node_parent, leaf_parent, up, exch, rlo, rhi, run_part, run_carry, qcnt, qoff, qflag, qlist, labels, ub, compkey, compmax, succ, par, cand_d, cand_j, eud, core_s, core_o, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1806,7 +1773,7 @@ static Layout make_layout(int64_t n, int dim) {
     L.hist = take(4 * radix_hist_elems());
     L.spts = take(4 * N * dim);
     L.orig = take(4 * N);
-    L.pos = take(4 * N);
+    L.cand_p = take(4 * N);
     L.recs = take(M * (dim == 3 ? sizeof(Rec<3>) : sizeof(Rec<2>)));
     L.lab2 = take(8 * M);
     L.height = take(M);
@@ -2097,7 +2064,7 @@ hipError_t propagate_labels(const uint32_t* labels, uint32_t* run_part, uint32_t
     k_run_partials<<<nb, 256, 0, st>>>(labels, n, run_part);
     k_tile_carries<<<1, 1024, 0, st>>>(run_part, nb, run_carry, ctrl);
     k_round_prep<3, false, false><<<nb, 256, 0, st>>>(labels, run_carry, rlo, rhi, lab2, nullptr, nullptr, nullptr,
-                                                      n, nullptr, ctrl, nullptr, nb, KeepArgs{});
+                                                      n, nullptr, ctrl, nullptr, nb, KeepArgs{}, nullptr);
     return hipGetLastError();
 }
 
@@ -2109,7 +2076,7 @@ struct Bufs {
     uint64_t *k0, *k1;
     uint32_t *v0, *v1, *hist;
     float* spts;
-    uint32_t *orig, *pos;
+    uint32_t *orig, *cand_p;
     Rec<DIM>* recs;
     uint2* lab2;
     uint8_t* height;
@@ -2137,7 +2104,7 @@ Bufs<DIM> carve(char* ws, const Layout& L) {
     b.hist = reinterpret_cast<uint32_t*>(ws + L.hist);
     b.spts = reinterpret_cast<float*>(ws + L.spts);
     b.orig = reinterpret_cast<uint32_t*>(ws + L.orig);
-    b.pos = reinterpret_cast<uint32_t*>(ws + L.pos);
+    b.cand_p = reinterpret_cast<uint32_t*>(ws + L.cand_p);
     b.recs = reinterpret_cast<Rec<DIM>*>(ws + L.recs);
     b.lab2 = reinterpret_cast<uint2*>(ws + L.lab2);
     b.height = reinterpret_cast<uint8_t*>(ws + L.height);
@@ -2177,7 +2144,8 @@ TraverseArgs<DIM> traverse_args(const Bufs<DIM>& b, int64_t n, uint32_t root) {
     ta.wave_lca = reinterpret_cast<const uint32_t*>(b.exch);  // the build's exchange words are free by now
     ta.core_s = nullptr;
     ta.core_o = nullptr;
-    ta.pos = b.pos;
+    ta.cand_p = b.cand_p;
+    ta.succ = b.succ;
     ta.qlist = nullptr;
     ta.touched = nullptr;
     ta.kept = nullptr;
@@ -2256,15 +2224,16 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     // (in round 1 none is kept: every point joined its candidate's
     // component in round 0)
     const bool keep = variant == 13 && round >= 2;
-    const KeepArgs ka = keep ? KeepArgs{b.cand_d, b.cand_j, b.pos, b.orig, b.compkey, b.qflag} : KeepArgs{};
+    const KeepArgs ka = keep ? KeepArgs{b.cand_d, b.cand_j, b.cand_p, b.orig, b.compkey, b.qflag} : KeepArgs{};
     if (round == 0) {
         k_round_prep<DIM, true, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
-                                                          cloud_of, ta.core_s, n, b.ub, b.ctrl, nullptr, nt, ka);
+                                                          cloud_of, ta.core_s, n, b.ub, b.ctrl, nullptr, nt, ka,
+                                                          b.succ);
     } else {
         if (!fold) k_tile_carries<<<1, 1024, 0, st>>>(b.run_part, nt, b.run_carry, b.ctrl);
         k_round_prep<DIM, false, true><<<nt, 256, 0, st>>>(b.labels, b.run_carry, b.rlo, b.rhi, b.lab2, b.spts,
                                                            cloud_of, ta.core_s, n, b.ub, b.ctrl,
-                                                           fold ? b.run_part : nullptr, nt, ka);
+                                                           fold ? b.run_part : nullptr, nt, ka, b.succ);
     }
     ta.first = round == 0;
     ta.all_absorbed = round == 1;
@@ -2294,11 +2263,11 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     if (prof) HIP_TRY(hipEventRecord(E[9 + 2 * round], st));
     if (ctx->counting) k_count_flags<<<std::min<unsigned>(grid_for(n - 1), 1024), 256, 0, st>>>(b.height, n - 1, b.ctrl);
     if (round == 1)
-        k_resolve<1><<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey, b.compmax, n,
-                                                  b.ctrl);
+        k_resolve<1><<<grid_for(n), 256, 0, st>>>(b.cand_d, b.cand_j, b.cand_p, b.labels, b.orig, b.compkey,
+                                                  b.compmax, b.succ, n, b.ctrl);
     else if (round > 1)
-        k_resolve<4><<<grid_for((n + 3) / 4), 256, 0, st>>>(b.cand_d, b.cand_j, b.labels, b.orig, b.compkey,
-                                                            b.compmax, n, b.ctrl);
+        k_resolve<4><<<grid_for((n + 3) / 4), 256, 0, st>>>(b.cand_d, b.cand_j, b.cand_p, b.labels, b.orig,
+                                                            b.compkey, b.compmax, b.succ, n, b.ctrl);
     if (cap)
         k_test_capture<<<grid_for(n), 256, 0, st>>>(b.labels, b.orig, b.ub, b.cand_d, b.cand_j, b.compkey,
                                                     b.compmax, n, *cap);
@@ -2315,10 +2284,9 @@ int enqueue_round(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n,
     rl.cnt_out = counts + kPartBlocks * ((round + 1) & 1);
     rl.cap = root_list_cap(n);
     const unsigned merge_grid = first ? grid_for(n) : (unsigned)mp_blocks;
-    k_merge_succ<<<merge_grid, 256, 0, st>>>(b.labels, b.pos, b.compkey, b.compmax, b.orig, b.succ, b.ctrl, n,
-                                             cloud_of != nullptr, first, rl);
     k_merge_parent<<<mp_blocks, 256, 0, st>>>(b.labels, b.succ, b.par, b.compkey, b.compmax, b.ub, b.eud,
-                                              reinterpret_cast<uint2*>(b.bpart), b.ctrl, n, first, rl);
+                                              reinterpret_cast<uint2*>(b.bpart), b.ctrl, n, first, rl,
+                                              cloud_of != nullptr);
     HIP_TRY(hipGetLastError());
     k_merge_jump<<<merge_grid, 256, 0, st>>>(b.labels, b.par, n, 1024, b.ctrl, first, rl);
     k_relabel<<<nt, 256, 0, st>>>(b.labels, b.par, n, 4096, b.run_part, reinterpret_cast<const uint2*>(b.bpart),
@@ -2724,7 +2692,7 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
         HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, 8, &j.codes_in1));
         const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
         k_count_dups<<<grid_for(n), 256, 0, st>>>(codes, n, b.ctrl);
-        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig, b.pos,
+        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig,
                                                    b.labels, b.exch);
         if (int rc = build_hierarchy<DIM>(ctx, b, codes, n, st)) return rc;
         break;
@@ -2746,7 +2714,7 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
         for (int s = 0; s < DIM * bits; s += 8) csh[cq++] = s;
         HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, csh, cq, &j.codes_in1));
         const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
-        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig, b.pos,
+        k_gather<DIM><<<grid_for(n), 256, 0, st>>>(j.pts, j.codes_in1 ? b.v1 : b.v0, n, b.spts, b.orig,
                                                    b.labels, b.exch);
         if (int rc = build_hierarchy<DIM>(ctx, b, codes, n, st)) return rc;
         break;
@@ -3032,7 +3000,7 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     const uint64_t* codes = in1 ? b.k1 : b.k0;
     const uint32_t* perm = in1 ? b.v1 : b.v0;
     // ---- one tree over all clouds
-    k_gather<3><<<grid_for(n), 256, 0, st>>>(pts3, perm, n, b.spts, b.orig, b.pos, b.labels, b.exch);
+    k_gather<3><<<grid_for(n), 256, 0, st>>>(pts3, perm, n, b.spts, b.orig, b.labels, b.exch);
     // a batch of single points runs no round, so every edge slot starts empty
     k_fill_u32<<<grid_for(4 * n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(b.eud), 4 * n, kNone);
     k_batch_sorted_cloud<<<grid_for(n), 256, 0, st>>>(cloud_of, perm, n, cloud_sorted);
@@ -3493,14 +3461,15 @@ __global__ __launch_bounds__(256) void k_test_reps(const int32_t* __restrict__ c
 
 // ... becomes the label of its points, and every component starts the
 // round as k_merge_parent leaves a root (no bound, no key, no edge).  Every
-// point starts with its own index as its last candidate, which lies in its
-// own component, so no earlier result is reused.
+// point starts with itself as its last candidate (index and position),
+// which lies in its own component, so no earlier result is reused.
 __global__ __launch_bounds__(256) void k_test_labels(const int32_t* __restrict__ comp,
                                                      const uint32_t* __restrict__ orig,
                                                      const uint32_t* __restrict__ rep, int64_t n,
                                                      uint32_t* __restrict__ labels, uint32_t* __restrict__ ub,
                                                      uint64_t* __restrict__ compkey, uint32_t* __restrict__ compmax,
-                                                     uint32_t* __restrict__ cand_d, uint32_t* __restrict__ cand_j) {
+                                                     uint32_t* __restrict__ cand_d, uint32_t* __restrict__ cand_j,
+                                                     uint32_t* __restrict__ cand_p) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const uint32_t o = orig[p];
@@ -3508,6 +3477,7 @@ __global__ __launch_bounds__(256) void k_test_labels(const int32_t* __restrict__
     labels[p] = l;
     cand_j[p] = o;
     cand_d[p] = 0u;
+    cand_p[p] = (uint32_t)p;
     if (l == (uint32_t)p) {
         ub[p] = kInfBits;
         compkey[p] = kKeyMax;
@@ -3561,7 +3531,7 @@ int test_round(emst_ctx* ctx, const float* pts, int64_t n, const int32_t* comp, 
     k_fill_u32<<<grid_for(n), 256, 0, st>>>(b.succ, n, kNone);
     k_test_reps<<<grid_for(n), 256, 0, st>>>(comp, b.orig, n, b.succ);
     k_test_labels<<<grid_for(n), 256, 0, st>>>(comp, b.orig, b.succ, n, b.labels, b.ub, b.compkey, b.compmax,
-                                               b.cand_d, b.cand_j);
+                                               b.cand_d, b.cand_j, b.cand_p);
     k_run_partials<<<run_tiles(n), 256, 0, st>>>(b.labels, n, b.run_part);
     RootList rl;
     uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(b.k0), reinterpret_cast<uint32_t*>(b.k1)};
@@ -3769,7 +3739,7 @@ extern "C" int emst_test_tree_boxes(emst_ctx* ctx, const float* d_points, int64_
     HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, shifts, 8, &in1));
     const uint64_t* codes = in1 ? b.k1 : b.k0;
     const uint32_t* perm = in1 ? b.v1 : b.v0;
-    k_gather<3><<<grid_for(n), 256, 0, st>>>(d_points, perm, n, b.spts, b.orig, b.pos, b.labels, b.exch);
+    k_gather<3><<<grid_for(n), 256, 0, st>>>(d_points, perm, n, b.spts, b.orig, b.labels, b.exch);
     if (int rc = build_tree<3>(ctx, b, codes, n, st)) return rc;
     k_test_boxes<<<grid_for(n - 1), 256, 0, st>>>(b.recs, n - 1, d_left, d_right, d_lo, d_hi);
     HIP_TRY(hipGetLastError());

@@ -49,7 +49,12 @@ struct TraverseArgs {
     // original index (null for the Euclidean tree)
     const float* core_s;
     const float* core_o;
-    const uint32_t* pos;  // sorted position of every original index
+    // each point's candidate: its sorted position (the leaf children of
+    // record k are positions k and k + 1), written with cand_d / cand_j
+    uint32_t* cand_p;
+    // the first round: the successor of every component (the component of
+    // its one point's candidate), written by the traversal itself
+    uint32_t* succ;
     // this round's query list (the points that still search, in Morton
     // order; length ctrl->qcount)
     const uint32_t* qlist;
@@ -102,7 +107,8 @@ __device__ __forceinline__ void flush_counts(Ctrl* ctrl, uint64_t internal, uint
 // kNone either way).
 template <int DIM>
 __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t i, uint32_t c, float best_d,
-                                             uint32_t best_j, uint32_t miss = kNone, bool offer = true) {
+                                             uint32_t best_j, uint32_t best_p, uint32_t miss = kNone,
+                                             bool offer = true) {
     const bool valid = i < a.n;
     const bool found = valid && best_j != kNone;
     uint64_t key = kKeyMax;
@@ -111,10 +117,16 @@ __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t
         const uint32_t db = found ? fbits(best_d) : miss;
         a.cand_d[i] = db;
         a.cand_j[i] = best_j;
-        if (found && offer) key = ((uint64_t)db << 32) | (uint64_t)min(oi, best_j);
+        if (found && offer) {  // (a kept candidate's position is already stored)
+            key = ((uint64_t)db << 32) | (uint64_t)min(oi, best_j);
+            a.cand_p[i] = best_p;
+        }
         if (a.first) {
+            // the point is its component (label = position = i), and a
+            // point's label is its position
             a.compkey[c] = key;
             a.compmax[c] = found ? max(oi, best_j) : kNone;
+            a.succ[c] = found ? best_p : c;
         }
     }
     if (a.first) return;
@@ -131,8 +143,8 @@ __device__ __forceinline__ void finish_query(const TraverseArgs<DIM>& a, int64_t
 // first, deferred children re-checked against the radius when popped).
 template <int DIM, int STACK, bool COUNT>
 __device__ __forceinline__ void descend(const TraverseArgs<DIM>& a, uint32_t node, const float* p, uint32_t c,
-                                        float& radius, float& best_d, uint32_t& best_j, uint64_t& n_int,
-                                        uint64_t& n_leaf, uint64_t& n_eval) {
+                                        float& radius, float& best_d, uint32_t& best_j, uint32_t& best_p,
+                                        uint64_t& n_int, uint64_t& n_leaf, uint64_t& n_eval) {
     uint32_t st_node[STACK];
     float st_d[STACK];
     int sp = 0;
@@ -163,7 +175,12 @@ __device__ __forceinline__ void descend(const TraverseArgs<DIM>& a, uint32_t nod
             if (d > radius) continue;
             if (leaf) {
                 const uint32_t j = ch[s].ref & ~kLeafFlag;
-                if (better(d, j, best_d, best_j)) { best_d = d; best_j = j; radius = d; }
+                if (better(d, j, best_d, best_j)) {
+                    best_d = d;
+                    best_j = j;
+                    best_p = node + (uint32_t)s;  // leaf children of record k: positions k, k + 1
+                    radius = d;
+                }
             } else {
                 go[s] = true;
                 dd[s] = d;
@@ -203,7 +220,7 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
     if (a.ctrl->done) return;  // the round loop has already finished
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
-    uint32_t c = kNone, best_j = kNone;
+    uint32_t c = kNone, best_j = kNone, best_p = kNone;
     float best_d = INFINITY;
     if (i < a.n) {
         float p[DIM];
@@ -212,9 +229,10 @@ __global__ __launch_bounds__(256) void k_traverse_lane(TraverseArgs<DIM> a) {
         c = a.labels[i];
         float radius = bitsf(a.ub[c]);
         const uint32_t root = start_node<DIM>(a, i);
-        if (root != kNone) descend<DIM, STACK, COUNT>(a, root, p, c, radius, best_d, best_j, n_int, n_leaf, n_eval);
+        if (root != kNone) descend<DIM, STACK, COUNT>(a, root, p, c, radius, best_d, best_j, best_p, n_int, n_leaf,
+                                       n_eval);
     }
-    finish_query<DIM>(a, i, c, best_d, best_j);
+    finish_query<DIM>(a, i, c, best_d, best_j, best_p);
     flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
 }
 
@@ -300,7 +318,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
         i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + t;
     }
     uint64_t n_int = 0, n_leaf = 0, n_eval = 0;
-    uint32_t c = kNone, best_j = kNone, miss = kNone;
+    uint32_t c = kNone, best_j = kNone, best_p = kNone, miss = kNone;
     bool offer = true;  // false: a kept candidate, already offered
     float best_d = INFINITY;
     if (i < a.n) {
@@ -405,8 +423,12 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 const bool b0 = in0 & l0 & (m0 <= radius);
                 const bool b1 = in1 & l1 & (m1 <= radius);
                 uint64_t bk = ((uint64_t)fbits(best_d) << 32) | best_j;
-                bk = (b0 & (k0 < bk)) ? k0 : bk;
-                bk = (b1 & (k1 < bk)) ? k1 : bk;
+                const bool t0 = b0 & (k0 < bk);
+                bk = t0 ? k0 : bk;
+                const bool t1 = b1 & (k1 < bk);
+                bk = t1 ? k1 : bk;
+                // the leaf children of record k are sorted positions k, k + 1
+                best_p = t1 ? node + 1u : (t0 ? node : best_p);
                 const float nd = bitsf((uint32_t)(bk >> 32));
                 if (SHARED && nd < radius) atomicMin(&a.ub[c], fbits(nd));
                 best_d = nd;
@@ -456,7 +478,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             if (!found) break;
         }
     }
-    finish_query<DIM>(a, i, c, best_d, best_j, miss, offer);
+    finish_query<DIM>(a, i, c, best_d, best_j, best_p, miss, offer);
     flush_counts<COUNT>(a.ctrl, n_int, n_leaf, n_eval);
 }
 
