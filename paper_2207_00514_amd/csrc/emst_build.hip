@@ -1443,17 +1443,22 @@ __global__ __launch_bounds__(256) void k_relabel(uint32_t* labels, const uint32_
 // exceed any small bound and the full path then costs 9 ms more.)
 constexpr int kMaxTieRun = 32;
 
+// keys (D bits, u); values: the slot ids, or with v_values the v of every
+// edge (one cloud: the sort then carries the whole edge, and the write
+// reads it in order)
 __global__ __launch_bounds__(256) void k_edge_du_keys(const uint4* __restrict__ eud, int64_t m,
-                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                      bool v_values) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     const uint4 s = eud[e];
     keys[e] = ((uint64_t)s.z << 32) | (uint64_t)s.x;
-    vals[e] = (uint32_t)e;
+    vals[e] = v_values ? s.y : (uint32_t)e;
 }
 
 __global__ __launch_bounds__(256) void k_tie_fix(const uint64_t* __restrict__ keys, uint32_t* __restrict__ order,
-                                                 const uint4* __restrict__ eud, int64_t m, Ctrl* ctrl) {
+                                                 const uint4* __restrict__ eud, int64_t m, Ctrl* ctrl,
+                                                 bool v_values) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r + 1 >= m) return;
     const uint64_t k = keys[r];
@@ -1468,10 +1473,13 @@ __global__ __launch_bounds__(256) void k_tie_fix(const uint64_t* __restrict__ ke
     const int len = (int)(e - r);
     uint32_t id[kMaxTieRun];
     uint64_t uv[kMaxTieRun];
-    for (int t = 0; t < len; ++t) {  // insertion sort by (u, v)
+    for (int t = 0; t < len; ++t) {  // insertion sort by (u, v); u is the run's
         const uint32_t x = order[r + t];
-        const uint4 s = eud[x];
-        const uint64_t y = ((uint64_t)s.x << 32) | s.y;
+        uint64_t y = x;  // v_values: the value is v
+        if (!v_values) {
+            const uint4 s = eud[x];
+            y = ((uint64_t)s.x << 32) | s.y;
+        }
         int q = t;
         while (q > 0 && uv[q - 1] > y) {
             uv[q] = uv[q - 1];
@@ -1509,6 +1517,21 @@ __global__ __launch_bounds__(256) void k_perm_keys(const uint32_t* __restrict__ 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     keys[i] = (uint64_t)src[perm[i]];
+}
+
+// One cloud: edge i is (u, v) = (low word of keys[i], v[i]) with D bits
+// the high word, all read in order.
+__global__ __launch_bounds__(256) void k_edge_write_kv(const uint64_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ v, int64_t m,
+                                                       int32_t* __restrict__ edges, float* __restrict__ w,
+                                                       float* __restrict__ d2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t k = keys[i];
+    const float d = bitsf((uint32_t)(k >> 32));
+    reinterpret_cast<int2*>(edges)[i] = make_int2((int32_t)(uint32_t)k, (int32_t)v[i]);
+    w[i] = edge_weight(d);
+    if (d2) d2[i] = d;
 }
 
 __global__ __launch_bounds__(256) void k_edge_write(const uint4* __restrict__ eud, const uint32_t* __restrict__ perm,
@@ -2486,13 +2509,16 @@ int run_rounds(emst_ctx* ctx, Bufs<DIM>& b, TraverseArgs<DIM>& ta, int64_t n, in
 // then, for a batch, stably by cloud.
 template <int DIM>
 int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_cloud, int cloud_bits, bool full,
-               const uint32_t** order, hipStream_t st) {
+               const uint32_t** order, hipStream_t st, const uint64_t** keys_out = nullptr) {
     int in1 = 0;
     const int ib = 32 - __builtin_clz((unsigned)(n - 1));  // bits of the largest index
     uint32_t *p, *p_alt;
     uint64_t *kd, *kd_alt;
+    // one cloud's fast path sorts the v of every edge as its value
+    const bool v_values = !full && !slot_cloud && keys_out;
+    if (keys_out) *keys_out = nullptr;
     if (!full) {
-        k_edge_du_keys<<<grid_for(n), 256, 0, st>>>(b.eud, n, b.k0, b.v0);
+        k_edge_du_keys<<<grid_for(n), 256, 0, st>>>(b.eud, n, b.k0, b.v0, v_values);
         int sh[8], q = 0;
         for (int s = 0; s < ib; s += 8) sh[q++] = s;
         for (int s = 32; s < 64; s += 8) sh[q++] = s;
@@ -2501,7 +2527,8 @@ int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_clou
         kd = in1 ? b.k1 : b.k0;
         kd_alt = in1 ? b.k0 : b.k1;
         p_alt = in1 ? b.v0 : b.v1;
-        k_tie_fix<<<grid_for(n), 256, 0, st>>>(kd, p, b.eud, n, b.ctrl);
+        k_tie_fix<<<grid_for(n), 256, 0, st>>>(kd, p, b.eud, n, b.ctrl, v_values);
+        if (v_values) *keys_out = kd;
     } else {
         k_edge_keys<<<grid_for(n), 256, 0, st>>>(b.eud, n, b.k0, b.v0);
         int sh[8], q = 0;
@@ -2755,8 +2782,12 @@ int job_enqueue(emst_ctx* ctx, Job& j, hipStream_t st) {
     }
     case kPhFinal: {  // canonical order (the full sort only after a long run of ties)
         const uint32_t* order = nullptr;
-        if (int rc = sort_edges<DIM>(ctx, b, n, nullptr, 0, j.full != 0, &order, st)) return rc;
-        k_edge_write<<<grid_for(n - 1), 256, 0, st>>>(b.eud, order, n - 1, j.edges, j.weights, j.d2);
+        const uint64_t* keys = nullptr;
+        if (int rc = sort_edges<DIM>(ctx, b, n, nullptr, 0, j.full != 0, &order, st, &keys)) return rc;
+        if (keys)  // the sorted keys and values are the edges
+            k_edge_write_kv<<<grid_for(n - 1), 256, 0, st>>>(keys, order, n - 1, j.edges, j.weights, j.d2);
+        else
+            k_edge_write<<<grid_for(n - 1), 256, 0, st>>>(b.eud, order, n - 1, j.edges, j.weights, j.d2);
         HIP_TRY(hipGetLastError());
         if (j.prof) HIP_TRY(hipEventRecord(E[3], st));
         break;

@@ -376,11 +376,17 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             }
             node = s;
         }
-        for (int64_t guard = 0; mask; ++guard) {
-            if (guard > 2 * a.n + 256) {
+        // Every iteration processes one node or pops one deferred node, so
+        // lanes that discard stale entries do not hold the others in a loop
+        // of their own.  A search visits each internal node once and pops
+        // each deferred node once.
+        bool have = mask != 0u;  // a node to process this iteration
+        for (int64_t guard = 0;; ++guard) {
+            if (guard > 4 * a.n + 256) {
                 atomicOr(&a.ctrl->error, kErrStack);
                 break;
             }
+            if (have) {
             const Rec<DIM> r = a.recs[node];
             if (COUNT) a.touched[node] = 1;
             Child<DIM> c0, c1;
@@ -399,12 +405,12 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             if (SHARED) radius = fminf(radius, bitsf(load_relaxed(&a.ub[c])));
             const float d0 = boxdist<DIM>(p, c0.lo, c0.hi);
             const float d1 = boxdist<DIM>(p, c1.lo, c1.hi);
-            const bool in0 = (mask & 1u) && c0.lab != c;
-            const bool in1 = (mask & 2u) && c1.lab != c;
+            const bool in0 = c0.lab != c;
+            const bool in1 = c1.lab != c;
             const bool l0 = (c0.ref & kLeafFlag) != 0u, l1 = (c1.ref & kLeafFlag) != 0u;
             if (COUNT) {
-                n_leaf += ((mask & 1u) && l0) + ((mask & 2u) && l1);
-                n_int += ((mask & 1u) && !l0) + ((mask & 2u) && !l1);
+                n_leaf += l0 + l1;
+                n_int += !l0 + !l1;
                 n_eval += (in0 && l0) + (in1 && l1);
             }
             // leaf candidates: (D, j) order, radius follows the best.  D >= 0,
@@ -437,7 +443,6 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             }
             const bool go0 = in0 && !l0 && d0 <= radius;
             const bool go1 = in1 && !l1 && d1 <= radius;
-            mask = 3u;
             if (go0 && go1) {
                 const bool near1 = d1 < d0;
                 const uint2 far = make_uint2(near1 ? c0.ref : c1.ref, fbits(near1 ? d0 : d1));
@@ -452,14 +457,14 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 }
                 lds[sp % kLdsDepth][t] = far;
                 ++sp;
-                continue;
-            }
-            if (go0 || go1) {
+            } else if (go0 || go1) {
                 node = go0 ? c0.ref : c1.ref;
-                continue;
+            } else {
+                have = false;
             }
-            bool found = false;
-            while (sp > 0) {
+            }
+            if (!have) {
+                if (sp == 0) break;
                 if (sp == base) {
                     // ring empty: move spilled entries back first (rare), so
                     // that every pop is a plain LDS read
@@ -469,13 +474,11 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 }
                 --sp;
                 const uint2 e = lds[sp % kLdsDepth][t];
-                if (bitsf(e.y) <= radius) {
+                if (bitsf(e.y) <= radius) {  // else the next iteration pops again
                     node = e.x;
-                    found = true;
-                    break;
+                    have = true;
                 }
             }
-            if (!found) break;
         }
     }
     finish_query<DIM>(a, i, c, best_d, best_j, best_p, miss, offer);
