@@ -414,8 +414,10 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 n_eval += (in0 && l0) + (in1 && l1);
             }
             // leaf candidates: (D, j) order, radius follows the best.  D >= 0,
-            // so (D bits, j) as one 64-bit integer has the same order.
-            {
+            // so (D bits, j) as one 64-bit integer has the same order.  (Most
+            // nodes a search visits have no leaf child: the whole block is
+            // skipped unless some lane of the wave meets one.)
+            if ((in0 & l0) | (in1 & l1)) {
                 float m0 = d0, m1 = d1;
                 if (MREACH) {  // a leaf box is its point, so d0 / d1 are the exact D
                     const uint32_t j0 = c0.ref & ~kLeafFlag, j1 = c1.ref & ~kLeafFlag;
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 if (SHARED && nd < radius) atomicMin(&a.ub[c], fbits(nd));
                 best_d = nd;
                 best_j = (uint32_t)bk;
-                radius = fminf(radius, best_d);
+                radius = nd < radius ? nd : radius;  // (no NaN: every coordinate is finite)
             }
             const bool go0 = in0 && !l0 && d0 <= radius;
             const bool go1 = in1 && !l1 && d1 <= radius;
