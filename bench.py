@@ -496,7 +496,7 @@ def serving_leg(args) -> dict:
         if kind == "batched":
             return serve.Server(workers=nw, max_batch=64, budget_bytes=16 << 30)
         if kind == "solver":
-            return serve.SolverServer(budget_bytes=16 << 30, max_slots=64)
+            return serve.SolverServer(budget_bytes=16 << 30, max_slots=256)
         return serve.FifoServer()
 
     def run(kind, rate, reqs):

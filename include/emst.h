@@ -200,19 +200,24 @@ int emst_build_mreach(emst_ctx *ctx, const float *d_points, int64_t n, int dim, 
 
 /*
  * Round-granular continuous batching (serving).  A solver keeps up to
- * max_slots requests inside a caller-provided device budget.  Each
- * emst_solver_step advances every running request by one phase -- its
- * tree, then one Boruvka round per step, then its edge order -- and waits
- * once for all of them, so a request admitted between two steps starts at
- * the next one while the others continue.  Every result is exactly
- * emst_build of that request alone.  All calls on one solver must come
- * from one thread; the budget must stay allocated until
- * emst_solver_destroy.
+ * max_slots requests inside a caller-provided device budget.  The requests
+ * admitted between two steps start together at the next emst_solver_step
+ * as one cohort: a batch as emst_build_batched builds it (one tree, one
+ * round loop for all of them).  Each step advances every live cohort by one
+ * phase -- per-cloud boxes, Morton codes, tree, boxes and the first round,
+ * then one Boruvka round per step, then the edge order -- and waits once
+ * for all of them, so a request admitted while others run starts at the
+ * next step.  Every result is exactly emst_build of that request alone.
+ * All calls on one solver must come from one thread; the budget must stay
+ * allocated until emst_solver_destroy.
  */
 typedef struct emst_solver emst_solver;
 
-/* Budget bytes one request of n points of dimension dim occupies (points,
- * workspace and outputs); 0 for invalid arguments. */
+/* Budget bytes one request of n points of dimension dim holds from admit to
+ * take (its points while it waits, the workspace and outputs of a cohort of
+ * that request alone); 0 for invalid arguments.  The requests admitted
+ * together share one cohort region of at most the sum of their shares; a
+ * finished cohort keeps only its outputs until its last result is taken. */
 size_t emst_solver_slot_bytes(int64_t n, int dim);
 
 /* d_budget: device memory of budget_bytes, 256-byte aligned, owned by the
@@ -223,18 +228,23 @@ int emst_solver_create(emst_ctx *ctx, void *d_budget, size_t budget_bytes, int32
 void emst_solver_destroy(emst_solver *solver);
 
 /* Admit a request: copies d_points [n][dim] into the budget (on `stream`)
- * and returns its slot.  EMST_EBUSY if no slot or no contiguous budget is
- * free now (retry after emst_solver_take), EMST_ENOMEM if the request does
- * not fit even an empty budget, EMST_EINVAL for bad arguments.  A request
- * of 0 or 1 point is finished at once.  Input problems of the points
- * (non-finite, overflowing extent) surface as the slot's status. */
+ * and returns its slot.  EMST_EBUSY if no slot is free, or the shares of
+ * the requests not yet taken leave less than this one's, or its points find
+ * no contiguous range (retry after emst_solver_take); EMST_ENOMEM if the
+ * request does not fit even an empty budget; EMST_EINVAL for bad
+ * arguments.  A request of 0 or 1 point is finished at once.  Input
+ * problems of the points (non-finite, overflowing extent) surface as the
+ * slot's status; the other requests of its cohort go on without it. */
 int emst_solver_admit(emst_solver *solver, const float *d_points, int64_t n, int32_t dim, int64_t tag,
                       void *stream, int32_t *slot);
 
-/* One phase for every running request; returns when all of them are done.
- * The requests run on a few streams of the solver (default priority),
- * after the work already queued on `stream`.  *n_finished (nullable) =
- * requests that finished or failed in this step. */
+/* Start a cohort of the requests admitted since the last step (as many, in
+ * admission order, as fit one contiguous free range; the others wait for
+ * the next step), then one phase for every live cohort; returns when all
+ * of them are done.  Cohorts run on a few streams of the solver (default
+ * priority), after the work already queued on `stream`.  A request that
+ * finds no range while no cohort holds memory fails with EMST_ENOMEM.
+ * *n_finished (nullable) = requests that finished or failed in this step. */
 int emst_solver_step(emst_solver *solver, void *stream, int32_t *n_finished);
 
 /* *state: 0 free, 1 running, 2 finished, < 0 failed with that status;

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/emst.h"
@@ -1573,21 +1574,82 @@ struct CloudMorton {   // host -> device, per cloud
     int32_t dim, bits;
 };
 
-// One block per cloud: unpack to 3D (z = 0 for 2D clouds; + 0 adds exactly,
-// so D is unchanged), record each point's cloud, reduce the cloud's box.
+// Empty per-cloud boxes for k_batch_unpack to grow (a cloud without points
+// keeps the box [0, 0]).
+__global__ __launch_bounds__(256) void k_batch_box_init(const CloudIn* __restrict__ cin, int32_t B,
+                                                        CloudBox* __restrict__ cbox) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= B) return;
+    const bool any = cin[c].n > 0;
+    CloudBox cb;
+    for (int k = 0; k < 3; ++k) {
+        cb.mn[k] = ord_enc(any ? INFINITY : 0.f);
+        cb.mx[k] = ord_enc(any ? -INFINITY : 0.f);
+    }
+    cb.bad = 0;
+    cb.pad = 0;
+    cbox[c] = cb;
+}
+
+// The cloud holding point g: the last cloud whose first point is at or
+// before g (an empty cloud shares its first point with the next cloud, so
+// the last of them is the one that holds g).
+__device__ __forceinline__ int cloud_at(const CloudIn* __restrict__ cin, int32_t B, int64_t g) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cin[mid].off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void box_flush(CloudBox* __restrict__ cb, const float* lo, const float* hi, bool bad) {
+    for (int k = 0; k < 3; ++k) {
+        atomicMin(&cb->mn[k], ord_enc(lo[k]));
+        atomicMax(&cb->mx[k], ord_enc(hi[k]));
+    }
+    if (bad) atomicOr(&cb->bad, 1u);
+}
+
+// Unpack to 3D (z = 0 for 2D clouds; + 0 adds exactly, so D is unchanged),
+// record each point's cloud and grow the cloud boxes (min / max ignore a
+// NaN; a non-finite coordinate marks the cloud bad).  One workgroup per
+// kUnpackPts consecutive points, so a large cloud spreads over many
+// workgroups: a workgroup inside one cloud reduces its box in LDS and merges
+// it with one set of atomics; one that spans clouds merges per thread at
+// every cloud change.
+constexpr int64_t kUnpackPts = 4096;
 __global__ __launch_bounds__(256) void k_batch_unpack(const float* __restrict__ pts, const CloudIn* __restrict__ cin,
-                                                      float* __restrict__ pts3, uint32_t* __restrict__ cloud_of,
-                                                      CloudBox* __restrict__ cbox) {
+                                                      int32_t B, int64_t n, float* __restrict__ pts3,
+                                                      uint32_t* __restrict__ cloud_of, CloudBox* __restrict__ cbox) {
     __shared__ float s_lo[4][3], s_hi[4][3];
     __shared__ uint32_t s_bad[4];
-    const int b = blockIdx.x;
-    const CloudIn ci = cin[b];
+    __shared__ int s_c[2];
+    const int64_t base = (int64_t)blockIdx.x * kUnpackPts;
+    const int64_t end = base + kUnpackPts < n ? base + kUnpackPts : n;
+    if (threadIdx.x == 0) {
+        s_c[0] = cloud_at(cin, B, base);
+        s_c[1] = cloud_at(cin, B, end - 1);
+    }
+    __syncthreads();
+    const bool one = s_c[0] == s_c[1];
+    int c = s_c[0];
+    CloudIn ci = cin[c];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    bool bad = false;
-    for (int64_t q = threadIdx.x; q < ci.n; q += blockDim.x) {
+    bool bad = false, any = false;
+    for (int64_t g = base + threadIdx.x; g < end; g += blockDim.x) {
+        if (!one) {
+            while (g >= ci.off + ci.n) {  // past this cloud (empty clouds are skipped)
+                if (any) box_flush(cbox + c, lo, hi, bad);
+                for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+                bad = any = false;
+                ci = cin[++c];
+            }
+        }
+        const int64_t q = g - ci.off;
         float x[3] = {0.f, 0.f, 0.f};
         for (int k = 0; k < ci.dim; ++k) x[k] = pts[ci.foff + q * ci.dim + k];
-        const int64_t g = ci.off + q;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             pts3[3 * g + k] = x[k];
@@ -1595,7 +1657,12 @@ __global__ __launch_bounds__(256) void k_batch_unpack(const float* __restrict__ 
             lo[k] = fminf(lo[k], x[k]);
             hi[k] = fmaxf(hi[k], x[k]);
         }
-        cloud_of[g] = (uint32_t)b;
+        cloud_of[g] = (uint32_t)c;
+        any = true;
+    }
+    if (!one) {
+        if (any) box_flush(cbox + c, lo, hi, bad);
+        return;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -1612,19 +1679,42 @@ __global__ __launch_bounds__(256) void k_batch_unpack(const float* __restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        CloudBox cb;
-        cb.bad = 0;
-        cb.pad = 0;
+        bool b = false;
         for (int v = 0; v < 4; ++v) {
-            cb.bad |= s_bad[v];
+            b |= s_bad[v] != 0;
             for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo[k], s_lo[v][k]); hi[k] = fmaxf(hi[k], s_hi[v][k]); }
         }
-        for (int k = 0; k < 3; ++k) {
-            cb.mn[k] = ord_enc(ci.n > 0 ? lo[k] : 0.f);
-            cb.mx[k] = ord_enc(ci.n > 0 ? hi[k] : 0.f);
-        }
-        cbox[b] = cb;
+        box_flush(cbox + c, lo, hi, b);
     }
+}
+
+static unsigned unpack_grid(int64_t n) { return (unsigned)((n + kUnpackPts - 1) / kUnpackPts); }
+
+// Per-cloud quantisation from the per-cloud boxes, on the device: the same
+// double operations as the host's morton_params, hence the same parameters.
+// `avail` = code bits below the cloud id.
+__global__ __launch_bounds__(256) void k_batch_mparams(const CloudBox* __restrict__ cbox,
+                                                       const CloudIn* __restrict__ cin, int32_t B, int avail,
+                                                       CloudMorton* __restrict__ cm) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= B) return;
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = ord_dec(cbox[c].mn[k]);
+        hi[k] = ord_dec(cbox[c].mx[k]);
+    }
+    const int dim = cin[c].dim;
+    const int bits = min(dim == 3 ? 21 : 32, avail / dim);
+    const MortonParams mp = morton_params(lo, hi, dim, bits);
+    CloudMorton m;
+    for (int k = 0; k < 3; ++k) {
+        m.lo[k] = mp.lo[k];
+        m.scale[k] = mp.scale[k];
+    }
+    m.qmax = mp.qmax;
+    m.dim = dim;
+    m.bits = bits;
+    cm[c] = m;
 }
 
 __global__ __launch_bounds__(256) void k_batch_morton(const float* __restrict__ pts3,
@@ -2981,7 +3071,8 @@ int batched_impl(emst_ctx* ctx, const float* pts, const int64_t* h_offsets, cons
     HIP_TRY(hipMemcpyAsync(d_cin, cin, sizeof(CloudIn) * B, hipMemcpyHostToDevice, st));
     // ---- unpack + per-cloud boxes, validation
     k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
-    k_batch_unpack<<<B, 256, 0, st>>>(pts, d_cin, pts3, cloud_of, d_cbox);
+    k_batch_box_init<<<grid_for(B), 256, 0, st>>>(d_cin, B, d_cbox);
+    k_batch_unpack<<<unpack_grid(n), 256, 0, st>>>(pts, d_cin, B, n, pts3, cloud_of, d_cbox);
     HIP_TRY(hipGetLastError());
     CloudBox* cbox = reinterpret_cast<CloudBox*>(h);  // reuses the staging area
     HIP_TRY(hipStreamSynchronize(st));
@@ -3181,43 +3272,303 @@ extern "C" int emst_build_mreach(emst_ctx* ctx, const float* d_points, int64_t n
 }
 
 // ---------------------------------------------------------------------------
-// Round-granular continuous batching: a solver holds up to max_slots
-// requests in a caller-provided device budget; every step advances every
-// running request by one phase (its tree, then one Boruvka round per step,
-// then its edge order) with one wait for all of them, so a request admitted
-// between two steps starts at the next one while the others keep going.
-// The requests of a step are spread over a few streams of the solver, so
-// the kernels of small requests, which fill a fraction of the GPU each,
-// run side by side.
+// Round-granular continuous batching.  A solver holds up to max_slots
+// requests inside a caller-provided device budget.  The requests admitted
+// between two steps start together as one cohort: a batch as
+// emst_build_batched builds it (one tree in which every request is its own
+// subtree, one round loop), run as a resumable sequence of phases -- boxes
+// and Morton codes, tree, boxes and the first round, one Boruvka round per
+// phase, edge order.  Each cohort has its own stream (default priority) and
+// event; a step starts a cohort, then moves every cohort whose phase has
+// completed on to its next one, and returns once at least one has moved.
+// Cohorts progress at their own pace, the kernels of all requests of a
+// cohort are launched once per phase, and at most kSolverCohorts run at
+// once, so that requests arriving meanwhile gather into the next cohort.
 
-constexpr int kSolverStreams = 4;
+#ifndef EMST_SOLVER_COHORTS
+#define EMST_SOLVER_COHORTS 8
+#endif
+constexpr int kSolverCohorts = EMST_SOLVER_COHORTS;
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The device arrays of a batch, carved from its workspace.
+struct BatchBufs {
+    Bufs<3> b;
+    float* pts3;
+    uint32_t* cloud_of;
+    uint32_t* cloud_sorted;
+    CloudIn* cin;
+    CloudBox* cbox;
+    CloudMorton* cm;
+    uint32_t* croot;
+};
+
+static BatchBufs batch_bufs(char* ws, int64_t n, int32_t B) {
+    const BatchLayout BL = make_batch_layout(n, B);
+    BatchBufs x;
+    x.b = carve<3>(ws, BL.base);
+    x.pts3 = reinterpret_cast<float*>(ws + BL.pts3);
+    x.cloud_of = reinterpret_cast<uint32_t*>(ws + BL.cloud_of);
+    x.cloud_sorted = reinterpret_cast<uint32_t*>(ws + BL.cloud_sorted);
+    x.cin = reinterpret_cast<CloudIn*>(ws + BL.cin);
+    x.cbox = reinterpret_cast<CloudBox*>(ws + BL.cbox);
+    x.cm = reinterpret_cast<CloudMorton*>(ws + BL.cm);
+    x.croot = reinterpret_cast<uint32_t*>(ws + BL.croot);
+    return x;
+}
+
+enum BPhase { kBCodes, kBTree, kBFit, kBRound, kBFinal, kBDone };
+
+// One batch as phases.  Every phase ends with a copy of the control block
+// into the job's pinned mirror (after the first also of the cloud boxes);
+// bjob_advance reads the mirror once the phase has completed.
+struct BJob {
+    int32_t B = 0;
+    int64_t n = 0;               // points of all clouds (each has two or more)
+    int64_t edges_total = 0;
+    const float* pts = nullptr;  // the clouds' float offsets (CloudIn::foff) count from here
+    char* ws = nullptr;          // emst_workspace_bytes_batched(n, B)
+    int32_t* edges = nullptr;
+    float* weights = nullptr;
+    float* d2 = nullptr;
+    char* h = nullptr;           // pinned host mirror (bjob_host_bytes(B))
+    int phase = kBCodes;
+    int round = 0;
+    int variant = 13;
+    int lds_depth = 8;
+    int height = 0;
+    uint32_t root = 0;
+    int codes_in1 = 0;
+    int full = 0;
+    int cloud_bits = 0;
+    int nshifts = 0;
+    int shifts[8] = {};
+    int64_t ncomp = 0;
+    emst_stats S;
+    Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(h); }
+    CloudIn* cin() const { return reinterpret_cast<CloudIn*>(h + a256(sizeof(Ctrl))); }
+    CloudBox* cbox() const {
+        return reinterpret_cast<CloudBox*>(reinterpret_cast<char*>(cin()) + a256(sizeof(CloudIn) * (size_t)B));
+    }
+};
+
+static size_t bjob_host_bytes(int32_t B) {
+    return a256(sizeof(Ctrl)) + a256(sizeof(CloudIn) * (size_t)B) + a256(sizeof(CloudBox) * (size_t)B);
+}
+
+static TraverseArgs<3> bjob_args(const BJob& j, const BatchBufs& x) {
+    TraverseArgs<3> ta = traverse_args<3>(x.b, j.n, j.root);
+    ta.cloud_of = x.cloud_sorted;
+    ta.cloud_root = x.croot;
+    ta.lds_depth = j.lds_depth;
+    return ta;
+}
+
+// Enqueue the job's current phase.
+static int bjob_enqueue(emst_ctx* ctx, BJob& j, hipStream_t st) {
+    BatchBufs x = batch_bufs(j.ws, j.n, j.B);
+    Bufs<3>& b = x.b;
+    const int64_t n = j.n;
+    switch (j.phase) {
+    case kBCodes: {  // per-cloud boxes and quantisation, codes with the cloud id on top
+        HIP_TRY(hipMemcpyAsync(x.cin, j.cin(), sizeof(CloudIn) * j.B, hipMemcpyHostToDevice, st));
+        k_init_ctrl<<<1, 64, 0, st>>>(b.ctrl);
+        k_batch_box_init<<<grid_for(j.B), 256, 0, st>>>(x.cin, j.B, x.cbox);
+        k_batch_unpack<<<unpack_grid(n), 256, 0, st>>>(j.pts, x.cin, j.B, n, x.pts3, x.cloud_of, x.cbox);
+        j.cloud_bits = j.B > 1 ? 64 - __builtin_clzll((unsigned long long)(j.B - 1)) : 0;
+        // a cloud that fails validation gets codes from its unusable box; the
+        // batch is then started again without it
+        k_batch_mparams<<<grid_for(j.B), 256, 0, st>>>(x.cbox, x.cin, j.B, 64 - j.cloud_bits, x.cm);
+        const int nb = (int)std::min<unsigned>(grid_for(n), kPartBlocks);
+        uint64_t* part = reinterpret_cast<uint64_t*>(b.bpart);
+        k_batch_morton<<<nb, 256, 0, st>>>(x.pts3, x.cloud_of, x.cm, n, 64 - j.cloud_bits, b.k0, b.v0, part);
+        k_or_and_final<<<1, 256, 0, st>>>(part, nb, b.ctrl);
+        HIP_TRY(hipMemcpyAsync(j.cbox(), x.cbox, sizeof(CloudBox) * j.B, hipMemcpyDeviceToHost, st));
+        break;
+    }
+    case kBTree: {  // sort, gather, hierarchy
+        HIP_TRY(radix_sort_pairs(st, b.k0, b.v0, b.k1, b.v1, b.hist, n, j.shifts, j.nshifts, &j.codes_in1));
+        const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
+        const uint32_t* perm = j.codes_in1 ? b.v1 : b.v0;
+        k_gather<3><<<grid_for(n), 256, 0, st>>>(x.pts3, perm, n, b.spts, b.orig, b.labels, b.exch);
+        k_fill_u32<<<grid_for(4 * n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(b.eud), 4 * n, kNone);
+        k_batch_sorted_cloud<<<grid_for(n), 256, 0, st>>>(x.cloud_of, perm, n, x.cloud_sorted);
+        if (int rc = build_hierarchy<3>(ctx, b, codes, n, st)) return rc;
+        break;
+    }
+    case kBFit: {  // boxes, every cloud's subtree root, the first round
+        const uint64_t* codes = j.codes_in1 ? b.k1 : b.k0;
+        if (int rc = fit_levels<3>(ctx, b, codes, n, (uint32_t)j.height, st)) return rc;
+        k_fill_u32<<<grid_for(j.B), 256, 0, st>>>(x.croot, j.B, kNone);
+        k_cloud_roots<<<grid_for(n - 1), 256, 0, st>>>(b.rlo, b.rhi, x.cloud_sorted, x.cin, n - 1, x.croot);
+        HIP_TRY(hipGetLastError());
+        TraverseArgs<3> ta = bjob_args(j, x);
+        if (int rc = enqueue_round<3>(ctx, b, ta, n, 0, j.height, j.variant, x.cloud_sorted, j.B, false, st))
+            return rc;
+        break;
+    }
+    case kBRound: {
+        TraverseArgs<3> ta = bjob_args(j, x);
+        if (int rc = enqueue_round<3>(ctx, b, ta, n, j.round, j.height, j.variant, x.cloud_sorted, j.B, false, st))
+            return rc;
+        break;
+    }
+    case kBFinal: {  // per-cloud canonical order (the full sort only after a long run of ties)
+        const uint32_t* order = nullptr;
+        if (int rc = sort_edges<3>(ctx, b, n, x.cloud_sorted, j.cloud_bits, j.full != 0, &order, st)) return rc;
+        k_batch_edge_write<<<grid_for(n), 256, 0, st>>>(b.eud, order, x.cloud_sorted, x.cin, n, j.edges, j.weights,
+                                                        j.d2);
+        break;
+    }
+    default:
+        return fail(ctx, EMST_EINTERNAL, "batch already finished");
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(j.ctrl(), b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    return EMST_OK;
+}
+
+// Once the phase has completed: read the mirror and pick the next phase.
+// After the first phase, clouds that fail validation are listed in *bad
+// (cloud, status) and the job stays where it is; the caller drops them and
+// starts the job again.
+static int bjob_advance(emst_ctx* ctx, BJob& j, std::vector<std::pair<int, int>>* bad) {
+    const Ctrl* h = j.ctrl();
+    switch (j.phase) {
+    case kBCodes: {
+        const CloudBox* cb = j.cbox();
+        bad->clear();
+        for (int32_t c = 0; c < j.B; ++c) {
+            float l[3], u[3];
+            for (int k = 0; k < 3; ++k) { l[k] = ord_dec(cb[c].mn[k]); u[k] = ord_dec(cb[c].mx[k]); }
+            if (cb[c].bad) bad->push_back({c, EMST_ENONFINITE});
+            else if (!extent_ok(l, u, 3)) bad->push_back({c, EMST_ERANGE});
+        }
+        if (!bad->empty()) return EMST_OK;
+        const uint64_t vary = h->key_or ^ h->key_and;
+        j.nshifts = 0;
+        for (int s = 0; s < 64; s += 8)
+            if ((vary >> s) & 0xFFull) j.shifts[j.nshifts++] = s;
+        j.phase = kBTree;
+        return EMST_OK;
+    }
+    case kBTree:
+        if (int rc = check_hierarchy(ctx, h, j.n)) return rc;
+        j.height = (int)h->height;
+        j.root = h->root;
+        j.S.tree_height = (int32_t)h->height;
+        j.ncomp = j.n;
+        j.round = 0;
+        j.phase = kBFit;
+        return EMST_OK;
+    case kBFit:
+    case kBRound: {
+        if (j.round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
+        j.S.components[j.round] = j.ncomp;
+        if (int rc = finish_round(ctx, h, j.round, j.B, j.ncomp, j.S)) return rc;
+        ++j.round;
+        if (j.ncomp <= j.B) {
+            if ((int64_t)h->edge_count != j.edges_total) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
+            j.S.rounds = j.round;
+            j.S.traversal_launches = j.round;
+            j.S.traversal_variant = j.variant;
+            j.phase = kBFinal;
+        } else {
+            j.phase = kBRound;
+        }
+        return EMST_OK;
+    }
+    case kBFinal:
+        if (h->long_ties && !j.full) j.full = 1;
+        else j.phase = kBDone;
+        return EMST_OK;
+    default:
+        return fail(ctx, EMST_EINTERNAL, "batch already finished");
+    }
+}
 
 struct SolverSlot {
     int state = 0;          // 0 free, 1 running, 2 done, < 0: failed with that status
     int64_t tag = 0;
-    size_t off = 0, bytes = 0;
+    size_t off = 0, bytes = 0;   // the points, until the cohort has unpacked them (bytes = 0 after)
+    size_t quota = 0;            // emst_solver_slot_bytes, held from admit to take
     int64_t n = 0;
     int dim = 3;
-    Job job;
+    int cohort = -1;        // -1: waiting for the next step
+    int64_t eoff = 0;       // first edge in the cohort's outputs
+    uint64_t order = 0;     // admission order
     std::string err;
+};
+
+struct Cohort {
+    bool live = false;      // phases still to run
+    bool held = false;      // owns its region (live: outputs and workspace; finished: the outputs
+                            // until every member's result is taken)
+    bool inflight = false;  // a phase is queued on `st`, `ev` follows it
+    bool fresh = false;     // not started: its first phase waits for the caller's stream
+    std::vector<int> slots; // member slots, in cloud order
+    size_t off = 0, bytes = 0;
+    int remaining = 0;      // members whose results were not taken yet
+    BJob job;
+    char* host = nullptr;   // pinned mirror of the job
+    size_t host_bytes = 0;
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
 };
 
 struct emst_solver {
     emst_ctx* ctx = nullptr;
     char* base = nullptr;
     size_t budget = 0;
+    size_t reserved = 0;    // sum of the shares of the admitted, not yet taken requests
+    uint64_t next_order = 0;
     std::vector<SolverSlot> slots;
-    Ctrl* h = nullptr;      // pinned mirrors, one per slot
-    hipStream_t lane[kSolverStreams] = {};
-    hipEvent_t fork = nullptr;  // orders the lanes after the caller's stream
+    std::vector<Cohort> cohorts;
+    hipEvent_t fork = nullptr;  // orders a cohort's first phase after the caller's stream
 };
 
-static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
-
+// Budget a request holds from admit to take: its points while they wait,
+// and the workspace and outputs of a cohort of that one request, so the
+// requests admitted together always fit one cohort.
 extern "C" size_t emst_solver_slot_bytes(int64_t n, int dim) {
     if (n < 0 || n > 0x7FFFFFFFll || (dim != 2 && dim != 3)) return 0;
     const size_t m = (size_t)(n > 1 ? n - 1 : 0);
-    return a256((size_t)n * dim * 4) + emst_workspace_bytes(n > 1 ? n : 2, dim) + a256(m * 8) + 2 * a256(m * 4);
+    return a256((size_t)n * dim * 4) + a256(emst_workspace_bytes_batched(n > 1 ? n : 2, 1)) + a256(m * 8) +
+           2 * a256(m * 4);
+}
+
+static size_t output_bytes(int64_t edges) { return a256((size_t)edges * 8) + 2 * a256((size_t)edges * 4); }
+
+static size_t cohort_bytes(int64_t points, int32_t clouds, int64_t edges) {
+    return output_bytes(edges) + a256(emst_workspace_bytes_batched(points, clouds));
+}
+
+// A free range of `need` bytes in the budget: the lowest one (cohorts) or
+// the highest one (the points of waiting requests), so that the two kinds
+// of region grow from opposite ends.
+static bool sv_place(const emst_solver* sv, size_t need, bool high, size_t* at) {
+    std::vector<std::pair<size_t, size_t>> used;
+    for (const SolverSlot& q : sv->slots)
+        if (q.state != 0 && q.bytes) used.push_back({q.off, q.off + q.bytes});
+    for (const Cohort& c : sv->cohorts)
+        if (c.held) used.push_back({c.off, c.off + c.bytes});
+    std::sort(used.begin(), used.end());
+    bool found = false;
+    size_t prev = 0;  // end of the used range before the current gap
+    for (size_t k = 0; k <= used.size(); ++k) {
+        const size_t gap_end = k < used.size() ? used[k].first : sv->budget;
+        if (gap_end >= prev && gap_end - prev >= need) {
+            if (!high) {
+                *at = prev;
+                return true;
+            }
+            *at = (gap_end - need) & ~(size_t)255;
+            found = *at >= prev;
+        }
+        if (k < used.size()) prev = std::max(prev, used[k].second);
+    }
+    return found;
 }
 
 extern "C" void emst_solver_destroy(emst_solver* sv);
@@ -3231,13 +3582,11 @@ extern "C" int emst_solver_create(emst_ctx* ctx, void* d_budget, size_t budget_b
     if (!sv) return EMST_ENOMEM;
     sv->ctx = ctx;
     sv->base = (char*)d_budget;
-    sv->budget = budget_bytes;
+    sv->budget = budget_bytes & ~(size_t)255;
     sv->slots.resize(max_slots);
-    bool ok = hipSetDevice(ctx->device) == hipSuccess &&
-              hipHostMalloc((void**)&sv->h, sizeof(Ctrl) * (size_t)max_slots, hipHostMallocDefault) == hipSuccess &&
-              hipEventCreateWithFlags(&sv->fork, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; ok && k < kSolverStreams; ++k)
-        ok = hipStreamCreateWithFlags(&sv->lane[k], hipStreamNonBlocking) == hipSuccess;
+    sv->cohorts.resize(max_slots);
+    const bool ok = hipSetDevice(ctx->device) == hipSuccess &&
+                    hipEventCreateWithFlags(&sv->fork, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         emst_solver_destroy(sv);
         return fail(ctx, EMST_EHIP, "solver set-up failed");
@@ -3248,13 +3597,15 @@ extern "C" int emst_solver_create(emst_ctx* ctx, void* d_budget, size_t budget_b
 
 extern "C" void emst_solver_destroy(emst_solver* sv) {
     if (!sv) return;
-    for (hipStream_t& l : sv->lane)
-        if (l) {
-            (void)hipStreamSynchronize(l);
-            (void)hipStreamDestroy(l);
+    for (Cohort& c : sv->cohorts) {
+        if (c.st) {
+            (void)hipStreamSynchronize(c.st);
+            (void)hipStreamDestroy(c.st);
         }
+        if (c.ev) (void)hipEventDestroy(c.ev);
+        if (c.host) (void)hipHostFree(c.host);
+    }
     if (sv->fork) (void)hipEventDestroy(sv->fork);
-    if (sv->h) (void)hipHostFree(sv->h);
     delete sv;
 }
 
@@ -3267,49 +3618,212 @@ extern "C" int emst_solver_admit(emst_solver* sv, const float* d_points, int64_t
     if (n < 0 || n > 0x7FFFFFFFll) return fail(ctx, EMST_EINVAL, "n out of range");
     if (dim != 2 && dim != 3) return fail(ctx, EMST_EINVAL, "dim must be 2 or 3");
     if (n > 0 && !d_points) return fail(ctx, EMST_EINVAL, "null pointer");
-    const size_t need = emst_solver_slot_bytes(n, dim);
-    if (need > sv->budget) return fail(ctx, EMST_ENOMEM, "request larger than the whole budget");
+    const size_t quota = emst_solver_slot_bytes(n, dim);
+    if (quota > sv->budget) return fail(ctx, EMST_ENOMEM, "request larger than the whole budget");
     int free_slot = -1;
     for (int s = 0; s < (int)sv->slots.size() && free_slot < 0; ++s)
         if (sv->slots[s].state == 0) free_slot = s;
     if (free_slot < 0) return fail(ctx, EMST_EBUSY, "no free slot");
-    // first fit in the budget, between the regions held by other slots
-    std::vector<std::pair<size_t, size_t>> used;
-    for (const SolverSlot& q : sv->slots)
-        if (q.state != 0) used.push_back({q.off, q.off + q.bytes});
-    std::sort(used.begin(), used.end());
+    if (sv->reserved + quota > sv->budget) return fail(ctx, EMST_EBUSY, "budget full");
+    const size_t pts_bytes = n >= 2 ? a256((size_t)n * dim * 4) : 0;
     size_t at = 0;
-    bool found = false;
-    for (const auto& u : used) {
-        if (u.first >= at + need) {
-            found = true;
-            break;
-        }
-        at = std::max(at, u.second);
-    }
-    if (!found && at + need > sv->budget) return fail(ctx, EMST_EBUSY, "budget full");
+    if (pts_bytes && !sv_place(sv, pts_bytes, true, &at)) return fail(ctx, EMST_EBUSY, "budget full");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (pts_bytes)
+        HIP_TRY(hipMemcpyAsync(sv->base + at, d_points, (size_t)n * dim * 4, hipMemcpyDeviceToDevice, st));
     SolverSlot& q = sv->slots[free_slot];
     q.tag = tag;
     q.off = at;
-    q.bytes = need;
+    q.bytes = pts_bytes;
+    q.quota = quota;
     q.n = n;
     q.dim = dim;
+    q.cohort = -1;
+    q.eoff = 0;
+    q.order = sv->next_order++;
     q.err.clear();
-    char* mem = sv->base + at;
-    const size_t m = (size_t)(n > 1 ? n - 1 : 0);
-    float* pts = reinterpret_cast<float*>(mem);
-    char* ws = mem + a256((size_t)n * dim * 4);
-    char* outs = ws + emst_workspace_bytes(n > 1 ? n : 2, dim);
-    int32_t* edges = reinterpret_cast<int32_t*>(outs);
-    float* weights = reinterpret_cast<float*>(outs + a256(m * 8));
-    float* d2 = reinterpret_cast<float*>(outs + a256(m * 8) + a256(m * 4));
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (n > 0) HIP_TRY(hipMemcpyAsync(pts, d_points, (size_t)n * dim * 4, hipMemcpyDeviceToDevice, st));
-    q.job = make_job(ctx, pts, n, dim, ws, edges, weights, d2, 0, nullptr, false, sv->h + free_slot, false);
     q.state = n < 2 ? 2 : 1;  // 0 or 1 point: nothing to do
+    sv->reserved += quota;
     *slot = free_slot;
     return EMST_OK;
+}
+
+static void release_points(SolverSlot& q) { q.bytes = 0; }
+
+// Fill the cloud table of cohort c from its member slots and restart its job.
+static void cohort_tables(emst_solver* sv, Cohort& co) {
+    BJob& j = co.job;
+    j.B = (int32_t)co.slots.size();
+    j.n = 0;
+    j.edges_total = 0;
+    CloudIn* cin = j.cin();
+    for (int32_t c = 0; c < j.B; ++c) {
+        SolverSlot& q = sv->slots[co.slots[c]];
+        cin[c].off = j.n;
+        cin[c].n = q.n;
+        cin[c].foff = (int64_t)(q.off / 4);  // floats from the budget's base
+        cin[c].eoff = j.edges_total;
+        cin[c].dim = q.dim;
+        cin[c].pad = 0;
+        q.eoff = j.edges_total;
+        j.n += q.n;
+        j.edges_total += q.n - 1;
+    }
+    // the outputs first: a finished cohort keeps only them
+    const size_t E = (size_t)j.edges_total;
+    char* region = sv->base + co.off;
+    j.edges = reinterpret_cast<int32_t*>(region);
+    j.weights = reinterpret_cast<float*>(region + a256(E * 8));
+    j.d2 = reinterpret_cast<float*>(region + a256(E * 8) + a256(E * 4));
+    j.ws = region + output_bytes(j.edges_total);
+    j.pts = reinterpret_cast<const float*>(sv->base);
+    j.phase = kBCodes;
+    j.round = 0;
+    j.full = 0;
+    memset(&j.S, 0, sizeof(j.S));
+}
+
+// Start a cohort from the requests waiting since the last step: as many, in
+// admission order, as fit one free range of the budget together, unless
+// kSolverCohorts cohorts run already.
+static int form_cohort(emst_solver* sv, int* done) {
+    emst_ctx* ctx = sv->ctx;
+    int live = 0;
+    for (const Cohort& c : sv->cohorts) live += c.live;
+    if (live >= kSolverCohorts) return EMST_OK;
+    std::vector<int> wait;
+    for (int s = 0; s < (int)sv->slots.size(); ++s)
+        if (sv->slots[s].state == 1 && sv->slots[s].cohort < 0) wait.push_back(s);
+    if (wait.empty()) return EMST_OK;
+    std::sort(wait.begin(), wait.end(), [&](int a, int b) { return sv->slots[a].order < sv->slots[b].order; });
+    int k = 0;
+    size_t at = 0;
+    int64_t pts = 0, edges = 0;
+    for (int s : wait) {
+        const int64_t n = sv->slots[s].n;
+        size_t where = 0;
+        if (!sv_place(sv, cohort_bytes(pts + n, k + 1, edges + n - 1), false, &where)) break;
+        at = where;
+        pts += n;
+        edges += n - 1;
+        ++k;
+    }
+    if (k == 0) {
+        bool any_held = false;
+        for (const Cohort& c : sv->cohorts) any_held |= c.held;
+        if (!any_held) {
+            // no cohort holds memory that a step or a take could free: the
+            // first waiting request fails instead of waiting for ever
+            SolverSlot& q = sv->slots[wait[0]];
+            q.state = EMST_ENOMEM;
+            q.err = "the budget has no free range for this request";
+            release_points(q);
+            ++*done;
+        }
+        return EMST_OK;
+    }
+    int ci = -1;
+    for (int c = 0; c < (int)sv->cohorts.size() && ci < 0; ++c)
+        if (!sv->cohorts[c].held) ci = c;
+    if (ci < 0) return EMST_OK;  // (cannot happen: a held cohort has a member slot)
+    Cohort& co = sv->cohorts[ci];
+    if (!co.st && hipStreamCreateWithFlags(&co.st, hipStreamNonBlocking) != hipSuccess)
+        return fail(ctx, EMST_EHIP, "hipStreamCreate failed");
+    if (!co.ev && hipEventCreateWithFlags(&co.ev, hipEventDisableTiming) != hipSuccess)
+        return fail(ctx, EMST_EHIP, "hipEventCreate failed");
+    const size_t hb = bjob_host_bytes(k);
+    if (co.host_bytes < hb) {
+        if (co.host) (void)hipHostFree(co.host);
+        co.host = nullptr;
+        co.host_bytes = 0;
+        if (hipHostMalloc((void**)&co.host, hb, hipHostMallocDefault) != hipSuccess)
+            return fail(ctx, EMST_EHIP, "hipHostMalloc failed");
+        co.host_bytes = hb;
+    }
+    co.slots.assign(wait.begin(), wait.begin() + k);
+    co.off = at;
+    co.bytes = cohort_bytes(pts, k, edges);
+    co.held = true;
+    co.live = true;
+    co.remaining = k;
+    co.inflight = false;
+    co.fresh = true;
+    co.job = BJob();
+    co.job.h = co.host;
+    int t = 13, depth = 8;
+    pick_shape(ctx, 1, 3, pts, &t, &depth);
+    co.job.variant = (t == 0 || t == 5 || t == 8 || t == 13) ? t : 7;
+    co.job.lds_depth = depth;
+    for (int s : co.slots) sv->slots[s].cohort = ci;
+    cohort_tables(sv, co);
+    return EMST_OK;
+}
+
+// A cohort's members fail together with `rc`.
+static void cohort_fail(emst_solver* sv, Cohort& co, int rc, const std::string& msg, int* done) {
+    for (int s : co.slots) {
+        SolverSlot& q = sv->slots[s];
+        q.state = rc;
+        q.err = msg;
+        q.cohort = -1;
+        release_points(q);
+        ++*done;
+    }
+    co.slots.clear();
+    co.live = false;
+    co.held = false;
+    co.remaining = 0;
+}
+
+// The host side of a completed phase of cohort c.
+static void cohort_advance(emst_solver* sv, Cohort& co, int* done) {
+    emst_ctx* ctx = sv->ctx;
+    std::vector<std::pair<int, int>> bad;
+    const int phase = co.job.phase;
+    const int rc = bjob_advance(ctx, co.job, &bad);
+    if (rc) {
+        cohort_fail(sv, co, rc, ctx->err, done);
+        return;
+    }
+    if (!bad.empty()) {
+        // invalid requests fail alone; the others start again without them
+        std::vector<int> keep;
+        size_t b = 0;
+        for (int32_t k = 0; k < (int32_t)co.slots.size(); ++k) {
+            SolverSlot& q = sv->slots[co.slots[k]];
+            if (b < bad.size() && bad[b].first == k) {
+                q.state = bad[b].second;
+                q.err = bad[b].second == EMST_ENONFINITE ? "non-finite coordinate"
+                                                         : "squared extent of the cloud overflows float32";
+                q.cohort = -1;
+                release_points(q);
+                ++*done;
+                ++b;
+            } else {
+                keep.push_back(co.slots[k]);
+            }
+        }
+        co.slots = keep;
+        co.remaining = (int)keep.size();
+        if (keep.empty()) {
+            co.live = false;
+            co.held = false;
+        } else {
+            cohort_tables(sv, co);  // the region, sized for more, still fits
+        }
+        return;
+    }
+    if (phase == kBCodes)  // the points are in the workspace now
+        for (int s : co.slots) release_points(sv->slots[s]);
+    if (co.job.phase == kBDone) {
+        co.live = false;
+        co.bytes = output_bytes(co.job.edges_total);  // the workspace is free again
+        for (int s : co.slots) {
+            sv->slots[s].state = 2;
+            ++*done;
+        }
+    }
 }
 
 extern "C" int emst_solver_step(emst_solver* sv, void* stream, int32_t* n_finished) {
@@ -3318,43 +3832,44 @@ extern "C" int emst_solver_step(emst_solver* sv, void* stream, int32_t* n_finish
     ctx->err.clear();
     if (n_finished) *n_finished = 0;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    // the lanes start after what the caller's stream holds (admitted points)
-    HIP_TRY(hipEventRecord(sv->fork, st));
-    for (hipStream_t l : sv->lane) HIP_TRY(hipStreamWaitEvent(l, sv->fork, 0));
-    std::vector<int> go;
-    int next_lane = 0;
-    for (int s = 0; s < (int)sv->slots.size(); ++s) {
-        SolverSlot& q = sv->slots[s];
-        if (q.state != 1) continue;
-        if (q.job.prof) q.job.prof = false;
-        hipStream_t l = sv->lane[next_lane++ % kSolverStreams];
-        const int rc = q.dim == 3 ? job_enqueue<3>(ctx, q.job, l) : job_enqueue<2>(ctx, q.job, l);
-        if (rc) {
-            q.state = rc;
-            q.err = ctx->err;
-        } else {
-            go.push_back(s);
-        }
-    }
-    hipError_t w = hipSuccess;
-    for (hipStream_t l : sv->lane) {
-        const hipError_t e = hipStreamSynchronize(l);
-        if (w == hipSuccess) w = e;
-    }
-    if (w != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(w));
     int done = 0;
-    for (int s : go) {
-        SolverSlot& q = sv->slots[s];
-        const int rc = q.dim == 3 ? job_advance<3>(ctx, q.job) : job_advance<2>(ctx, q.job);
-        if (rc) {
-            q.state = rc;
-            q.err = ctx->err;
-            ++done;
-        } else if (q.job.phase == kPhDone) {
-            q.state = 2;
-            ++done;
+    if (int rc = form_cohort(sv, &done)) return rc;
+    bool fresh = false;
+    for (const Cohort& c : sv->cohorts) fresh |= c.live && c.fresh;
+    // a new cohort starts after what the caller's stream holds (admitted points)
+    if (fresh) HIP_TRY(hipEventRecord(sv->fork, reinterpret_cast<hipStream_t>(stream)));
+    for (;;) {
+        bool moved = false, busy = false;
+        for (Cohort& co : sv->cohorts) {
+            if (!co.live) continue;
+            if (co.inflight) {
+                const hipError_t q = hipEventQuery(co.ev);
+                if (q == hipErrorNotReady) {
+                    busy = true;
+                    continue;
+                }
+                if (q != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(q));
+                co.inflight = false;
+                moved = true;
+                cohort_advance(sv, co, &done);
+                if (!co.live) continue;
+            }
+            if (co.fresh) {
+                HIP_TRY(hipStreamWaitEvent(co.st, sv->fork, 0));
+                co.fresh = false;
+            }
+            if (int rc = bjob_enqueue(ctx, co.job, co.st)) {
+                (void)hipStreamSynchronize(co.st);
+                cohort_fail(sv, co, rc, ctx->err, &done);
+                moved = true;
+                continue;
+            }
+            HIP_TRY(hipEventRecord(co.ev, co.st));
+            co.inflight = true;
+            busy = true;
         }
+        if (moved || !busy) break;
+        std::this_thread::yield();
     }
     if (n_finished) *n_finished = done;
     return EMST_OK;
@@ -3377,6 +3892,8 @@ extern "C" int emst_solver_take(emst_solver* sv, int32_t slot, int32_t* d_edges,
     if (q.state < 0) {
         const int rc = q.state;
         ctx->err = q.err;
+        sv->reserved -= q.quota;
+        release_points(q);
         q.state = 0;
         return rc;
     }
@@ -3384,12 +3901,20 @@ extern "C" int emst_solver_take(emst_solver* sv, int32_t slot, int32_t* d_edges,
     if (m) {
         if (!d_edges || !d_weights) return fail(ctx, EMST_EINVAL, "null pointer");
         if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+        const BJob& j = sv->cohorts[q.cohort].job;
         hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-        HIP_TRY(hipMemcpyAsync(d_edges, q.job.edges, m * 8, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(d_weights, q.job.weights, m * 4, hipMemcpyDeviceToDevice, st));
-        if (d_d2) HIP_TRY(hipMemcpyAsync(d_d2, q.job.d2, m * 4, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_edges, j.edges + 2 * q.eoff, m * 8, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_weights, j.weights + q.eoff, m * 4, hipMemcpyDeviceToDevice, st));
+        if (d_d2) HIP_TRY(hipMemcpyAsync(d_d2, j.d2 + q.eoff, m * 4, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
+    if (q.cohort >= 0) {
+        Cohort& co = sv->cohorts[q.cohort];
+        if (--co.remaining == 0) co.held = false;
+        q.cohort = -1;
+    }
+    sv->reserved -= q.quota;
+    release_points(q);
     q.state = 0;
     return EMST_OK;
 }

@@ -14,13 +14,14 @@ Latency of a request = completion on the host - arrival.  The server
 reports p50/p99 latency and Mpoints/s over the run.
 
 ``SolverServer`` is the round-granular form on the native solver: requests
-join between any two steps (one Boruvka round each) instead of between
-batches.
+join between any two steps (one Boruvka round of every running cohort)
+instead of between batches.
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
+import queue
 import threading
 import time
 from typing import Callable, List, Optional
@@ -206,12 +207,17 @@ class FifoServer:
 
 class SolverServer:
     """Round-granular continuous batching on the native solver
-    (``emst_solver_*``): one driver thread admits every queued request that
-    finds a slot and budget, advances all running requests by one phase per
-    step (tree, one Boruvka round, edge order) and hands finished results
-    back.  A request arriving while others run joins at the next step."""
+    (``emst_solver_*``): one driver thread admits every uploaded request
+    that finds a slot and budget, steps the solver (the requests admitted
+    since the last step start as one cohort, every cohort whose phase
+    completed moves on by one phase: tree, one Boruvka round, edge order)
+    and takes finished results.  A request arriving while others run joins
+    the next cohort.  `copy_workers` threads, each with its own stream, copy
+    the points of arriving requests to the device and finished results back,
+    so that the driver thread only drives the solver."""
 
-    def __init__(self, budget_bytes: int = 8 << 30, max_slots: int = 64, device: int = 0):
+    def __init__(self, budget_bytes: int = 8 << 30, max_slots: int = 64, device: int = 0,
+                 copy_workers: int = 4):
         import torch
         from . import Context, Solver
         self.device = device
@@ -219,10 +225,14 @@ class SolverServer:
         self._solver = Solver(self._ctx, budget_bytes, max_slots)
         self._stream = torch.cuda.Stream(device=device)
         self.budget = budget_bytes
-        self._queue: collections.deque = collections.deque()
+        self.copy_workers = max(1, copy_workers)
+        self._ready: collections.deque = collections.deque()   # (request, device points)
+        self._uploading = 0
+        self._jobs: "queue.Queue" = queue.Queue()
         self._cv = threading.Condition()
         self._closed = False
         self._thread: Optional[threading.Thread] = None
+        self._copiers: List[threading.Thread] = []
         self._steps = 0
         self.t0 = time.perf_counter()
 
@@ -237,10 +247,14 @@ class SolverServer:
             return
         with self._cv:
             req.arrival = self.now() if req.arrival == 0.0 else req.arrival
-            self._queue.append(req)
-            self._cv.notify()
+            self._uploading += 1
+        self._jobs.put(("up", req))
 
     def start(self) -> None:
+        for _ in range(self.copy_workers):
+            t = threading.Thread(target=self._copy, daemon=True)
+            t.start()
+            self._copiers.append(t)
         self._thread = threading.Thread(target=self._run, daemon=True)
         self._thread.start()
 
@@ -250,46 +264,76 @@ class SolverServer:
             self._cv.notify_all()
         if self._thread:
             self._thread.join()
+        for _ in self._copiers:
+            self._jobs.put(None)
+        for t in self._copiers:
+            t.join()
         self._solver.close()
+
+    def _copy(self) -> None:
+        import torch
+        stream = torch.cuda.Stream(device=self.device)
+        while True:
+            job = self._jobs.get()
+            if job is None:
+                return
+            with torch.cuda.stream(stream):
+                if job[0] == "up":
+                    r = job[1]
+                    try:
+                        pts = torch.from_numpy(r.points).to(f"cuda:{self.device}")
+                        stream.synchronize()
+                    except Exception as exc:
+                        r.error, r.done = str(exc), self.now()
+                        pts = None
+                    with self._cv:
+                        if pts is not None:
+                            self._ready.append((r, pts))
+                        self._uploading -= 1
+                        self._cv.notify_all()
+                else:
+                    _, r, e, w, d = job
+                    r.edges, r.weights, r.d2 = e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()
+                    r.done = self.now()
 
     def _run(self) -> None:
         import torch
-        running = {}   # slot -> (request, device copy of its points until the next step)
+        running = {}   # slot -> request
         while True:
             with self._cv:
-                while not self._queue and not running and not self._closed:
+                while not self._ready and not running and not (self._closed and not self._uploading):
                     self._cv.wait()
-                if not self._queue and not running and self._closed:
+                if not self._ready and not running and self._closed and not self._uploading:
                     return
-                waiting = list(self._queue)
+                ready = list(self._ready)
             with torch.cuda.stream(self._stream):
-                for r in waiting:
-                    pts = torch.from_numpy(r.points).to(f"cuda:{self.device}")
+                for r, pts in ready:
                     slot = self._solver.admit(pts, tag=r.rid, stream=self._stream)
                     if slot is None:
                         break
+                    pts.record_stream(self._stream)   # the solver copies it on this stream
                     with self._cv:
-                        self._queue.popleft()
+                        self._ready.popleft()
                     r.start = self.now()
                     r.batch = self._steps
-                    running[slot] = (r, pts)
+                    running[slot] = r
                 if not running:
                     continue
-                self._solver.step(stream=self._stream)
+                fin = self._solver.step(stream=self._stream)
                 self._steps += 1
+                if fin == 0 and not any(len(r.points) < 2 for r in running.values()):
+                    continue
                 for slot in list(running):
                     state, _ = self._solver.poll(slot)
                     if state == 1:
-                        running[slot] = (running[slot][0], None)
                         continue
-                    r = running.pop(slot)[0]
+                    r = running.pop(slot)
                     try:
                         e, w, d = self._solver.take(slot, stream=self._stream)
-                        self._stream.synchronize()
-                        r.edges, r.weights, r.d2 = e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()
                     except Exception as exc:  # a failed request fails alone
-                        r.error = str(exc)
-                    r.done = self.now()
+                        r.error, r.done = str(exc), self.now()
+                        continue
+                    self._jobs.put(("down", r, e, w, d))
 
 
 def replay(server, requests: List[Request], arrivals: List[float],
