@@ -239,22 +239,42 @@ int emst_solver_admit(emst_solver *solver, const float *d_points, int64_t n, int
                       void *stream, int32_t *slot);
 
 /* Start a cohort of the requests admitted since the last step (as many, in
- * admission order, as fit one contiguous free range; the others wait for
- * the next step), then one phase for every live cohort; returns when all
- * of them are done.  Cohorts run on a few streams of the solver (default
- * priority), after the work already queued on `stream`.  A request that
- * finds no range while no cohort holds memory fails with EMST_ENOMEM.
- * *n_finished (nullable) = requests that finished or failed in this step. */
+ * admission order, as fit one contiguous free range, unless 8 cohorts run
+ * already; the others wait for a later step), then move every cohort whose
+ * queued phase has completed on to its next phase; returns once at least
+ * one cohort has moved (at once if none runs).  Each cohort runs on its own
+ * stream of the solver (default priority), after the work queued on
+ * `stream` before its first step.  A request that finds no range while no
+ * cohort holds memory fails with EMST_ENOMEM.  *n_finished (nullable) =
+ * requests that finished or failed in this step. */
 int emst_solver_step(emst_solver *solver, void *stream, int32_t *n_finished);
 
 /* *state: 0 free, 1 running, 2 finished, < 0 failed with that status;
  * *tag (nullable) the admit tag. */
 int emst_solver_poll(const emst_solver *solver, int32_t slot, int32_t *state, int64_t *tag);
 
-/* Copy a finished request's n-1 edges, weights and (nullable) d2 out, as
- * emst_build writes them, and free its slot.  A failed request returns its
- * status (message in emst_last_error) and frees its slot; a running one
- * gives EMST_EBUSY. */
+/* The slots whose request has finished or failed and is not taken yet: up
+ * to `cap` of them into slots[], their number in *count.  They come ordered
+ * by cohort and by position in the cohort's outputs, the order in which
+ * emst_solver_take_many copies them in the fewest pieces. */
+int emst_solver_ready(const emst_solver *solver, int32_t *slots, int32_t cap, int32_t *count);
+
+/* emst_solver_take for `count` finished requests at once (every slot must
+ * hold a finished result, state 2; else EMST_EINVAL and nothing is taken).
+ * Their results go one after another into d_edges [total][2], d_weights
+ * [total] and d_d2 [total] (nullable): request i owns rows
+ * h_offsets[i] .. h_offsets[i+1]-1 (h_offsets: count + 1 entries, host).
+ * Results that lie back to back in one cohort's outputs are copied in one
+ * piece; copies are queued on `stream`, and the slots are free. */
+int emst_solver_take_many(emst_solver *solver, const int32_t *slots, int32_t count, int32_t *d_edges,
+                          float *d_weights, float *d_d2, int64_t *h_offsets, void *stream);
+
+/* Queue on `stream` the copies of a finished request's n-1 edges, weights
+ * and (nullable) d2, as emst_build writes them, and free its slot (the
+ * outputs are complete once `stream` reaches that point; the solver reuses
+ * the memory they come from only after the copies).  A failed request
+ * returns its status (message in emst_last_error) and frees its slot; a
+ * running one gives EMST_EBUSY. */
 int emst_solver_take(emst_solver *solver, int32_t slot, int32_t *d_edges, float *d_weights, float *d_d2,
                      void *stream);
 

@@ -13,6 +13,7 @@ every call raises -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -35,7 +36,8 @@ EXPORTS = [
     "emst_workspace_bytes_batched", "emst_build_batched", "emst_test_tree_boxes",
     "emst_core_distances", "emst_build_mreach", "emst_set_autotune", "emst_get_autotune",
     "emst_solver_slot_bytes", "emst_solver_create", "emst_solver_destroy", "emst_solver_admit",
-    "emst_solver_step", "emst_solver_poll", "emst_solver_take",
+    "emst_solver_step", "emst_solver_poll", "emst_solver_ready", "emst_solver_take",
+    "emst_solver_take_many",
     "emst_test_round", "emst_test_distances", "emst_test_weights",
     "emst_set_graphs", "emst_set_lds_depth", "emst_build_noalloc",
 ]
@@ -128,6 +130,10 @@ def lib():
         L.emst_solver_step.restype = i32
         L.emst_solver_poll.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.emst_solver_poll.restype = i32
+        L.emst_solver_ready.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+        L.emst_solver_ready.restype = i32
+        L.emst_solver_take_many.argtypes = [vp, ctypes.POINTER(i32), i32, vp, vp, vp, ctypes.POINTER(i64), vp]
+        L.emst_solver_take_many.restype = i32
         L.emst_solver_take.argtypes = [vp, i32, vp, vp, vp, vp]
         L.emst_solver_take.restype = i32
         L.emst_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -502,8 +508,11 @@ def build(points, **kw):
 
 class Solver:
     """Round-granular continuous batching on one context (emst_solver_*):
-    ``admit`` requests at any time, ``step`` advances every running one by
-    one phase, ``take`` returns a finished result exactly as ``build``."""
+    ``admit`` requests at any time; ``step`` starts the requests admitted
+    since the last step as one cohort and moves every cohort whose phase
+    has completed on by one phase; ``ready`` lists the finished slots;
+    ``take`` returns a finished result exactly as ``build`` (written on
+    ``stream``, by default the current stream)."""
 
     def __init__(self, ctx: "Context", budget_bytes: int, max_slots: int = 64):
         import torch
@@ -556,13 +565,45 @@ class Solver:
         self.ctx._check(lib().emst_solver_poll(self._h, int(slot), ctypes.byref(state), ctypes.byref(tag)))
         return state.value, tag.value
 
+    def ready(self):
+        """Slots whose request finished or failed and is not taken yet."""
+        cap = max(len(self._pending), 1)
+        buf = (ctypes.c_int32 * cap)()
+        count = ctypes.c_int32(0)
+        self.ctx._check(lib().emst_solver_ready(self._h, buf, cap, ctypes.byref(count)))
+        return list(buf[:count.value])
+
+    def take_many(self, slots, want_d2: bool = True, stream=None):
+        """Finished results of `slots` (all state 2; ``ready`` order copies
+        in the fewest pieces), concatenated: edges [M, 2], weights [M], d2
+        [M] or None, and offsets (k + 1 ints: request i owns rows
+        offsets[i]:offsets[i+1])."""
+        import torch
+        slots = [int(s) for s in slots]
+        total = sum(max(self._pending[s][0] - 1, 0) for s in slots)
+        device = f"cuda:{self.ctx.device}"
+        with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+            edges = torch.empty((total, 2), dtype=torch.int32, device=device)
+            weights = torch.empty(total, dtype=torch.float32, device=device)
+            d2 = torch.empty(total, dtype=torch.float32, device=device) if want_d2 else None
+        arr = (ctypes.c_int32 * max(len(slots), 1))(*slots)
+        offs = (ctypes.c_int64 * (len(slots) + 1))()
+        self.ctx._check(lib().emst_solver_take_many(self._h, arr, len(slots), ctypes.c_void_p(edges.data_ptr()),
+                                                    ctypes.c_void_p(weights.data_ptr()),
+                                                    ctypes.c_void_p(d2.data_ptr() if d2 is not None else 0),
+                                                    offs, _stream_handle(stream)))
+        for s in slots:
+            self._pending.pop(s)
+        return edges, weights, d2, list(offs)
+
     def take(self, slot: int, want_d2: bool = True, stream=None):
         import torch
         n, device = self._pending.pop(slot)
         m = max(n - 1, 0)
-        edges = torch.empty((m, 2), dtype=torch.int32, device=device)
-        weights = torch.empty(m, dtype=torch.float32, device=device)
-        d2 = torch.empty(m, dtype=torch.float32, device=device) if want_d2 else None
+        with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+            edges = torch.empty((m, 2), dtype=torch.int32, device=device)
+            weights = torch.empty(m, dtype=torch.float32, device=device)
+            d2 = torch.empty(m, dtype=torch.float32, device=device) if want_d2 else None
         self.ctx._check(lib().emst_solver_take(self._h, int(slot), ctypes.c_void_p(edges.data_ptr()),
                                                ctypes.c_void_p(weights.data_ptr()),
                                                ctypes.c_void_p(d2.data_ptr() if d2 is not None else 0),

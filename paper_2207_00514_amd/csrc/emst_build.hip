@@ -3278,12 +3278,16 @@ extern "C" int emst_build_mreach(emst_ctx* ctx, const float* d_points, int64_t n
 // emst_build_batched builds it (one tree in which every request is its own
 // subtree, one round loop), run as a resumable sequence of phases -- boxes
 // and Morton codes, tree, boxes and the first round, one Boruvka round per
-// phase, edge order.  Each cohort has its own stream (default priority) and
-// event; a step starts a cohort, then moves every cohort whose phase has
+// phase, edge order.  Each cohort has its own stream (default priority); a
+// step starts a cohort, then moves every cohort whose queued phase has
 // completed on to its next one, and returns once at least one has moved.
-// Cohorts progress at their own pace, the kernels of all requests of a
-// cohort are launched once per phase, and at most kSolverCohorts run at
-// once, so that requests arriving meanwhile gather into the next cohort.
+// As in emst_build, the round after the one in flight is queued before the
+// host has read the first while the last shrink predicts that more rounds
+// are needed (a round queued past the end returns at once), so a cohort's
+// rounds do not wait for the host.  Cohorts progress at their own pace, the
+// kernels of all requests of a cohort are launched once per phase, and at
+// most kSolverCohorts run at once, so that requests arriving meanwhile
+// gather into the next cohort.
 
 #ifndef EMST_SOLVER_COHORTS
 #define EMST_SOLVER_COHORTS 8
@@ -3320,9 +3324,9 @@ static BatchBufs batch_bufs(char* ws, int64_t n, int32_t B) {
 
 enum BPhase { kBCodes, kBTree, kBFit, kBRound, kBFinal, kBDone };
 
-// One batch as phases.  Every phase ends with a copy of the control block
-// into the job's pinned mirror (after the first also of the cloud boxes);
-// bjob_advance reads the mirror once the phase has completed.
+// One batch as phases.  Every queued phase ends with a copy of the control
+// block into one of two pinned mirrors (after the first phase also of the
+// cloud boxes); bjob_advance reads it once the phase has completed.
 struct BJob {
     int32_t B = 0;
     int64_t n = 0;               // points of all clouds (each has two or more)
@@ -3332,9 +3336,14 @@ struct BJob {
     int32_t* edges = nullptr;
     float* weights = nullptr;
     float* d2 = nullptr;
-    char* h = nullptr;           // pinned host mirror (bjob_host_bytes(B))
-    int phase = kBCodes;
-    int round = 0;
+    char* h = nullptr;           // pinned host block (bjob_host_bytes(B))
+    int phase = kBCodes;         // the next phase to queue
+    bool wait = false;           // the phase in flight must be read before the next is queued
+    bool rounds_done = false;    // a round left one component per cloud
+    int next_round = 0;          // the next round to queue
+    int round = 0;               // the next round to read
+    int64_t ncomp = 0;           // components entering `round`
+    int64_t prev = 0;            // components entering `round` - 1 (0: none)
     int variant = 13;
     int lds_depth = 8;
     int height = 0;
@@ -3344,17 +3353,28 @@ struct BJob {
     int cloud_bits = 0;
     int nshifts = 0;
     int shifts[8] = {};
-    int64_t ncomp = 0;
     emst_stats S;
-    Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(h); }
-    CloudIn* cin() const { return reinterpret_cast<CloudIn*>(h + a256(sizeof(Ctrl))); }
+    Ctrl* ctrl(int k) const { return reinterpret_cast<Ctrl*>(h + (size_t)k * a256(sizeof(Ctrl))); }
+    CloudIn* cin() const { return reinterpret_cast<CloudIn*>(h + 2 * a256(sizeof(Ctrl))); }
     CloudBox* cbox() const {
         return reinterpret_cast<CloudBox*>(reinterpret_cast<char*>(cin()) + a256(sizeof(CloudIn) * (size_t)B));
     }
 };
 
 static size_t bjob_host_bytes(int32_t B) {
-    return a256(sizeof(Ctrl)) + a256(sizeof(CloudIn) * (size_t)B) + a256(sizeof(CloudBox) * (size_t)B);
+    return 2 * a256(sizeof(Ctrl)) + a256(sizeof(CloudIn) * (size_t)B) + a256(sizeof(CloudBox) * (size_t)B);
+}
+
+// Whether the job's next phase may be queued while `inflight` (0-2) queued
+// phases have not been read.
+static bool bjob_can_queue(const BJob& j, int inflight) {
+    if (j.phase == kBDone) return false;
+    if (inflight == 0) return true;
+    if (inflight >= 2 || j.wait) return false;
+    if (j.phase == kBRound)  // one round in flight: queue the next if the last shrink predicts it is needed
+        return j.next_round < 64 &&
+               (j.prev == 0 || (double)j.ncomp * (double)j.ncomp >= 2.0 * (double)j.prev * (double)j.B);
+    return j.phase == kBFinal;  // the round in flight was queued past the end
 }
 
 static TraverseArgs<3> bjob_args(const BJob& j, const BatchBufs& x) {
@@ -3365,11 +3385,13 @@ static TraverseArgs<3> bjob_args(const BJob& j, const BatchBufs& x) {
     return ta;
 }
 
-// Enqueue the job's current phase.
-static int bjob_enqueue(emst_ctx* ctx, BJob& j, hipStream_t st) {
+// Queue the job's next phase; its control block goes to `mirror`, and
+// *kind receives the phase queued.
+static int bjob_enqueue(emst_ctx* ctx, BJob& j, hipStream_t st, Ctrl* mirror, int* kind) {
     BatchBufs x = batch_bufs(j.ws, j.n, j.B);
     Bufs<3>& b = x.b;
     const int64_t n = j.n;
+    *kind = j.phase;
     switch (j.phase) {
     case kBCodes: {  // per-cloud boxes and quantisation, codes with the cloud id on top
         HIP_TRY(hipMemcpyAsync(x.cin, j.cin(), sizeof(CloudIn) * j.B, hipMemcpyHostToDevice, st));
@@ -3385,6 +3407,7 @@ static int bjob_enqueue(emst_ctx* ctx, BJob& j, hipStream_t st) {
         k_batch_morton<<<nb, 256, 0, st>>>(x.pts3, x.cloud_of, x.cm, n, 64 - j.cloud_bits, b.k0, b.v0, part);
         k_or_and_final<<<1, 256, 0, st>>>(part, nb, b.ctrl);
         HIP_TRY(hipMemcpyAsync(j.cbox(), x.cbox, sizeof(CloudBox) * j.B, hipMemcpyDeviceToHost, st));
+        j.wait = true;
         break;
     }
     case kBTree: {  // sort, gather, hierarchy
@@ -3395,6 +3418,7 @@ static int bjob_enqueue(emst_ctx* ctx, BJob& j, hipStream_t st) {
         k_fill_u32<<<grid_for(4 * n), 256, 0, st>>>(reinterpret_cast<uint32_t*>(b.eud), 4 * n, kNone);
         k_batch_sorted_cloud<<<grid_for(n), 256, 0, st>>>(x.cloud_of, perm, n, x.cloud_sorted);
         if (int rc = build_hierarchy<3>(ctx, b, codes, n, st)) return rc;
+        j.wait = true;
         break;
     }
     case kBFit: {  // boxes, every cloud's subtree root, the first round
@@ -3406,12 +3430,17 @@ static int bjob_enqueue(emst_ctx* ctx, BJob& j, hipStream_t st) {
         TraverseArgs<3> ta = bjob_args(j, x);
         if (int rc = enqueue_round<3>(ctx, b, ta, n, 0, j.height, j.variant, x.cloud_sorted, j.B, false, st))
             return rc;
+        j.next_round = 1;
+        j.phase = kBRound;
         break;
     }
     case kBRound: {
+        if (j.next_round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
         TraverseArgs<3> ta = bjob_args(j, x);
-        if (int rc = enqueue_round<3>(ctx, b, ta, n, j.round, j.height, j.variant, x.cloud_sorted, j.B, false, st))
+        if (int rc = enqueue_round<3>(ctx, b, ta, n, j.next_round, j.height, j.variant, x.cloud_sorted, j.B, false,
+                                      st))
             return rc;
+        ++j.next_round;
         break;
     }
     case kBFinal: {  // per-cloud canonical order (the full sort only after a long run of ties)
@@ -3419,24 +3448,26 @@ static int bjob_enqueue(emst_ctx* ctx, BJob& j, hipStream_t st) {
         if (int rc = sort_edges<3>(ctx, b, n, x.cloud_sorted, j.cloud_bits, j.full != 0, &order, st)) return rc;
         k_batch_edge_write<<<grid_for(n), 256, 0, st>>>(b.eud, order, x.cloud_sorted, x.cin, n, j.edges, j.weights,
                                                         j.d2);
+        j.wait = true;
         break;
     }
     default:
         return fail(ctx, EMST_EINTERNAL, "batch already finished");
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(j.ctrl(), b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(mirror, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     return EMST_OK;
 }
 
-// Once the phase has completed: read the mirror and pick the next phase.
-// After the first phase, clouds that fail validation are listed in *bad
-// (cloud, status) and the job stays where it is; the caller drops them and
-// starts the job again.
-static int bjob_advance(emst_ctx* ctx, BJob& j, std::vector<std::pair<int, int>>* bad) {
-    const Ctrl* h = j.ctrl();
-    switch (j.phase) {
+// Once a queued phase of kind `kind` has completed: read its mirror `h` and
+// pick the next phase.  After the first phase, clouds that fail validation
+// are listed in *bad (cloud, status) and the job stays where it is; the
+// caller drops them and starts the job again.  A round read after the last
+// one (queued before the end was known) changes nothing.
+static int bjob_advance(emst_ctx* ctx, BJob& j, int kind, const Ctrl* h, std::vector<std::pair<int, int>>* bad) {
+    switch (kind) {
     case kBCodes: {
+        j.wait = false;
         const CloudBox* cb = j.cbox();
         bad->clear();
         for (int32_t c = 0; c < j.B; ++c) {
@@ -3454,33 +3485,39 @@ static int bjob_advance(emst_ctx* ctx, BJob& j, std::vector<std::pair<int, int>>
         return EMST_OK;
     }
     case kBTree:
+        j.wait = false;
         if (int rc = check_hierarchy(ctx, h, j.n)) return rc;
         j.height = (int)h->height;
         j.root = h->root;
         j.S.tree_height = (int32_t)h->height;
         j.ncomp = j.n;
+        j.prev = 0;
         j.round = 0;
+        j.next_round = 0;
+        j.rounds_done = false;
         j.phase = kBFit;
         return EMST_OK;
     case kBFit:
     case kBRound: {
-        if (j.round >= 64) return fail(ctx, EMST_EINTERNAL, "too many rounds");
-        j.S.components[j.round] = j.ncomp;
+        if (j.rounds_done) return EMST_OK;  // queued past the end: it returned at once
+        const int64_t entering = j.ncomp;
+        j.S.components[j.round] = entering;
         if (int rc = finish_round(ctx, h, j.round, j.B, j.ncomp, j.S)) return rc;
+        j.prev = entering;
         ++j.round;
         if (j.ncomp <= j.B) {
             if ((int64_t)h->edge_count != j.edges_total) return fail(ctx, EMST_EINTERNAL, "wrong edge count");
             j.S.rounds = j.round;
             j.S.traversal_launches = j.round;
             j.S.traversal_variant = j.variant;
+            j.rounds_done = true;
             j.phase = kBFinal;
-        } else {
-            j.phase = kBRound;
         }
         return EMST_OK;
     }
     case kBFinal:
-        if (h->long_ties && !j.full) j.full = 1;
+        j.wait = false;
+        if (h->long_ties && !j.full) j.full = 1;  // again, with the full sort
         else j.phase = kBDone;
         return EMST_OK;
     default:
@@ -3504,17 +3541,20 @@ struct SolverSlot {
 struct Cohort {
     bool live = false;      // phases still to run
     bool held = false;      // owns its region (live: outputs and workspace; finished: the outputs
-                            // until every member's result is taken)
-    bool inflight = false;  // a phase is queued on `st`, `ev` follows it
+                            // until every member's result is taken and copied)
     bool fresh = false;     // not started: its first phase waits for the caller's stream
+    bool releasing = false; // every result taken; the region is free once `rel` has completed
     std::vector<int> slots; // member slots, in cloud order
     size_t off = 0, bytes = 0;
     int remaining = 0;      // members whose results were not taken yet
     BJob job;
-    char* host = nullptr;   // pinned mirror of the job
+    char* host = nullptr;   // pinned block of the job
     size_t host_bytes = 0;
     hipStream_t st = nullptr;
-    hipEvent_t ev = nullptr;
+    int nq = 0, head = 0;   // queued phases not yet read: a ring of two
+    int kind[2] = {};
+    hipEvent_t ev[2] = {};  // follows each queued phase
+    hipEvent_t rel = nullptr;
 };
 
 struct emst_solver {
@@ -3571,6 +3611,23 @@ static bool sv_place(const emst_solver* sv, size_t need, bool high, size_t* at) 
     return found;
 }
 
+// The largest free range of the budget.
+static size_t sv_largest_gap(const emst_solver* sv) {
+    std::vector<std::pair<size_t, size_t>> used;
+    for (const SolverSlot& q : sv->slots)
+        if (q.state != 0 && q.bytes) used.push_back({q.off, q.off + q.bytes});
+    for (const Cohort& c : sv->cohorts)
+        if (c.held) used.push_back({c.off, c.off + c.bytes});
+    std::sort(used.begin(), used.end());
+    size_t best = 0, prev = 0;
+    for (size_t k = 0; k <= used.size(); ++k) {
+        const size_t gap_end = k < used.size() ? used[k].first : sv->budget;
+        if (gap_end > prev) best = std::max(best, gap_end - prev);
+        if (k < used.size()) prev = std::max(prev, used[k].second);
+    }
+    return best;
+}
+
 extern "C" void emst_solver_destroy(emst_solver* sv);
 
 extern "C" int emst_solver_create(emst_ctx* ctx, void* d_budget, size_t budget_bytes, int32_t max_slots,
@@ -3602,11 +3659,22 @@ extern "C" void emst_solver_destroy(emst_solver* sv) {
             (void)hipStreamSynchronize(c.st);
             (void)hipStreamDestroy(c.st);
         }
-        if (c.ev) (void)hipEventDestroy(c.ev);
+        for (hipEvent_t e : c.ev)
+            if (e) (void)hipEventDestroy(e);
+        if (c.rel) (void)hipEventDestroy(c.rel);
         if (c.host) (void)hipHostFree(c.host);
     }
     if (sv->fork) (void)hipEventDestroy(sv->fork);
     delete sv;
+}
+
+// Regions of cohorts whose results have all been taken and copied are free.
+static void reclaim(emst_solver* sv) {
+    for (Cohort& c : sv->cohorts)
+        if (c.releasing && hipEventQuery(c.rel) == hipSuccess) {
+            c.releasing = false;
+            c.held = false;
+        }
 }
 
 extern "C" int emst_solver_admit(emst_solver* sv, const float* d_points, int64_t n, int32_t dim, int64_t tag,
@@ -3626,6 +3694,7 @@ extern "C" int emst_solver_admit(emst_solver* sv, const float* d_points, int64_t
     if (free_slot < 0) return fail(ctx, EMST_EBUSY, "no free slot");
     if (sv->reserved + quota > sv->budget) return fail(ctx, EMST_EBUSY, "budget full");
     const size_t pts_bytes = n >= 2 ? a256((size_t)n * dim * 4) : 0;
+    reclaim(sv);
     size_t at = 0;
     if (pts_bytes && !sv_place(sv, pts_bytes, true, &at)) return fail(ctx, EMST_EBUSY, "budget full");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
@@ -3679,7 +3748,12 @@ static void cohort_tables(emst_solver* sv, Cohort& co) {
     j.ws = region + output_bytes(j.edges_total);
     j.pts = reinterpret_cast<const float*>(sv->base);
     j.phase = kBCodes;
+    j.wait = false;
+    j.rounds_done = false;
+    j.next_round = 0;
     j.round = 0;
+    j.ncomp = 0;
+    j.prev = 0;
     j.full = 0;
     memset(&j.S, 0, sizeof(j.S));
 }
@@ -3692,23 +3766,25 @@ static int form_cohort(emst_solver* sv, int* done) {
     int live = 0;
     for (const Cohort& c : sv->cohorts) live += c.live;
     if (live >= kSolverCohorts) return EMST_OK;
+    reclaim(sv);
     std::vector<int> wait;
     for (int s = 0; s < (int)sv->slots.size(); ++s)
         if (sv->slots[s].state == 1 && sv->slots[s].cohort < 0) wait.push_back(s);
     if (wait.empty()) return EMST_OK;
     std::sort(wait.begin(), wait.end(), [&](int a, int b) { return sv->slots[a].order < sv->slots[b].order; });
+    const size_t gap = sv_largest_gap(sv);
     int k = 0;
     size_t at = 0;
     int64_t pts = 0, edges = 0;
     for (int s : wait) {
         const int64_t n = sv->slots[s].n;
-        size_t where = 0;
-        if (!sv_place(sv, cohort_bytes(pts + n, k + 1, edges + n - 1), false, &where)) break;
-        at = where;
+        if (cohort_bytes(pts + n, k + 1, edges + n - 1) > gap) break;
         pts += n;
         edges += n - 1;
         ++k;
     }
+    if (k > 0 && !sv_place(sv, cohort_bytes(pts, k, edges), false, &at))
+        return fail(ctx, EMST_EINTERNAL, "no range for a cohort that fits the largest gap");
     if (k == 0) {
         bool any_held = false;
         for (const Cohort& c : sv->cohorts) any_held |= c.held;
@@ -3730,8 +3806,9 @@ static int form_cohort(emst_solver* sv, int* done) {
     Cohort& co = sv->cohorts[ci];
     if (!co.st && hipStreamCreateWithFlags(&co.st, hipStreamNonBlocking) != hipSuccess)
         return fail(ctx, EMST_EHIP, "hipStreamCreate failed");
-    if (!co.ev && hipEventCreateWithFlags(&co.ev, hipEventDisableTiming) != hipSuccess)
-        return fail(ctx, EMST_EHIP, "hipEventCreate failed");
+    for (hipEvent_t* e : {&co.ev[0], &co.ev[1], &co.rel})
+        if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+            return fail(ctx, EMST_EHIP, "hipEventCreate failed");
     const size_t hb = bjob_host_bytes(k);
     if (co.host_bytes < hb) {
         if (co.host) (void)hipHostFree(co.host);
@@ -3747,8 +3824,10 @@ static int form_cohort(emst_solver* sv, int* done) {
     co.held = true;
     co.live = true;
     co.remaining = k;
-    co.inflight = false;
+    co.nq = 0;
+    co.head = 0;
     co.fresh = true;
+    co.releasing = false;
     co.job = BJob();
     co.job.h = co.host;
     int t = 13, depth = 8;
@@ -3762,6 +3841,8 @@ static int form_cohort(emst_solver* sv, int* done) {
 
 // A cohort's members fail together with `rc`.
 static void cohort_fail(emst_solver* sv, Cohort& co, int rc, const std::string& msg, int* done) {
+    (void)hipStreamSynchronize(co.st);  // nothing queued may outlive the region
+    co.nq = 0;
     for (int s : co.slots) {
         SolverSlot& q = sv->slots[s];
         q.state = rc;
@@ -3776,12 +3857,11 @@ static void cohort_fail(emst_solver* sv, Cohort& co, int rc, const std::string& 
     co.remaining = 0;
 }
 
-// The host side of a completed phase of cohort c.
-static void cohort_advance(emst_solver* sv, Cohort& co, int* done) {
+// The host side of a completed phase (kind, mirror) of a cohort.
+static void cohort_advance(emst_solver* sv, Cohort& co, int kind, const Ctrl* mirror, int* done) {
     emst_ctx* ctx = sv->ctx;
     std::vector<std::pair<int, int>> bad;
-    const int phase = co.job.phase;
-    const int rc = bjob_advance(ctx, co.job, &bad);
+    const int rc = bjob_advance(ctx, co.job, kind, mirror, &bad);
     if (rc) {
         cohort_fail(sv, co, rc, ctx->err, done);
         return;
@@ -3814,7 +3894,7 @@ static void cohort_advance(emst_solver* sv, Cohort& co, int* done) {
         }
         return;
     }
-    if (phase == kBCodes)  // the points are in the workspace now
+    if (kind == kBCodes)  // the points are in the workspace now
         for (int s : co.slots) release_points(sv->slots[s]);
     if (co.job.phase == kBDone) {
         co.live = false;
@@ -3842,31 +3922,33 @@ extern "C" int emst_solver_step(emst_solver* sv, void* stream, int32_t* n_finish
         bool moved = false, busy = false;
         for (Cohort& co : sv->cohorts) {
             if (!co.live) continue;
-            if (co.inflight) {
-                const hipError_t q = hipEventQuery(co.ev);
-                if (q == hipErrorNotReady) {
-                    busy = true;
-                    continue;
-                }
+            while (co.nq > 0) {  // read the completed phases in order
+                const hipError_t q = hipEventQuery(co.ev[co.head]);
+                if (q == hipErrorNotReady) break;
                 if (q != hipSuccess) return fail(ctx, EMST_EHIP, hipGetErrorString(q));
-                co.inflight = false;
+                const int k = co.head;
+                co.head ^= 1;
+                --co.nq;
                 moved = true;
-                cohort_advance(sv, co, &done);
-                if (!co.live) continue;
+                cohort_advance(sv, co, co.kind[k], co.job.ctrl(k), &done);
+                if (!co.live) break;
             }
-            if (co.fresh) {
-                HIP_TRY(hipStreamWaitEvent(co.st, sv->fork, 0));
-                co.fresh = false;
+            if (!co.live) continue;
+            while (bjob_can_queue(co.job, co.nq)) {
+                if (co.fresh) {
+                    HIP_TRY(hipStreamWaitEvent(co.st, sv->fork, 0));
+                    co.fresh = false;
+                }
+                const int k = co.head ^ co.nq;
+                if (int rc = bjob_enqueue(ctx, co.job, co.st, co.job.ctrl(k), &co.kind[k])) {
+                    cohort_fail(sv, co, rc, ctx->err, &done);
+                    moved = true;
+                    break;
+                }
+                HIP_TRY(hipEventRecord(co.ev[k], co.st));
+                ++co.nq;
             }
-            if (int rc = bjob_enqueue(ctx, co.job, co.st)) {
-                (void)hipStreamSynchronize(co.st);
-                cohort_fail(sv, co, rc, ctx->err, &done);
-                moved = true;
-                continue;
-            }
-            HIP_TRY(hipEventRecord(co.ev, co.st));
-            co.inflight = true;
-            busy = true;
+            busy |= co.live && co.nq > 0;
         }
         if (moved || !busy) break;
         std::this_thread::yield();
@@ -3879,6 +3961,83 @@ extern "C" int emst_solver_poll(const emst_solver* sv, int32_t slot, int32_t* st
     if (!sv || slot < 0 || slot >= (int)sv->slots.size() || !state) return EMST_EINVAL;
     *state = sv->slots[slot].state;
     if (tag) *tag = sv->slots[slot].tag;
+    return EMST_OK;
+}
+
+extern "C" int emst_solver_ready(const emst_solver* sv, int32_t* slots, int32_t cap, int32_t* count) {
+    if (!sv || !count || cap < 0 || (cap > 0 && !slots)) return EMST_EINVAL;
+    std::vector<std::pair<std::pair<int, int64_t>, int32_t>> r;
+    for (int s = 0; s < (int)sv->slots.size(); ++s)
+        if (sv->slots[s].state == 2 || sv->slots[s].state < 0) r.push_back({{sv->slots[s].cohort, sv->slots[s].eoff}, s});
+    std::sort(r.begin(), r.end());
+    int32_t k = 0;
+    for (; k < cap && k < (int32_t)r.size(); ++k) slots[k] = r[k].second;
+    *count = k;
+    return EMST_OK;
+}
+
+extern "C" int emst_solver_take_many(emst_solver* sv, const int32_t* slots, int32_t count, int32_t* d_edges,
+                                     float* d_weights, float* d_d2, int64_t* h_offsets, void* stream) {
+    if (!sv || count < 0 || (count > 0 && (!slots || !h_offsets))) return EMST_EINVAL;
+    emst_ctx* ctx = sv->ctx;
+    ctx->err.clear();
+    std::vector<char> seen(sv->slots.size(), 0);
+    int64_t total = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t s = slots[i];
+        if (s < 0 || s >= (int32_t)sv->slots.size() || seen[s]) return fail(ctx, EMST_EINVAL, "bad or repeated slot");
+        seen[s] = 1;
+        if (sv->slots[s].state != 2) return fail(ctx, EMST_EINVAL, "slot holds no finished result");
+        h_offsets[i] = total;
+        total += sv->slots[s].n > 1 ? sv->slots[s].n - 1 : 0;
+    }
+    if (count > 0) h_offsets[count] = total;
+    if (total > 0 && (!d_edges || !d_weights)) return fail(ctx, EMST_EINVAL, "null pointer");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // one copy per array for every run of results that lie back to back in
+    // one cohort's outputs
+    for (int32_t i = 0; i < count;) {
+        const SolverSlot& q = sv->slots[slots[i]];
+        int64_t m = q.n > 1 ? q.n - 1 : 0;
+        int32_t k = i + 1;
+        if (q.cohort >= 0) {
+            for (; k < count; ++k) {
+                const SolverSlot& r = sv->slots[slots[k]];
+                if (r.cohort != q.cohort || r.eoff != q.eoff + m) break;
+                m += r.n - 1;
+            }
+            const BJob& j = sv->cohorts[q.cohort].job;
+            const int64_t o = h_offsets[i];
+            HIP_TRY(hipMemcpyAsync(d_edges + 2 * o, j.edges + 2 * q.eoff, (size_t)m * 8, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(d_weights + o, j.weights + q.eoff, (size_t)m * 4, hipMemcpyDeviceToDevice, st));
+            if (d_d2) HIP_TRY(hipMemcpyAsync(d_d2 + o, j.d2 + q.eoff, (size_t)m * 4, hipMemcpyDeviceToDevice, st));
+        }
+        i = k;
+    }
+    // each cohort touched passes the copies on its (idle) stream; the last
+    // take of a cohort frees its region once they are done
+    std::vector<int> taken(sv->cohorts.size(), 0);
+    for (int32_t i = 0; i < count; ++i)
+        if (sv->slots[slots[i]].cohort >= 0) ++taken[sv->slots[slots[i]].cohort];
+    for (int c = 0; c < (int)sv->cohorts.size(); ++c) {
+        if (!taken[c]) continue;
+        Cohort& co = sv->cohorts[c];
+        HIP_TRY(hipEventRecord(co.rel, st));
+        HIP_TRY(hipStreamWaitEvent(co.st, co.rel, 0));
+        co.remaining -= taken[c];
+        if (co.remaining == 0) {
+            HIP_TRY(hipEventRecord(co.rel, co.st));
+            co.releasing = true;
+        }
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        SolverSlot& q = sv->slots[slots[i]];
+        sv->reserved -= q.quota;
+        release_points(q);
+        q.cohort = -1;
+        q.state = 0;
+    }
     return EMST_OK;
 }
 
@@ -3901,16 +4060,23 @@ extern "C" int emst_solver_take(emst_solver* sv, int32_t slot, int32_t* d_edges,
     if (m) {
         if (!d_edges || !d_weights) return fail(ctx, EMST_EINVAL, "null pointer");
         if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, EMST_EHIP, "hipSetDevice failed");
-        const BJob& j = sv->cohorts[q.cohort].job;
+        Cohort& co = sv->cohorts[q.cohort];
+        const BJob& j = co.job;
         hipStream_t st = reinterpret_cast<hipStream_t>(stream);
         HIP_TRY(hipMemcpyAsync(d_edges, j.edges + 2 * q.eoff, m * 8, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(d_weights, j.weights + q.eoff, m * 4, hipMemcpyDeviceToDevice, st));
         if (d_d2) HIP_TRY(hipMemcpyAsync(d_d2, j.d2 + q.eoff, m * 4, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        // the cohort's (idle) stream passes these copies, so that its release
+        // event follows the copies of every take, whatever their streams
+        HIP_TRY(hipEventRecord(co.rel, st));
+        HIP_TRY(hipStreamWaitEvent(co.st, co.rel, 0));
     }
     if (q.cohort >= 0) {
         Cohort& co = sv->cohorts[q.cohort];
-        if (--co.remaining == 0) co.held = false;
+        if (--co.remaining == 0) {
+            HIP_TRY(hipEventRecord(co.rel, co.st));
+            co.releasing = true;
+        }
         q.cohort = -1;
     }
     sv->reserved -= q.quota;

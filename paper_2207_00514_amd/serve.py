@@ -292,9 +292,14 @@ class SolverServer:
                         self._uploading -= 1
                         self._cv.notify_all()
                 else:
-                    _, r, e, w, d = job
-                    r.edges, r.weights, r.d2 = e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()
-                    r.done = self.now()
+                    _, ev, reqs, e, w, d, offs = job
+                    stream.wait_event(ev)   # the solver's copies into e, w, d
+                    edges, weights, d2 = e.cpu().numpy(), w.cpu().numpy(), d.cpu().numpy()
+                    t = self.now()
+                    for i, r in enumerate(reqs):
+                        a, b = offs[i], offs[i + 1]
+                        r.edges, r.weights, r.d2 = edges[a:b], weights[a:b], d2[a:b]
+                        r.done = t
 
     def _run(self) -> None:
         import torch
@@ -319,21 +324,24 @@ class SolverServer:
                     running[slot] = r
                 if not running:
                     continue
-                fin = self._solver.step(stream=self._stream)
+                self._solver.step(stream=self._stream)
                 self._steps += 1
-                if fin == 0 and not any(len(r.points) < 2 for r in running.values()):
-                    continue
-                for slot in list(running):
-                    state, _ = self._solver.poll(slot)
-                    if state == 1:
+                ok = []
+                for slot in self._solver.ready():
+                    if self._solver.poll(slot)[0] == 2:
+                        ok.append(slot)
                         continue
-                    r = running.pop(slot)
+                    r = running.pop(slot)   # a failed request fails alone
                     try:
-                        e, w, d = self._solver.take(slot, stream=self._stream)
-                    except Exception as exc:  # a failed request fails alone
-                        r.error, r.done = str(exc), self.now()
-                        continue
-                    self._jobs.put(("down", r, e, w, d))
+                        self._solver.take(slot, stream=self._stream)
+                    except Exception as exc:
+                        r.error = str(exc)
+                    r.done = self.now()
+                if ok:
+                    e, w, d, offs = self._solver.take_many(ok, stream=self._stream)
+                    ev = torch.cuda.Event()
+                    ev.record(self._stream)
+                    self._jobs.put(("down", ev, [running.pop(s) for s in ok], e, w, d, offs))
 
 
 def replay(server, requests: List[Request], arrivals: List[float],

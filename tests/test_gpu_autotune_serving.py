@@ -227,6 +227,48 @@ def test_solver_round_granular_admission_equals_alone():
     solver.close()
 
 
+def test_solver_take_many_equals_alone():
+    """ready() lists finished slots by cohort and position; take_many copies
+    them back to back, each request's rows equal to its build alone; a
+    failed slot is refused by take_many and taken alone."""
+    import paper_2207_00514_amd as emst
+    ctx = emst.Context(0)
+    alone = emst.Context(0)
+    solver = emst.Solver(ctx, 256 << 20, max_slots=16)
+    clouds = [W.small_random(n, d, 90 + i, k) for i, (n, d, k) in enumerate(
+        [(4000, 3, "uniform"), (1, 3, "uniform"), (9000, 2, "dup"), (2, 3, "int"), (15000, 3, "outlier")])]
+    bad = W.small_random(300, 2, 99)
+    bad[3, 0] = np.nan
+    slots = [solver.admit(dev(c), tag=i) for i, c in enumerate(clouds[:3])]
+    f = solver.admit(dev(bad), tag=99)
+    solver.step()
+    slots += [solver.admit(dev(c), tag=3 + i) for i, c in enumerate(clouds[3:])]  # a second cohort
+    assert None not in slots and f is not None
+    _solve_all(solver, ctx)
+    ready = solver.ready()
+    assert sorted(ready) == sorted(slots + [f])
+    with pytest.raises(emst.EmstError) as ei:
+        solver.take_many([f] + slots)
+    assert ei.value.name == "EMST_EINVAL"
+    with pytest.raises(emst.EmstError) as ei:
+        solver.take(f)
+    assert ei.value.name == "EMST_ENONFINITE"
+    order = [s for s in solver.ready()]
+    assert sorted(order) == sorted(slots)
+    e, w, d, offs = solver.take_many(order)
+    e, w, d = host((e, w, d))
+    for k, s in enumerate(order):
+        c = clouds[slots.index(s)]
+        a, b = offs[k], offs[k + 1]
+        assert b - a == max(len(c) - 1, 0)
+        got = (e[a:b], w[a:b], d[a:b])
+        if len(c) < 2:
+            continue
+        assert same_tree(got, host(alone.build(dev(c)))), f"slot {s}"
+    assert solver.ready() == []
+    solver.close()
+
+
 def test_solver_budget_busy_and_failures():
     import paper_2207_00514_amd as emst
     ctx = emst.Context(0)
