@@ -2718,9 +2718,8 @@ void finish_stats(emst_ctx* ctx, emst_stats& S) {
 // One cloud's build as a resumable sequence of phases.  Each phase
 // enqueues its work and a copy of the control block into the job's pinned
 // host mirror; after the stream has drained, advance() reads the mirror and
-// picks the next phase.  emst_build runs one job to the end; the solver
-// (emst_solver_*) runs many, one phase each per step, with one wait per
-// step for all of them.
+// picks the next phase.  emst_build, emst_build_mreach and the one-round
+// test hook run one job to the end.
 //
 // k_pts = 0: the EMST.  k_pts >= 1: the MST under mutual reachability with
 // core distances of k_pts (k_pts = 1 gives zero cores, hence the EMST);

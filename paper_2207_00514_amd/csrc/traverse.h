@@ -454,10 +454,10 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                         atomicOr(&a.ctrl->error, kErrStack);
                         break;
                     }
-                    spill[base] = lds[base % kLdsDepth][t];
+                    spill[base] = lds[(unsigned)base % kLdsDepth][t];
                     ++base;
                 }
-                lds[sp % kLdsDepth][t] = far;
+                lds[(unsigned)sp % kLdsDepth][t] = far;
                 ++sp;
             } else if (go0 || go1) {
                 node = go0 ? c0.ref : c1.ref;
@@ -471,11 +471,11 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                     // ring empty: move spilled entries back first (rare), so
                     // that every pop is a plain LDS read
                     const int back = base < kLdsDepth ? base : kLdsDepth;
-                    for (int q = 1; q <= back; ++q) lds[(base - q) % kLdsDepth][t] = spill[base - q];
+                    for (int q = 1; q <= back; ++q) lds[(unsigned)(base - q) % kLdsDepth][t] = spill[base - q];
                     base -= back;
                 }
                 --sp;
-                const uint2 e = lds[sp % kLdsDepth][t];
+                const uint2 e = lds[(unsigned)sp % kLdsDepth][t];
                 if (bitsf(e.y) <= radius) {  // else the next iteration pops again
                     node = e.x;
                     have = true;
@@ -578,10 +578,10 @@ __global__ __launch_bounds__(256) void k_core_dist(TraverseArgs<DIM> a, int k, f
                     atomicOr(&a.ctrl->error, kErrStack);
                     break;
                 }
-                spill[base] = lds[base % kDepth][t];
+                spill[base] = lds[(unsigned)base % kDepth][t];
                 ++base;
             }
-            lds[sp % kDepth][t] = far;
+            lds[(unsigned)sp % kDepth][t] = far;
             ++sp;
             continue;
         }
@@ -593,11 +593,11 @@ __global__ __launch_bounds__(256) void k_core_dist(TraverseArgs<DIM> a, int k, f
         while (sp > 0) {
             if (sp == base) {  // as in k_traverse_fast
                 const int back = base < kDepth ? base : kDepth;
-                for (int q = 1; q <= back; ++q) lds[(base - q) % kDepth][t] = spill[base - q];
+                for (int q = 1; q <= back; ++q) lds[(unsigned)(base - q) % kDepth][t] = spill[base - q];
                 base -= back;
             }
             --sp;
-            const uint2 e = lds[sp % kDepth][t];
+            const uint2 e = lds[(unsigned)sp % kDepth][t];
             if (bitsf(e.y) <= radius) {
                 node = e.x;
                 found = true;
