@@ -445,24 +445,29 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
             }
             const bool go0 = in0 && !l0 && d0 <= radius;
             const bool go1 = in1 && !l1 && d1 <= radius;
-            if (go0 && go1) {
-                const bool near1 = d1 < d0;
-                const uint2 far = make_uint2(near1 ? c0.ref : c1.ref, fbits(near1 ? d0 : d1));
-                node = near1 ? c1.ref : c0.ref;
+            // the next node is a select; only deferring the farther child
+            // of two branches (few branches keep the wave's scalar
+            // instructions, which manage the lane masks, down)
+            const bool both = go0 && go1;
+            const bool near1 = d1 < d0;
+            const uint2 far = make_uint2(near1 ? c0.ref : c1.ref, fbits(near1 ? d0 : d1));
+            node = both ? (near1 ? c1.ref : c0.ref) : (go0 ? c0.ref : c1.ref);
+            have = go0 || go1;
+            if (both) {
                 if (sp - base == kLdsDepth) {  // ring full: move its oldest entry out
-                    if (base >= STACK) {
+                    if (base < STACK) {
+                        spill[base] = lds[(unsigned)base % kLdsDepth][t];
+                        ++base;
+                    } else {  // (cannot happen: the stack holds a tree's height) end the search
                         atomicOr(&a.ctrl->error, kErrStack);
-                        break;
+                        have = false;
+                        sp = base = 0;
                     }
-                    spill[base] = lds[(unsigned)base % kLdsDepth][t];
-                    ++base;
                 }
-                lds[(unsigned)sp % kLdsDepth][t] = far;
-                ++sp;
-            } else if (go0 || go1) {
-                node = go0 ? c0.ref : c1.ref;
-            } else {
-                have = false;
+                if (have) {
+                    lds[(unsigned)sp % kLdsDepth][t] = far;
+                    ++sp;
+                }
             }
             }
             if (!have) {
@@ -476,10 +481,9 @@ __global__ __launch_bounds__(256) void k_traverse_fast(TraverseArgs<DIM> a) {
                 }
                 --sp;
                 const uint2 e = lds[(unsigned)sp % kLdsDepth][t];
-                if (bitsf(e.y) <= radius) {  // else the next iteration pops again
-                    node = e.x;
-                    have = true;
-                }
+                // else the next iteration pops again
+                have = bitsf(e.y) <= radius;
+                node = have ? e.x : node;
             }
         }
     }
