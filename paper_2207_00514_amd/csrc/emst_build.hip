@@ -322,13 +322,21 @@ __device__ __forceinline__ int split_bit(const uint64_t* __restrict__ codes, int
 // between threads (agent-scope acquire/release would write back and
 // invalidate the per-XCD L2 caches at every step); every other store is read
 // by later kernels only.  The boxes are fitted afterwards, level by level.
-template <int DIM>
+// A node's leaf range, height and parent link go out together in one 16-byte
+// NodeInfo once its parent is known (k_unpack_nodes spreads them into their
+// arrays): the stores of the climb land at scattered nodes, and four separate
+// stores per node each cost a whole memory sector.  The child references
+// are written with the boxes by the fit (REFS: here as well, for the test
+// hook that reads the hierarchy without fitting it).
+struct alignas(16) NodeInfo {
+    uint32_t lo, hi, link, height;
+};
+
+template <int DIM, bool REFS>
 __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ codes,
                                                const uint32_t* __restrict__ orig, int64_t n, Rec<DIM>* recs,
-                                               uint32_t* __restrict__ leaf_parent,
-                                               uint32_t* __restrict__ node_parent, uint64_t* exch,
-                                               uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi,
-                                               uint8_t* __restrict__ height, Ctrl* ctrl) {
+                                               uint32_t* __restrict__ leaf_parent, NodeInfo* __restrict__ info,
+                                               uint64_t* exch, Ctrl* ctrl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t l = i, r = i;
@@ -348,9 +356,10 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         else left_child = split_bit(codes, r) < split_bit(codes, l - 1);
         const uint32_t parent = (uint32_t)(left_child ? r : l - 1);
         const int side = left_child ? 0 : 1;
-        set_child_ref<DIM>(&recs[parent], side, self_ref);
-        if (leaf) leaf_parent[i] = (parent << 1) | (uint32_t)side;
-        else node_parent[self] = (parent << 1) | (uint32_t)side;
+        const uint32_t link = (parent << 1) | (uint32_t)side;
+        if (REFS) set_child_ref<DIM>(&recs[parent], side, self_ref);
+        if (leaf) leaf_parent[i] = link;
+        else info[self] = NodeInfo{(uint32_t)l, (uint32_t)r, link, h};  // self's range and height
         // Two sibling leaves: node k holds leaves k and k+1 exactly when
         // leaf k is a left child and leaf k+1 a right child.  Both leaf
         // threads see this from the split bits of adjacent pairs (which
@@ -377,23 +386,35 @@ __global__ __launch_bounds__(256) void k_build(const uint64_t* __restrict__ code
         self = parent;
         self_ref = parent;
         leaf = false;
-        rlo[parent] = (uint32_t)l;
-        rhi[parent] = (uint32_t)r;
-        height[parent] = (uint8_t)h;
         if (l == 0 && r == n - 1) {
             ctrl->root = parent;
             ctrl->height = h;
-            node_parent[parent] = kNone;
+            info[parent] = NodeInfo{(uint32_t)l, (uint32_t)r, kNone, h};
             return;
         }
     }
 }
 
-// A leaf's box is its point, stored in its parent's record.  The left leaf
-// of two sibling leaves (a node of height 1) also stores their union in
-// that node's parent's record, so the level fit starts at height 2.
+__global__ __launch_bounds__(256) void k_unpack_nodes(const NodeInfo* __restrict__ info, int64_t m,
+                                                      uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi,
+                                                      uint32_t* __restrict__ node_parent,
+                                                      uint8_t* __restrict__ height) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const NodeInfo x = info[k];
+    rlo[k] = x.lo;
+    rhi[k] = x.hi;
+    node_parent[k] = x.link;
+    height[k] = (uint8_t)x.height;
+}
+
+// A leaf's box is its point, stored with its reference in its parent's
+// record.  The left leaf of two sibling leaves (a node of height 1) also
+// stores their union in that node's parent's record, so the level fit
+// starts at height 2.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ spts,
+                                                    const uint32_t* __restrict__ orig,
                                                     const uint32_t* __restrict__ leaf_parent,
                                                     const uint32_t* __restrict__ node_parent, int64_t n,
                                                     Rec<DIM>* recs) {
@@ -403,7 +424,7 @@ __global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ sp
 #pragma unroll
     for (int k = 0; k < DIM; ++k) p[k] = spts[i * DIM + k];
     const uint32_t link = leaf_parent[i];
-    set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), p, p);
+    set_child<DIM>(&recs[link >> 1], (int)(link & 1u), p, p, orig[i] | kLeafFlag);
     if ((link & 1u) == 0u && i + 1 < n && leaf_parent[i + 1] == (link | 1u)) {
         const uint32_t up = node_parent[link >> 1];
         if (up == kNone) return;
@@ -414,7 +435,7 @@ __global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ sp
             lo[k] = fminf(p[k], q);
             hi[k] = fmaxf(p[k], q);
         }
-        set_child_box<DIM>(&recs[up >> 1], (int)(up & 1u), lo, hi);
+        set_child<DIM>(&recs[up >> 1], (int)(up & 1u), lo, hi, link >> 1);
     }
 }
 
@@ -460,7 +481,7 @@ __global__ __launch_bounds__(256) void k_fit_level(const uint32_t* __restrict__ 
             lo[d] = fminf(c0.lo[d], c1.lo[d]);
             hi[d] = fmaxf(c0.hi[d], c1.hi[d]);
         }
-        set_child_box<DIM>(&recs[link >> 1], (int)(link & 1u), lo, hi);
+        set_child<DIM>(&recs[link >> 1], (int)(link & 1u), lo, hi, k);
     }
 }
 
@@ -2652,9 +2673,11 @@ int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_clou
 // Hierarchy (bottom-up, exchange only) and the leaf boxes.
 template <int DIM>
 int build_hierarchy(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hipStream_t st) {
-    k_build<DIM><<<grid_for(n), 256, 0, st>>>(codes, b.orig, n, b.recs, b.leaf_parent, b.node_parent, b.exch, b.rlo,
-                                              b.rhi, b.height, b.ctrl);
-    k_fit_leaves<DIM><<<grid_for(n), 256, 0, st>>>(b.spts, b.leaf_parent, b.node_parent, n, b.recs);
+    // the node infos live in the cells' array until the cells are made
+    NodeInfo* info = reinterpret_cast<NodeInfo*>(b.up);
+    k_build<DIM, false><<<grid_for(n), 256, 0, st>>>(codes, b.orig, n, b.recs, b.leaf_parent, info, b.exch, b.ctrl);
+    k_unpack_nodes<<<grid_for(n - 1), 256, 0, st>>>(info, n - 1, b.rlo, b.rhi, b.node_parent, b.height);
+    k_fit_leaves<DIM><<<grid_for(n), 256, 0, st>>>(b.spts, b.orig, b.leaf_parent, b.node_parent, n, b.recs);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
 }
@@ -4390,8 +4413,9 @@ extern "C" int emst_test_tree_from_codes(emst_ctx* ctx, const uint64_t* d_codes,
     k_init_ctrl<<<1, 64, 0, st>>>(ctrl);
     k_test_prep<<<grid_for(n), 256, 0, st>>>(d_leaf_labels, n, spts, orig, labels, exch);
     uint8_t* height = reinterpret_cast<uint8_t*>(ws + L.height);
-    k_build<3><<<grid_for(n), 256, 0, st>>>(d_codes, orig, n, recs, leaf_parent, node_parent, exch, rlo, rhi, height,
-                                            ctrl);
+    NodeInfo* info = reinterpret_cast<NodeInfo*>(ws + L.up);
+    k_build<3, true><<<grid_for(n), 256, 0, st>>>(d_codes, orig, n, recs, leaf_parent, info, exch, ctrl);
+    k_unpack_nodes<<<grid_for(n - 1), 256, 0, st>>>(info, n - 1, rlo, rhi, node_parent, height);
     HIP_TRY(propagate_labels(labels, run_part, run_carry, rlo, rhi, lab2, n, ctrl, st));
     k_test_extract<<<grid_for(n - 1), 256, 0, st>>>(recs, lab2, node_parent, n - 1, d_left, d_right, d_label);
     HIP_TRY(hipGetLastError());

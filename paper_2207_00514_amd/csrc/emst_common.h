@@ -76,20 +76,24 @@ __device__ __forceinline__ void unpack<2>(const Rec<2>& r, Child<2>& c0, Child<2
     c0.lab = kInvalid; c0.ref = r.meta.y; c1.lab = kInvalid; c1.ref = r.meta.w;
 }
 
-// Write the reference / the box of child `side` of record r.
+// Write the reference of child `side` of record r.
 template <int DIM>
 __device__ __forceinline__ void set_child_ref(Rec<DIM>* r, int side, uint32_t ref) {
     if (DIM == 3) reinterpret_cast<uint32_t*>(r)[8 * side + 7] = ref;
     else reinterpret_cast<uint32_t*>(r)[8 + 2 * side + 1] = ref;
 }
 
+// Box and reference of child `side` in one go (3D: the whole 32-byte half
+// of the record, two 16-byte stores).
 template <int DIM>
-__device__ __forceinline__ void set_child_box(Rec<DIM>* r, int side, const float* lo, const float* hi) {
-    float* f = reinterpret_cast<float*>(r) + (DIM == 3 ? 8 : 4) * side;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        f[k] = lo[k];
-        f[(DIM == 3 ? 4 : 2) + k] = hi[k];
+__device__ __forceinline__ void set_child(Rec<DIM>* r, int side, const float* lo, const float* hi, uint32_t ref) {
+    if constexpr (DIM == 3) {
+        float4* f = reinterpret_cast<float4*>(r) + 2 * side;
+        f[0] = make_float4(lo[0], lo[1], lo[2], 0.f);
+        f[1] = make_float4(hi[0], hi[1], hi[2], __uint_as_float(ref));
+    } else {
+        reinterpret_cast<float4*>(r)[side] = make_float4(lo[0], lo[1], hi[0], hi[1]);
+        reinterpret_cast<uint32_t*>(r)[8 + 2 * side + 1] = ref;
     }
 }
 
