@@ -55,20 +55,23 @@ TRAFFIC_SOURCES = ("traverse.h", "emst_common.h", "emst_kernels.h")
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 MEASURED_TRAFFIC = {
     # (workload, variant, source hash): (FETCH_SIZE KiB, WRITE_SIZE KiB, TCC hit fraction, profile)
-    ("cosmology3d_37m", 13, "0ca00fd74b4dbfa9"):
-        (1183503.0, 294826.5, 0.882, "profiles/k_traverse_fast_cosmology3d_37m.md"),
+    ("cosmology3d_37m", 13, "a2025fcf28faa80d"):
+        (1172456.2, 294876.0, 0.881, "profiles/k_traverse_fast_cosmology3d_37m.md"),
 }
 # What bounds the traversal, from counters of the same runs (per launch
 # type): VALU busy = VALU issue cycles / (SIMDs x kernel cycles), lane
-# utilisation = active lanes per VALU instruction / 64, resident waves per CU.
+# utilisation = active lanes per VALU instruction / 64, resident waves per
+# CU, scalar instructions per vector instruction.
 MEASURED_LIMITER = {
     # (workload, variant, source hash): {"full": {...}, "list": {...}, "profile": path}
-    ("cosmology3d_37m", 13, "0ca00fd74b4dbfa9"): {
-        "bound_by": "VALU issue x lane divergence (not HBM)",
-        "full": {"launches": "rounds 0-1", "valu_busy": 0.740, "lane_utilisation": 0.396,
-                 "waves_per_cu": 27.3, "of_waves_per_cu": 32, "l2_hit": 0.908, "hbm_frac": 0.095},
-        "list": {"launches": "rounds 2-10", "valu_busy": 0.554, "lane_utilisation": 0.521,
-                 "waves_per_cu": 24.7, "of_waves_per_cu": 32, "l2_hit": 0.853, "hbm_frac": 0.150},
+    ("cosmology3d_37m", 13, "a2025fcf28faa80d"): {
+        "bound_by": "instruction issue x lane divergence (not HBM)",
+        "full": {"launches": "rounds 0-1", "valu_busy": 0.568, "lane_utilisation": 0.406,
+                 "salu_per_valu": 0.94, "waves_per_cu": 27.2, "of_waves_per_cu": 32, "l2_hit": 0.907,
+                 "hbm_frac": 0.098},
+        "list": {"launches": "rounds 2-10", "valu_busy": 0.415, "lane_utilisation": 0.532,
+                 "salu_per_valu": 1.00, "waves_per_cu": 24.7, "of_waves_per_cu": 32, "l2_hit": 0.854,
+                 "hbm_frac": 0.150},
         "profile": "profiles/k_traverse_fast_cosmology3d_37m.md",
     },
 }

@@ -3831,11 +3831,8 @@ static int form_cohort(emst_solver* sv, int* done) {
     for (hipEvent_t* e : {&co.ev[0], &co.ev[1], &co.rel})
         if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
             return fail(ctx, EMST_EHIP, "hipEventCreate failed");
-    const size_t hb = bjob_host_bytes(k);
-    if (co.host_bytes < hb) {
-        if (co.host) (void)hipHostFree(co.host);
-        co.host = nullptr;
-        co.host_bytes = 0;
+    if (!co.host) {  // sized once for the largest cohort (pinned allocations are slow)
+        const size_t hb = bjob_host_bytes((int32_t)sv->slots.size());
         if (hipHostMalloc((void**)&co.host, hb, hipHostMallocDefault) != hipSuccess)
             return fail(ctx, EMST_EHIP, "hipHostMalloc failed");
         co.host_bytes = hb;
@@ -3937,12 +3934,18 @@ extern "C" int emst_solver_step(emst_solver* sv, void* stream, int32_t* n_finish
     int done = 0;
     if (int rc = form_cohort(sv, &done)) return rc;
     bool fresh = false;
-    for (const Cohort& c : sv->cohorts) fresh |= c.live && c.fresh;
+    std::vector<Cohort*> act;  // the live cohorts (the table holds one entry per slot)
+    for (Cohort& c : sv->cohorts)
+        if (c.live) {
+            act.push_back(&c);
+            fresh |= c.fresh;
+        }
     // a new cohort starts after what the caller's stream holds (admitted points)
     if (fresh) HIP_TRY(hipEventRecord(sv->fork, reinterpret_cast<hipStream_t>(stream)));
     for (;;) {
         bool moved = false, busy = false;
-        for (Cohort& co : sv->cohorts) {
+        for (Cohort* cp : act) {
+            Cohort& co = *cp;
             if (!co.live) continue;
             while (co.nq > 0) {  // read the completed phases in order
                 const hipError_t q = hipEventQuery(co.ev[co.head]);
