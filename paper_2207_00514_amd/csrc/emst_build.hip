@@ -408,69 +408,114 @@ __global__ __launch_bounds__(256) void k_unpack_nodes(const NodeInfo* __restrict
     height[k] = (uint8_t)x.height;
 }
 
-// A leaf's box is its point, stored with its reference in its parent's
-// record.  The left leaf of two sibling leaves (a node of height 1) also
-// stores their union in that node's parent's record, so the level fit
-// starts at height 2.
+// Boxes, bottom-up.  One workgroup per tile of kFitTile consecutive leaves
+// fits every node whose leaf range lies inside its tile: each leaf's thread
+// stores the leaf's box (its point) and reference into the parent's record
+// and climbs while the parent lies inside the tile; at each such node the
+// first child to arrive parks its box in LDS and stops, the second forms the
+// union, stores it with the node's reference into the node's parent's record
+// and climbs on.  Only LDS and one workgroup take part, so no thread waits
+// on another and no cross-XCD ordering is needed.  The same pass spreads the
+// tile's node records (range, parent link, height) into their arrays and
+// lists the tile's nodes whose range crosses a tile border; those (a few per
+// border and height) are fitted afterwards, one launch per height.
+constexpr int kFitTile = 1024;
+
 template <int DIM>
-__global__ __launch_bounds__(256) void k_fit_leaves(const float* __restrict__ spts,
-                                                    const uint32_t* __restrict__ orig,
-                                                    const uint32_t* __restrict__ leaf_parent,
-                                                    const uint32_t* __restrict__ node_parent, int64_t n,
-                                                    Rec<DIM>* recs) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float p[DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) p[k] = spts[i * DIM + k];
-    const uint32_t link = leaf_parent[i];
-    set_child<DIM>(&recs[link >> 1], (int)(link & 1u), p, p, orig[i] | kLeafFlag);
-    if ((link & 1u) == 0u && i + 1 < n && leaf_parent[i + 1] == (link | 1u)) {
-        const uint32_t up = node_parent[link >> 1];
-        if (up == kNone) return;
+__global__ __launch_bounds__(256) void k_fit_tiles(const float* __restrict__ spts, const uint32_t* __restrict__ orig,
+                                                   const uint32_t* __restrict__ leaf_parent,
+                                                   const NodeInfo* __restrict__ info, int64_t n, Rec<DIM>* recs,
+                                                   uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi,
+                                                   uint32_t* __restrict__ node_parent, uint8_t* __restrict__ height,
+                                                   uint2* __restrict__ span, uint32_t* __restrict__ span_count,
+                                                   Ctrl* ctrl) {
+    if (ctrl->error) return;  // the build failed: its records are incomplete
+    __shared__ uint32_t s_arrive[kFitTile];
+    __shared__ float s_box[kFitTile][2][2 * DIM];  // per node of the tile and child side: lo, hi
+    __shared__ uint32_t s_lo[kFitTile], s_hi[kFitTile], s_link[kFitTile];
+    __shared__ uint2 s_span[kFitTile];
+    __shared__ uint32_t s_nspan, s_base;
+    const int t = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kFitTile;
+    const int64_t m = n - 1;
+    if (t == 0) s_nspan = 0;
+    for (int x = t; x < kFitTile; x += 256) s_arrive[x] = 0;
+    __syncthreads();
+    for (int x = t; x < kFitTile; x += 256) {
+        const int64_t k = t0 + x;
+        if (k >= m) break;
+        const NodeInfo v = info[k];
+        rlo[k] = v.lo;
+        rhi[k] = v.hi;
+        node_parent[k] = v.link;
+        height[k] = (uint8_t)v.height;
+        s_lo[x] = v.lo;
+        s_hi[x] = v.hi;
+        s_link[x] = v.link;
+        if (v.lo / kFitTile != v.hi / kFitTile) s_span[atomicAdd(&s_nspan, 1u)] = make_uint2((uint32_t)k, v.height);
+    }
+    __syncthreads();
+    if (t == 0) s_base = s_nspan ? atomicAdd(span_count, s_nspan) : 0u;
+    __syncthreads();
+    // (the list has room for n - 1 entries, at most 129 per tile border of a
+    // valid tree)
+    for (uint32_t x = t; x < s_nspan; x += 256) {
+        if ((int64_t)s_base + x < m) span[s_base + x] = s_span[x];
+        else atomicOr(&ctrl->error, kErrStack);
+    }
+    const uint32_t lo_in = (uint32_t)t0, hi_in = (uint32_t)min<int64_t>(t0 + kFitTile - 1, n - 1);
+    for (int x = t; x < kFitTile; x += 256) {
+        const int64_t i = t0 + x;
+        if (i >= n) break;
         float lo[DIM], hi[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            const float q = spts[(i + 1) * DIM + k];
-            lo[k] = fminf(p[k], q);
-            hi[k] = fmaxf(p[k], q);
+        for (int k = 0; k < DIM; ++k) lo[k] = hi[k] = spts[i * DIM + k];
+        uint32_t link = leaf_parent[i];
+        uint32_t ref = orig[i] | kLeafFlag;
+        for (int step = 0; step < 160; ++step) {  // a climb passes at most height + 1 <= 129 nodes
+            const uint32_t P = link >> 1;
+            const int side = (int)(link & 1u);
+            if ((int64_t)P >= m) {  // (not from a valid tree)
+                atomicOr(&ctrl->error, kErrStack);
+                break;
+            }
+            set_child<DIM>(&recs[P], side, lo, hi, ref);
+            const int64_t ps = (int64_t)P - t0;
+            if (ps < 0 || ps >= kFitTile) break;                    // P spans the tile's border
+            if (s_lo[ps] < lo_in || s_hi[ps] > hi_in) break;         // likewise
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                s_box[ps][side][k] = lo[k];
+                s_box[ps][side][DIM + k] = hi[k];
+            }
+            __threadfence_block();
+            if (atomicAdd(&s_arrive[ps], 1u) == 0u) break;  // the sibling completes P
+            __threadfence_block();
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                lo[k] = fminf(lo[k], s_box[ps][1 - side][k]);
+                hi[k] = fmaxf(hi[k], s_box[ps][1 - side][DIM + k]);
+            }
+            ref = P;
+            link = s_link[ps];
+            if (link == kNone) break;  // the root
         }
-        set_child<DIM>(&recs[up >> 1], (int)(up & 1u), lo, hi, link >> 1);
     }
 }
 
-// Nodes grouped by height: keys = height, values = node id, for one stable
-// radix pass; then the first sorted position of every height.  Heights of
-// internal nodes run without gaps from 1 to the root's.
-__global__ __launch_bounds__(256) void k_height_keys(const uint8_t* __restrict__ height, int64_t m,
-                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    keys[k] = height[k];
-    vals[k] = (uint32_t)k;
-}
-
-__global__ __launch_bounds__(256) void k_level_starts(const uint64_t* __restrict__ keys, int64_t m,
-                                                      uint32_t* __restrict__ starts) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const uint32_t h = (uint32_t)keys[i];
-    if (i == 0 || keys[i - 1] != h) starts[h] = (uint32_t)i;
-    if (i == m - 1) starts[h + 1] = (uint32_t)m;
-}
-
-// Nodes of height h (sorted positions [starts[h], starts[h+1])): box = union
-// of the two child boxes in the own record, stored in the parent's record.
-// Children have smaller heights, so the launch of the previous level has
-// written them.
+// The listed nodes of height h (ranges across a tile border): box = union
+// of the two child boxes in the own record, stored with the node's
+// reference in the parent's record.  Their children are leaves and nodes
+// fitted by k_fit_tiles, or listed nodes of smaller height.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_fit_level(const uint32_t* __restrict__ ids,
-                                                   const uint32_t* __restrict__ starts, uint32_t h,
-                                                   const uint32_t* __restrict__ node_parent, Rec<DIM>* recs) {
-    const int64_t end = starts[h + 1];
-    for (int64_t j = starts[h] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < end;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = ids[j];
+__global__ __launch_bounds__(256) void k_fit_span(const uint2* __restrict__ span,
+                                                  const uint32_t* __restrict__ span_count, int64_t cap, uint32_t h,
+                                                  const uint32_t* __restrict__ node_parent, Rec<DIM>* recs) {
+    const uint32_t cnt = (uint32_t)min<int64_t>(*span_count, cap);
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
+        const uint2 e = span[j];
+        if (e.y != h) continue;
+        const uint32_t k = e.x;
         const uint32_t link = node_parent[k];
         if (link == kNone) continue;
         Child<DIM> c0, c1;
@@ -2670,14 +2715,20 @@ int sort_edges(emst_ctx* ctx, Bufs<DIM>& b, int64_t n, const uint32_t* slot_clou
     return EMST_OK;
 }
 
-// Hierarchy (bottom-up, exchange only) and the leaf boxes.
+// Hierarchy (bottom-up, exchange only) and the boxes of every node inside
+// a tile of kFitTile leaves.  The node records live in the cells' array,
+// the list of nodes across tile borders in the exchange words (both free
+// until the cells and the wave starts are made), its length in the sort's
+// histogram (free until the next sort).
 template <int DIM>
 int build_hierarchy(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, hipStream_t st) {
-    // the node infos live in the cells' array until the cells are made
     NodeInfo* info = reinterpret_cast<NodeInfo*>(b.up);
     k_build<DIM, false><<<grid_for(n), 256, 0, st>>>(codes, b.orig, n, b.recs, b.leaf_parent, info, b.exch, b.ctrl);
-    k_unpack_nodes<<<grid_for(n - 1), 256, 0, st>>>(info, n - 1, b.rlo, b.rhi, b.node_parent, b.height);
-    k_fit_leaves<DIM><<<grid_for(n), 256, 0, st>>>(b.spts, b.orig, b.leaf_parent, b.node_parent, n, b.recs);
+    k_fill_u32<<<1, 64, 0, st>>>(b.hist, 1, 0u);
+    const unsigned tiles = (unsigned)((n + kFitTile - 1) / kFitTile);
+    k_fit_tiles<DIM><<<tiles, 256, 0, st>>>(b.spts, b.orig, b.leaf_parent, info, n, b.recs, b.rlo, b.rhi,
+                                              b.node_parent, b.height, reinterpret_cast<uint2*>(b.exch), b.hist,
+                                              b.ctrl);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
 }
@@ -2689,26 +2740,17 @@ static int check_hierarchy(emst_ctx* ctx, const Ctrl* h, int64_t n) {
     return EMST_OK;
 }
 
-// The internal boxes, one launch per height below the root H: node ids are
-// grouped by height first (the exchange words, the key buffer not holding
-// the codes and the index buffers are dead by now).
+// The boxes of the nodes across tile borders, one launch per height below
+// the root H (after build_hierarchy, whose list they come from).
 template <int DIM>
 int fit_levels(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, uint32_t H, hipStream_t st) {
-    const int64_t m = n - 1;
-    uint64_t* hkeys = b.exch;
-    uint64_t* kfree = (codes == b.k0) ? b.k1 : b.k0;
-    k_height_keys<<<grid_for(m), 256, 0, st>>>(b.height, m, hkeys, b.v0);
-    const int hshift = 0;
-    int in1 = 0;
-    HIP_TRY(radix_sort_pairs(st, hkeys, b.v0, kfree, b.v1, b.hist, m, &hshift, 1, &in1));
-    const uint64_t* skeys = in1 ? kfree : hkeys;
-    const uint32_t* ids = in1 ? b.v1 : b.v0;
-    uint32_t* starts = b.hist;  // the sort's histogram is free again
-    k_level_starts<<<grid_for(m), 256, 0, st>>>(skeys, m, starts);
-    const unsigned fgrid = std::min<unsigned>(grid_for(m), 1024);
-    // height 1 (two leaves) was fitted with the leaves
-    for (uint32_t h = 2; h < H; ++h)
-        k_fit_level<DIM><<<fgrid, 256, 0, st>>>(ids, starts, h, b.node_parent, b.recs);
+    (void)codes;
+    // at most 128 listed nodes per tile border
+    const int64_t cap = ((n + kFitTile - 1) / kFitTile) * 128;
+    const unsigned grid = std::min<unsigned>(grid_for(cap), 1024);
+    for (uint32_t h = 1; h < H; ++h)
+        k_fit_span<DIM><<<grid, 256, 0, st>>>(reinterpret_cast<const uint2*>(b.exch), b.hist, n - 1, h,
+                                               b.node_parent, b.recs);
     HIP_TRY(hipGetLastError());
     return EMST_OK;
 }
