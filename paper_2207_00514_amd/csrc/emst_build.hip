@@ -419,7 +419,7 @@ __global__ __launch_bounds__(256) void k_unpack_nodes(const NodeInfo* __restrict
 // tile's node records (range, parent link, height) into their arrays and
 // lists the tile's nodes whose range crosses a tile border; those (a few per
 // border and height) are fitted afterwards, one launch per height.
-constexpr int kFitTile = 1024;
+constexpr int kFitTile = 512;  // 256 and 1024 measured slower (LDS per workgroup vs nodes across borders)
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_fit_tiles(const float* __restrict__ spts, const uint32_t* __restrict__ orig,
@@ -2745,8 +2745,9 @@ static int check_hierarchy(emst_ctx* ctx, const Ctrl* h, int64_t n) {
 template <int DIM>
 int fit_levels(emst_ctx* ctx, Bufs<DIM>& b, const uint64_t* codes, int64_t n, uint32_t H, hipStream_t st) {
     (void)codes;
-    // at most 128 listed nodes per tile border
-    const int64_t cap = ((n + kFitTile - 1) / kFitTile) * 128;
+    // at most 129 listed nodes per tile border (the grid only; the kernel
+    // reads the list's length)
+    const int64_t cap = ((n + kFitTile - 1) / kFitTile) * 129;
     const unsigned grid = std::min<unsigned>(grid_for(cap), 1024);
     for (uint32_t h = 1; h < H; ++h)
         k_fit_span<DIM><<<grid, 256, 0, st>>>(reinterpret_cast<const uint2*>(b.exch), b.hist, n - 1, h,
