@@ -321,13 +321,14 @@ __device__ __forceinline__ int split_bit(const uint64_t* __restrict__ codes, int
 // exchange and continues upwards.  Only the 64-bit atomic exchange crosses
 // between threads (agent-scope acquire/release would write back and
 // invalidate the per-XCD L2 caches at every step); every other store is read
-// by later kernels only.  The boxes are fitted afterwards, level by level.
-// A node's leaf range, height and parent link go out together in one 16-byte
-// NodeInfo once its parent is known (k_unpack_nodes spreads them into their
-// arrays): the stores of the climb land at scattered nodes, and four separate
-// stores per node each cost a whole memory sector.  The child references
-// are written with the boxes by the fit (REFS: here as well, for the test
-// hook that reads the hierarchy without fitting it).
+// by later kernels only.  The boxes are fitted afterwards (k_fit_tiles,
+// k_fit_span).  A node's leaf range, height and parent link go out together
+// in one 16-byte NodeInfo once its parent is known (the fit, or
+// k_unpack_nodes, spreads them into their arrays): the stores of the climb
+// land at scattered nodes, and four separate stores per node each cost a
+// whole memory sector.  The child references are written with the boxes by
+// the fit (REFS: here as well, for the test hook that reads the hierarchy
+// without fitting it).
 struct alignas(16) NodeInfo {
     uint32_t lo, hi, link, height;
 };
@@ -3354,10 +3355,7 @@ extern "C" int emst_build_mreach(emst_ctx* ctx, const float* d_points, int64_t n
 // most kSolverCohorts run at once, so that requests arriving meanwhile
 // gather into the next cohort.
 
-#ifndef EMST_SOLVER_COHORTS
-#define EMST_SOLVER_COHORTS 8
-#endif
-constexpr int kSolverCohorts = EMST_SOLVER_COHORTS;
+constexpr int kSolverCohorts = 8;  // live cohorts at most (4 and 16 measured no better on a serving trace)
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
