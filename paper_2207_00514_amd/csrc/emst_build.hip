@@ -1950,7 +1950,7 @@ static Layout make_layout(int64_t n, int dim) {
     L.k1 = take(keys);
     L.v0 = take(4 * N);
     L.v1 = take(4 * N);
-    L.hist = take(4 * radix_hist_elems());
+    L.hist = take(4 * radix_scratch_elems(n));
     L.spts = take(4 * N * dim);
     L.orig = take(4 * N);
     L.cand_p = take(4 * N);

@@ -224,6 +224,199 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// One-sweep passes (decoupled look-back, Merrill & Garland; its use for LSD
+// radix sort by Adinets & Merrill): one global count of every digit of every
+// pass first, then per pass a single launch in which each workgroup takes
+// the next tile (in launch order, from a counter), ranks it as the downsweep
+// does, publishes its per-digit counts, and adds up the counts of the tiles
+// before it -- each tile publishes its own count before it looks back, and
+// the inclusive prefix once it knows it, so a look-back stops at the first
+// inclusive prefix it meets and only ever waits on tiles that have started.
+// A status word is (flag << 30) | count: flag 1 = the tile's own count,
+// 2 = inclusive prefix (counts stay below 2^30: kRadixOneMin <= n < 2^30).
+// The words go through device-coherent atomics; each one holds its datum.
+
+constexpr uint32_t kOsAgg = 1u << 30, kOsIncl = 2u << 30, kOsMask = (1u << 30) - 1u;
+
+struct RsShifts {
+    int s[8];
+};
+
+__global__ __launch_bounds__(kRsThreads) void rs_fill(uint32_t* __restrict__ p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// ghist[q][d] += occurrences of digit d at shift q among the keys.
+__global__ __launch_bounds__(kRsThreads) void rs_global_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                             RsShifts sh, int np, uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[kRsWaves][8][256];
+    const int t = threadIdx.x, w = t / 64;
+    for (int k = t; k < kRsWaves * 8 * 256; k += kRsThreads) (&h[0][0][0])[k] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + t; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        for (int q = 0; q < np; ++q) atomicAdd(&h[w][q][(uint32_t)(k >> sh.s[q]) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int k = t; k < np * 256; k += kRsThreads) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int v = 0; v < kRsWaves; ++v) c += (&h[v][0][0])[k];
+        if (c) atomicAdd(&ghist[k], c);
+    }
+}
+
+// gstart[q][d] = digits below d at shift q (one workgroup per shift).
+__global__ __launch_bounds__(kRsThreads) void rs_global_scan(const uint32_t* __restrict__ ghist,
+                                                             uint32_t* __restrict__ gstart) {
+    __shared__ uint32_t wsum[kRsWaves];
+    const int t = threadIdx.x, w = t / 64, lane = t & 63;
+    const uint32_t v = ghist[blockIdx.x * 256 + t];
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    gstart[blockIdx.x * 256 + t] = x - v + before;
+}
+
+__device__ __forceinline__ uint32_t os_load(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void os_store(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(kRsThreads) void rs_onesweep(const uint64_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          int64_t n, int shift, const uint32_t* __restrict__ gstart,
+                                                          uint32_t* status, uint32_t* status_next,
+                                                          uint32_t* counter, uint32_t* err) {
+    constexpr int kRsItems = ITEMS;
+    constexpr int kRsTile = kRsThreads * ITEMS;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t gbase[256];   // global start of every digit for this tile
+    __shared__ uint32_t lstart[256];  // tile-local start of every digit
+    __shared__ uint32_t wsum[kRsWaves];
+    __shared__ __attribute__((aligned(16))) uint32_t cnt[kRsItems][kRsWaves][256];
+    static_assert(sizeof(cnt) >= kRsTile * (sizeof(uint64_t) + sizeof(uint32_t)), "staging fits");
+    uint64_t* skey = reinterpret_cast<uint64_t*>(&cnt[0][0][0]);
+    uint32_t* sval = reinterpret_cast<uint32_t*>(skey + kRsTile);
+    const int t = threadIdx.x, w = t / 64, lane = t & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (t == 0) s_tile = atomicAdd(counter, 1u);
+    for (int k = t; k < kRsItems * kRsWaves * 256; k += kRsThreads) (&cnt[0][0][0])[k] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t tb = tile * kRsTile;
+    const int valid = (int)min((int64_t)kRsTile, n - tb);
+    uint64_t key[kRsItems];
+    uint32_t val[kRsItems], dig[kRsItems], rank[kRsItems];
+    bool ok[kRsItems];
+#pragma unroll
+    for (int s = 0; s < kRsItems; ++s) {
+        const int64_t idx = tb + (int64_t)s * kRsThreads + t;
+        ok[s] = idx < n;
+        key[s] = ok[s] ? kin[idx] : 0ull;
+        val[s] = ok[s] ? vin[idx] : 0u;
+        dig[s] = (uint32_t)(key[s] >> shift) & 255u;
+    }
+#pragma unroll
+    for (int s = 0; s < kRsItems; ++s) {
+        uint64_t peers = __ballot(ok[s]);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig[s] >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        rank[s] = (uint32_t)__popcll(peers & lt_mask);
+        if (ok[s] && rank[s] == 0) cnt[s][w][dig[s]] = (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    uint32_t total;
+    {
+        uint32_t off = 0;
+#pragma unroll
+        for (int s = 0; s < kRsItems; ++s)
+#pragma unroll
+            for (int ww = 0; ww < kRsWaves; ++ww) {
+                const uint32_t c = cnt[s][ww][t];
+                cnt[s][ww][t] = off;
+                off += c;
+            }
+        total = off;
+        uint32_t x = total;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        lstart[t] = x - total + before;
+    }
+    // digit t: publish this tile's count, add up the tiles before it
+    uint32_t excl = 0;
+    if (tile == 0) {
+        os_store(&status[t], kOsIncl | total);
+    } else {
+        os_store(&status[tile * 256 + t], kOsAgg | total);
+        for (int64_t p = tile - 1; p >= 0; --p) {
+            uint32_t v = os_load(&status[p * 256 + t]);
+            for (uint32_t spin = 0; (v >> 30) == 0u; ++spin) {
+                if (spin > (1u << 22)) {  // (bounded: a missing tile is a bug, not a wait)
+                    atomicOr(err, 1u);
+                    v = kOsIncl;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                v = os_load(&status[p * 256 + t]);
+            }
+            excl += v & kOsMask;
+            if ((v >> 30) == 2u) break;
+        }
+        os_store(&status[tile * 256 + t], kOsIncl | (excl + total));
+    }
+    gbase[t] = gstart[t] + excl;
+    os_store(&status_next[tile * 256 + t], 0u);  // the next pass's status starts empty
+    __syncthreads();
+    uint32_t lpos[kRsItems];
+#pragma unroll
+    for (int s = 0; s < kRsItems; ++s) lpos[s] = ok[s] ? lstart[dig[s]] + cnt[s][w][dig[s]] + rank[s] : 0u;
+    __syncthreads();  // cnt is reused for staging from here on
+#pragma unroll
+    for (int s = 0; s < kRsItems; ++s) {
+        if (ok[s]) {
+            skey[lpos[s]] = key[s];
+            sval[lpos[s]] = val[s];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kRsItems; ++s) {
+        const int lp = s * kRsThreads + t;
+        if (lp < valid) {
+            const uint64_t k = skey[lp];
+            const uint32_t d = (uint32_t)(k >> shift) & 255u;
+            const uint32_t dst = gbase[d] + (uint32_t)lp - lstart[d];
+            kout[dst] = k;
+            vout[dst] = sval[lp];
+        }
+    }
+}
+
 static int rs_items(int64_t n) { return n >= kRsBigN ? 16 : 8; }
 
 RadixPlan radix_plan(int64_t n) {
@@ -249,9 +442,37 @@ hipError_t radix_sort_pairs(hipStream_t stream, uint64_t* k0, uint32_t* v0, uint
                             uint32_t* hist, int64_t n, const int* shifts, int nshifts, int* result_in_1) {
     *result_in_1 = 0;
     if (n <= 1 || nshifts == 0) return hipSuccess;
-    const RadixPlan p = radix_plan(n);
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
+    if (n >= kRadixOneMin && n < ((int64_t)1 << 30) && nshifts <= 8) {
+        // scratch after the count table: global counts, global starts, the
+        // pass counters and an error word, two status arrays
+        const int64_t tiles = (n + kRadixOneTile - 1) / kRadixOneTile;
+        uint32_t* base = hist + radix_hist_elems();
+        uint32_t* ghist = base;
+        uint32_t* gstart = base + 8 * 256;
+        uint32_t* counters = base + 3 * 8 * 256;  // [8] pass counters, [9] error
+        uint32_t* status[2] = {counters + 64, counters + 64 + tiles * 256};
+        RsShifts sh;
+        for (int q = 0; q < 8; ++q) sh.s[q] = q < nshifts ? shifts[q] : 0;
+        rs_fill<<<1, kRsThreads, 0, stream>>>(ghist, 8 * 256);
+        rs_fill<<<1, kRsThreads, 0, stream>>>(counters, 64);
+        rs_fill<<<(unsigned)std::min<int64_t>((tiles * 256 + kRsThreads - 1) / kRsThreads, 1024), kRsThreads, 0,
+                  stream>>>(status[0], tiles * 256);
+        rs_global_hist<<<(unsigned)std::min<int64_t>(tiles, 1024), kRsThreads, 0, stream>>>(ka, n, sh, nshifts,
+                                                                                             ghist);
+        rs_global_scan<<<nshifts, kRsThreads, 0, stream>>>(ghist, gstart);
+        for (int q = 0; q < nshifts; ++q) {
+            rs_onesweep<16><<<(unsigned)tiles, kRsThreads, 0, stream>>>(ka, va, kb, vb, n, shifts[q], gstart + q * 256,
+                                                                        status[q & 1], status[(q + 1) & 1],
+                                                                        counters + q, counters + 8);
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        *result_in_1 = (nshifts & 1);
+        return hipGetLastError();
+    }
+    const RadixPlan p = radix_plan(n);
     for (int q = 0; q < nshifts; ++q) {
         if (rs_items(n) == 16) rs_pass<16>(stream, p, ka, va, kb, vb, hist, n, shifts[q]);
         else rs_pass<8>(stream, p, ka, va, kb, vb, hist, n, shifts[q]);

@@ -256,8 +256,10 @@ def test_tree_and_labels_on_random_codes(ctx):
 
 def test_radix_sort(ctx):
     rng = np.random.default_rng(5)
-    # 8,388,608 keys and up run the 16-item tile shape
-    for n in (2, 100, 2047, 2048, 2049, 100_000, 3_000_001, 8_388_608, 9_000_001):
+    # 8,388,608 keys and up run the 16-item tile shape; from 4,194,304 keys
+    # on a pass is one launch with look-back across tiles
+    for n in (2, 100, 2047, 2048, 2049, 100_000, 3_000_001, 4_194_303, 4_194_304, 4_194_305, 8_388_608,
+              9_000_001):
         keys = rng.integers(0, 2 ** 63, n, dtype=np.int64)
         keys[: n // 3] = keys[0]  # many equal keys: stability matters
         if n > 10:
