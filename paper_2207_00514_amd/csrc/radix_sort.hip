@@ -228,16 +228,18 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep(const uint64_t* __res
 // One-sweep passes (decoupled look-back, Merrill & Garland; its use for LSD
 // radix sort by Adinets & Merrill): one global count of every digit of every
 // pass first, then per pass a single launch in which each workgroup takes
-// the next tile (in launch order, from a counter), ranks it as the downsweep
-// does, publishes its per-digit counts, and adds up the counts of the tiles
-// before it -- each tile publishes its own count before it looks back, and
-// the inclusive prefix once it knows it, so a look-back stops at the first
-// inclusive prefix it meets and only ever waits on tiles that have started.
+// the next tile (in launch order, from a counter), ranks it, publishes its
+// per-digit counts, and adds up the counts of the tiles before it -- each
+// tile publishes its own count before it looks back, and the inclusive
+// prefix once it knows it, so a look-back stops at the first inclusive
+// prefix it meets and only ever waits on tiles that have started.
 // A status word is (flag << 30) | count: flag 1 = the tile's own count,
 // 2 = inclusive prefix (counts stay below 2^30: kRadixOneMin <= n < 2^30).
 // The words go through device-coherent atomics; each one holds its datum.
 
 constexpr uint32_t kOsAgg = 1u << 30, kOsIncl = 2u << 30, kOsMask = (1u << 30) - 1u;
+// predecessor status words a look-back step loads at once
+constexpr int kOsWindow = 8;
 
 struct RsShifts {
     int s[8];
@@ -294,128 +296,165 @@ __device__ __forceinline__ void os_store(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int ITEMS>
-__global__ __launch_bounds__(kRsThreads) void rs_onesweep(const uint64_t* __restrict__ kin,
-                                                          const uint32_t* __restrict__ vin,
-                                                          uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          int64_t n, int shift, const uint32_t* __restrict__ gstart,
-                                                          uint32_t* status, uint32_t* status_next,
-                                                          uint32_t* counter, uint32_t* err) {
-    constexpr int kRsItems = ITEMS;
-    constexpr int kRsTile = kRsThreads * ITEMS;
+// Each wave owns a contiguous chunk of 64 x ITEMS keys of the tile (item s
+// of lane l is key s * 64 + l of the chunk), so the tile's order is (wave,
+// item, lane) and one running count per wave and digit ranks it stably: the
+// lanes of an item read their digit's count, and the first lane of each
+// digit adds the item's peers (a wave's LDS operations complete in order).
+// The first 256 threads then own one digit each for the scans and the
+// look-back.  Keys, then values, go through LDS in the sorted order so that
+// the stores of a digit's run are contiguous.
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(6))) void rs_onesweep(const uint64_t* __restrict__ kin,
+                                                       const uint32_t* __restrict__ vin,
+                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                       int64_t n, int shift, const uint32_t* __restrict__ gstart,
+                                                       uint32_t* status, uint32_t* status_next, uint32_t* counter,
+                                                       uint32_t* err) {
+    constexpr int kWaves = THREADS / 64;
+    constexpr int kTile = THREADS * ITEMS;
+    static_assert(THREADS >= 256 && THREADS % 64 == 0, "one digit per thread of the first 256");
     __shared__ uint32_t s_tile;
     __shared__ uint32_t gbase[256];   // global start of every digit for this tile
     __shared__ uint32_t lstart[256];  // tile-local start of every digit
-    __shared__ uint32_t wsum[kRsWaves];
-    __shared__ __attribute__((aligned(16))) uint32_t cnt[kRsItems][kRsWaves][256];
-    static_assert(sizeof(cnt) >= kRsTile * (sizeof(uint64_t) + sizeof(uint32_t)), "staging fits");
-    uint64_t* skey = reinterpret_cast<uint64_t*>(&cnt[0][0][0]);
-    uint32_t* sval = reinterpret_cast<uint32_t*>(skey + kRsTile);
+    __shared__ uint32_t wsum[4];
+    __shared__ __attribute__((aligned(16))) uint64_t stage[kTile];
+    static_assert(sizeof(stage) >= kWaves * 256 * sizeof(uint32_t), "the wave counts fit");
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(stage);  // [wave][digit] until the staging
+    uint32_t* sval = cnt;
     const int t = threadIdx.x, w = t / 64, lane = t & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (t == 0) s_tile = atomicAdd(counter, 1u);
-    for (int k = t; k < kRsItems * kRsWaves * 256; k += kRsThreads) (&cnt[0][0][0])[k] = 0;
+    for (int k = t; k < kWaves * 256; k += THREADS) cnt[k] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
-    const int64_t tb = tile * kRsTile;
-    const int valid = (int)min((int64_t)kRsTile, n - tb);
-    uint64_t key[kRsItems];
-    uint32_t val[kRsItems], dig[kRsItems], rank[kRsItems];
-    bool ok[kRsItems];
+    const int64_t tb = tile * kTile;
+    const int valid = (int)min((int64_t)kTile, n - tb);
+    uint64_t key[ITEMS];
+    uint32_t val[ITEMS], rank[ITEMS];
+    bool ok[ITEMS];
+    // (a key's digit is recomputed where needed: fewer live registers)
+    auto digit = [&](uint64_t k) { return (uint32_t)(k >> shift) & 255u; };
 #pragma unroll
-    for (int s = 0; s < kRsItems; ++s) {
-        const int64_t idx = tb + (int64_t)s * kRsThreads + t;
+    for (int s = 0; s < ITEMS; ++s) {
+        const int64_t idx = tb + (int64_t)(w * ITEMS + s) * 64 + lane;
         ok[s] = idx < n;
         key[s] = ok[s] ? kin[idx] : 0ull;
         val[s] = ok[s] ? vin[idx] : 0u;
-        dig[s] = (uint32_t)(key[s] >> shift) & 255u;
     }
+    uint32_t* wcnt = cnt + w * 256;
 #pragma unroll
-    for (int s = 0; s < kRsItems; ++s) {
+    for (int s = 0; s < ITEMS; ++s) {
+        const uint32_t dg = digit(key[s]);
         uint64_t peers = __ballot(ok[s]);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const bool bit = (dig[s] >> b) & 1u;
+            const bool bit = (dg >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        rank[s] = (uint32_t)__popcll(peers & lt_mask);
-        if (ok[s] && rank[s] == 0) cnt[s][w][dig[s]] = (uint32_t)__popcll(peers);
+        const uint32_t r = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t before = ok[s] ? wcnt[dg] : 0u;
+        rank[s] = before + r;
+        if (ok[s] && r == 0) wcnt[dg] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    uint32_t total;
-    {
+    uint32_t total = 0, x = 0;
+    if (t < 256) {
         uint32_t off = 0;
 #pragma unroll
-        for (int s = 0; s < kRsItems; ++s)
-#pragma unroll
-            for (int ww = 0; ww < kRsWaves; ++ww) {
-                const uint32_t c = cnt[s][ww][t];
-                cnt[s][ww][t] = off;
-                off += c;
-            }
+        for (int ww = 0; ww < kWaves; ++ww) {
+            const uint32_t c = cnt[ww * 256 + t];
+            cnt[ww * 256 + t] = off;
+            off += c;
+        }
         total = off;
-        uint32_t x = total;
+        x = total;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o);
             if (lane >= o) x += y;
         }
         if (lane == 63) wsum[w] = x;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (t < 256) {
         uint32_t before = 0;
         for (int k = 0; k < w; ++k) before += wsum[k];
         lstart[t] = x - total + before;
-    }
-    // digit t: publish this tile's count, add up the tiles before it
-    uint32_t excl = 0;
-    if (tile == 0) {
-        os_store(&status[t], kOsIncl | total);
-    } else {
-        os_store(&status[tile * 256 + t], kOsAgg | total);
-        for (int64_t p = tile - 1; p >= 0; --p) {
-            uint32_t v = os_load(&status[p * 256 + t]);
-            for (uint32_t spin = 0; (v >> 30) == 0u; ++spin) {
-                if (spin > (1u << 22)) {  // (bounded: a missing tile is a bug, not a wait)
-                    atomicOr(err, 1u);
-                    v = kOsIncl;
-                    break;
+        // digit t: publish this tile's count, add up the tiles before it
+        uint32_t excl = 0;
+        if (tile == 0) {
+            os_store(&status[t], kOsIncl | total);
+        } else {
+            os_store(&status[tile * 256 + t], kOsAgg | total);
+            // the status words of kOsWindow tiles before are loaded at once,
+            // then added up nearest first until an inclusive one
+            bool found = false;
+            for (int64_t p = tile - 1; !found; p -= kOsWindow) {
+                uint32_t v[kOsWindow];
+#pragma unroll
+                for (int j = 0; j < kOsWindow; ++j) v[j] = p - j >= 0 ? os_load(&status[(p - j) * 256 + t]) : kOsIncl;
+#pragma unroll
+                for (int j = 0; j < kOsWindow; ++j) {
+                    if (found) break;
+                    for (uint32_t spin = 0; (v[j] >> 30) == 0u; ++spin) {
+                        if (spin > (1u << 22)) {  // (bounded: a missing tile is a bug, not a wait)
+                            atomicOr(err, 1u);
+                            v[j] = kOsIncl;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        v[j] = os_load(&status[(p - j) * 256 + t]);
+                    }
+                    excl += v[j] & kOsMask;
+                    found = (v[j] >> 30) == 2u;
                 }
-                __builtin_amdgcn_s_sleep(1);
-                v = os_load(&status[p * 256 + t]);
             }
-            excl += v & kOsMask;
-            if ((v >> 30) == 2u) break;
+            os_store(&status[tile * 256 + t], kOsIncl | (excl + total));
         }
-        os_store(&status[tile * 256 + t], kOsIncl | (excl + total));
-    }
-    gbase[t] = gstart[t] + excl;
-    os_store(&status_next[tile * 256 + t], 0u);  // the next pass's status starts empty
-    __syncthreads();
-    uint32_t lpos[kRsItems];
-#pragma unroll
-    for (int s = 0; s < kRsItems; ++s) lpos[s] = ok[s] ? lstart[dig[s]] + cnt[s][w][dig[s]] + rank[s] : 0u;
-    __syncthreads();  // cnt is reused for staging from here on
-#pragma unroll
-    for (int s = 0; s < kRsItems; ++s) {
-        if (ok[s]) {
-            skey[lpos[s]] = key[s];
-            sval[lpos[s]] = val[s];
-        }
+        gbase[t] = gstart[t] + excl;
+        os_store(&status_next[tile * 256 + t], 0u);  // the next pass's status starts empty
     }
     __syncthreads();
+    uint32_t lpos[ITEMS];
 #pragma unroll
-    for (int s = 0; s < kRsItems; ++s) {
-        const int lp = s * kRsThreads + t;
+    for (int s = 0; s < ITEMS; ++s) {
+        const uint32_t dg = digit(key[s]);
+        lpos[s] = ok[s] ? lstart[dg] + wcnt[dg] + rank[s] : 0u;
+    }
+    __syncthreads();  // the counts are overwritten by the staging from here on
+#pragma unroll
+    for (int s = 0; s < ITEMS; ++s)
+        if (ok[s]) stage[lpos[s]] = key[s];
+    __syncthreads();
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int s = 0; s < ITEMS; ++s) {
+        const int lp = s * THREADS + t;
+        dst[s] = 0u;
         if (lp < valid) {
-            const uint64_t k = skey[lp];
-            const uint32_t d = (uint32_t)(k >> shift) & 255u;
-            const uint32_t dst = gbase[d] + (uint32_t)lp - lstart[d];
-            kout[dst] = k;
-            vout[dst] = sval[lp];
+            const uint64_t k = stage[lp];
+            const uint32_t d = digit(k);
+            dst[s] = gbase[d] + (uint32_t)lp - lstart[d];
+            kout[dst[s]] = k;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < ITEMS; ++s)
+        if (ok[s]) sval[lpos[s]] = val[s];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < ITEMS; ++s) {
+        const int lp = s * THREADS + t;
+        if (lp < valid) vout[dst[s]] = sval[lp];
     }
 }
+
+// Threads and items per thread of a one-sweep tile (kRadixOneTile keys).
+constexpr int kOsThreads = 512;
+constexpr int kOsItems = kRadixOneTile / kOsThreads;
 
 static int rs_items(int64_t n) { return n >= kRsBigN ? 16 : 8; }
 
@@ -463,7 +502,7 @@ hipError_t radix_sort_pairs(hipStream_t stream, uint64_t* k0, uint32_t* v0, uint
                                                                                              ghist);
         rs_global_scan<<<nshifts, kRsThreads, 0, stream>>>(ghist, gstart);
         for (int q = 0; q < nshifts; ++q) {
-            rs_onesweep<16><<<(unsigned)tiles, kRsThreads, 0, stream>>>(ka, va, kb, vb, n, shifts[q], gstart + q * 256,
+            rs_onesweep<kOsThreads, kOsItems><<<(unsigned)tiles, kOsThreads, 0, stream>>>(ka, va, kb, vb, n, shifts[q], gstart + q * 256,
                                                                         status[q & 1], status[(q + 1) & 1],
                                                                         counters + q, counters + 8);
             std::swap(ka, kb);
