@@ -17,6 +17,10 @@
 // Items are loaded striped (item s of thread t is tile element s*256 + t),
 // so the (slot, wave, lane) order equals the input order and the sort is
 // stable.
+//
+// From kRadixOneMin keys on, a pass is instead one launch of rs_onesweep
+// (decoupled look-back across tiles, after one count of every digit of
+// every pass by rs_global_hist), described below.
 #include "radix_sort.h"
 
 namespace emst {
@@ -303,14 +307,14 @@ __device__ __forceinline__ void os_store(uint32_t* p, uint32_t v) {
 // digit adds the item's peers (a wave's LDS operations complete in order).
 // The first 256 threads then own one digit each for the scans and the
 // look-back.  Keys, then values, go through LDS in the sorted order so that
-// the stores of a digit's run are contiguous.
+// the stores of a digit's run are contiguous.  At most 80 registers keep
+// six waves per SIMD (three 512-thread workgroups per compute unit, which
+// their 35 KB of LDS allows too).
 template <int THREADS, int ITEMS>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(6))) void rs_onesweep(const uint64_t* __restrict__ kin,
-                                                       const uint32_t* __restrict__ vin,
-                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                       int64_t n, int shift, const uint32_t* __restrict__ gstart,
-                                                       uint32_t* status, uint32_t* status_next, uint32_t* counter,
-                                                       uint32_t* err) {
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(6))) void rs_onesweep(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ gstart, uint32_t* status,
+    uint32_t* status_next, uint32_t* counter, uint32_t* err) {
     constexpr int kWaves = THREADS / 64;
     constexpr int kTile = THREADS * ITEMS;
     static_assert(THREADS >= 256 && THREADS % 64 == 0, "one digit per thread of the first 256");
@@ -502,9 +506,9 @@ hipError_t radix_sort_pairs(hipStream_t stream, uint64_t* k0, uint32_t* v0, uint
                                                                                              ghist);
         rs_global_scan<<<nshifts, kRsThreads, 0, stream>>>(ghist, gstart);
         for (int q = 0; q < nshifts; ++q) {
-            rs_onesweep<kOsThreads, kOsItems><<<(unsigned)tiles, kOsThreads, 0, stream>>>(ka, va, kb, vb, n, shifts[q], gstart + q * 256,
-                                                                        status[q & 1], status[(q + 1) & 1],
-                                                                        counters + q, counters + 8);
+            rs_onesweep<kOsThreads, kOsItems><<<(unsigned)tiles, kOsThreads, 0, stream>>>(
+                ka, va, kb, vb, n, shifts[q], gstart + q * 256, status[q & 1], status[(q + 1) & 1], counters + q,
+                counters + 8);
             std::swap(ka, kb);
             std::swap(va, vb);
         }
