@@ -422,8 +422,8 @@ def test_batched_512_clouds(ctx):
 def test_cosmology3d_37m(ctx):
     """The full 37M-point cosmology-like cloud through emst_build, edge by
     edge against the oracle's kd-tree Boruvka: Morton codes (no rank-space
-    switch), the 16-item radix tiles, the scan kernels above 1024 tiles and
-    the query-list rounds all run at this size."""
+    switch), the one-sweep radix passes, the scan kernels above 1024 tiles
+    and the query-list rounds all run at this size."""
     import time
     t0 = time.perf_counter()
     pts = W.make("cosmology3d_37m")
@@ -439,6 +439,17 @@ def test_cosmology3d_37m(ctx):
     ref = oracle.kdboruvka(pts, threads=min(16, os.cpu_count() or 1))
     print(f"oracle {time.perf_counter() - t0:.1f} s", flush=True)
     assert_same(got, ref, "cosmology3d_37m")
+
+
+def test_one_sweep_odd_pass_count(ctx):
+    """5,000,000 points: from 2^22 keys on every radix pass is one launch
+    with look-back across tiles.  With 23 bits of point index the edge order
+    takes 7 passes (3 on the index, 4 on the length), so the sorted edges
+    end in the second buffer; the Morton sort takes 8."""
+    pts = W.clustered3d(5_000_000, seed=41)
+    got = run(ctx, pts, 13)
+    ref = oracle.kdboruvka(pts, threads=min(16, os.cpu_count() or 1))
+    assert_same(got, ref, "clustered3d n=5,000,000")
 
 
 def test_tree_boxes_are_exact(ctx):
