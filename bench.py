@@ -57,6 +57,8 @@ MEASURED_TRAFFIC = {
     # (workload, variant, source hash): (FETCH_SIZE KiB, WRITE_SIZE KiB, TCC hit fraction, profile)
     ("cosmology3d_37m", 13, "a2025fcf28faa80d"):
         (1172456.2, 294876.0, 0.881, "profiles/k_traverse_fast_cosmology3d_37m.md"),
+    ("clustered3d_2m", 13, "a2025fcf28faa80d"):
+        (70849.3, 18651.3, 0.878, "profiles/k_traverse_fast_clustered3d_2m.md"),
 }
 # What bounds the traversal, from counters of the same runs (per launch
 # type): VALU busy = VALU issue cycles / (SIMDs x kernel cycles), lane
@@ -73,6 +75,16 @@ MEASURED_LIMITER = {
                  "salu_per_valu": 1.00, "waves_per_cu": 24.7, "of_waves_per_cu": 32, "l2_hit": 0.854,
                  "hbm_frac": 0.150},
         "profile": "profiles/k_traverse_fast_cosmology3d_37m.md",
+    },
+    ("clustered3d_2m", 13, "a2025fcf28faa80d"): {
+        "bound_by": "instruction issue x lane divergence (not HBM)",
+        "full": {"launches": "rounds 0-1", "valu_busy": 0.511, "lane_utilisation": 0.403,
+                 "salu_per_valu": 0.94, "waves_per_cu": 23.8, "of_waves_per_cu": 32, "l2_hit": 0.914,
+                 "hbm_frac": 0.083},
+        "list": {"launches": "rounds 2-8", "valu_busy": 0.291, "lane_utilisation": 0.566,
+                 "salu_per_valu": 0.99, "waves_per_cu": 15.3, "of_waves_per_cu": 32, "l2_hit": 0.828,
+                 "hbm_frac": 0.111},
+        "profile": "profiles/k_traverse_fast_clustered3d_2m.md",
     },
 }
 
