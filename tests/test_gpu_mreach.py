@@ -123,6 +123,17 @@ def test_mreach_clustered3d_2m(ctx):
     assert_same_tree(got, oracle.kdboruvka_mreach(pts, core2, threads=16), "clustered3d_2m k=4")
 
 
+def test_mreach_one_sweep_size(ctx):
+    """5,000,000 cosmology-recipe points, k_pts = 8: from 2^22 points on the
+    Morton and edge sorts are one-sweep radix passes (the edge order in an
+    odd number of them); cores and the whole tree against the oracle."""
+    pts = W.make("cosmology3d_37m", 5_000_000)
+    core2 = oracle.core_distances(pts, 8, "kd", threads=16)
+    got, gcore = gpu_tree(ctx, pts, 8)
+    assert same(gcore, core2)
+    assert_same_tree(got, oracle.kdboruvka_mreach(pts, core2, threads=16), "cosmology3d n=5,000,000 k=8")
+
+
 def test_errors(ctx):
     import paper_2207_00514_amd as emst
     pts = dev(W.small_random(100, 3, 1))
