@@ -445,11 +445,13 @@ def test_one_sweep_odd_pass_count(ctx):
     """5,000,000 points: from 2^22 keys on every radix pass is one launch
     with look-back across tiles.  With 23 bits of point index the edge order
     takes 7 passes (3 on the index, 4 on the length), so the sorted edges
-    end in the second buffer; the Morton sort takes 8."""
-    pts = W.clustered3d(5_000_000, seed=41)
-    got = run(ctx, pts, 13)
-    ref = oracle.kdboruvka(pts, threads=min(16, os.cpu_count() or 1))
-    assert_same(got, ref, "clustered3d n=5,000,000")
+    end in the second buffer; the Morton sort takes 8 passes in 3D and 4
+    (32-bit codes) in 2D."""
+    for pts in (W.clustered3d(5_000_000, seed=41), W.uniform2d(5_000_000, seed=42)):
+        print(f"one-sweep n={len(pts)} dim={pts.shape[1]}", flush=True)
+        got = run(ctx, pts, 13)
+        ref = oracle.kdboruvka(pts, threads=min(16, os.cpu_count() or 1))
+        assert_same(got, ref, f"n=5,000,000 dim={pts.shape[1]}")
 
 
 def test_tree_boxes_are_exact(ctx):
