@@ -509,3 +509,12 @@ def test_skewed3d_2m(ctx):
     got = run(ctx, pts)
     assert ctx.stats()["rank_codes"] == 1
     assert_same(got, oracle.kdboruvka(pts, threads=16), "skewed3d_2m")
+
+
+def test_skewed3d_rank_space_one_sweep(ctx):
+    """5,000,000 skewed points: the rank-space rebuild's per-axis sorts (4
+    passes each) and the rank-space Morton sort run as one-sweep passes."""
+    pts = W.skewed3d(5_000_000)
+    got = run(ctx, pts)
+    assert ctx.stats()["rank_codes"] == 1
+    assert_same(got, oracle.kdboruvka(pts, threads=16), "skewed3d n=5,000,000")
