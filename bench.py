@@ -246,6 +246,7 @@ def bench_single(args) -> int:
     phases = {"tree_ms": 0.0, "rounds_ms": 0.0, "finalize_ms": 0.0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    trav_round = None  # per round, the shortest traversal launch of the timed steps
     for _ in range(args.steps):
         ctx.build(pts, out=out)
         st = ctx.stats()
@@ -253,6 +254,8 @@ def bench_single(args) -> int:
         launches += st["rounds"]
         for k in phases:
             phases[k] += st[k]
+        tr = list(st["traversal_ms_round"][:st["rounds"]])
+        trav_round = tr if trav_round is None else [min(a, b) for a, b in zip(trav_round, tr)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     secs = t1 - t0
@@ -325,6 +328,16 @@ def bench_single(args) -> int:
         "rounds": rounds,
         "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in phases.items()},
         "roofline": roofline,
+        # per Borůvka round: the counting run's components, queries, tests per
+        # query and node records loaded; the shortest traversal launch of the
+        # timed steps (HIP events)
+        "round_table": [
+            {"round": r, "components": int(cst["components"][r]), "queries": int(q_round[r]),
+             "child_tests_per_query": round(cst["child_tests_round"][r] / max(q_round[r], 1), 2),
+             "leaf_tests_per_query": round(cst["leaf_tests_round"][r] / max(q_round[r], 1), 2),
+             "records_loaded": int(t_round[r]),
+             "traversal_ms_min": None if trav_round is None or r >= len(trav_round) else round(trav_round[r], 3)}
+            for r in range(rounds)],
     }
     edges, w, d2 = (t.cpu().numpy() for t in out)
     del ctx, out
